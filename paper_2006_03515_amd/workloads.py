@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs (source fields, pressures, target samples).
+
+This module only draws inputs: it holds none of the method's arithmetic, and both
+the GPU path and the CPU oracle take their inputs from it.  All randomness is
+numpy Generator(PCG64(seed)).
+
+Physical units: cm, Torr.  A source field is I(y) of eq. (Ifun) sampled at the
+cell centres x0 + (i + 1/2) h of an n^3 grid spanning [0, L]^3.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+P_Q = 30.0                # quenching pressure [Torr] (Section 4.1)
+O2_FRACTION = 150.0 / 760.0
+
+
+def p_o2_of(p):
+    """Partial pressure of O2 at air pressure p, keeping 150 Torr at 760 Torr."""
+    return p * O2_FRACTION
+
+
+def quench(p):
+    """p_q / (p + p_q): the quenching factor of eq. (Ifun)."""
+    return P_Q / (p + P_Q)
+
+
+@dataclass
+class Workload:
+    name: str
+    n: int
+    L: float           # cube side [cm]
+    p: float           # air pressure [Torr]
+    I: np.ndarray      # (n, n, n) float64 source
+
+    @property
+    def h(self):
+        return self.L / self.n
+
+    @property
+    def p_o2(self):
+        return p_o2_of(self.p)
+
+    @property
+    def prefactor(self):
+        return quench(self.p)
+
+
+def centres(n, L):
+    return (np.arange(n) + 0.5) * (L / n)
+
+
+def _mesh(n, L):
+    c = centres(n, L)
+    return np.meshgrid(c, c, c, indexing="ij")
+
+
+def gaussian_peak(n=32, L=0.1, amp=1e20, sigma=0.01, p=760.0):
+    """One Gaussian 1e20 exp(-|r-c|^2/sigma^2) at the cube centre (1 mm cube, 32^3)."""
+    X, Y, Z = _mesh(n, L)
+    c = L / 2
+    I = amp * np.exp(-((X - c) ** 2 + (Y - c) ** 2 + (Z - c) ** 2) / sigma ** 2)
+    return Workload("gaussian_peak_%d" % n, n, L, p, I)
+
+
+def two_heads_random(n=128, L=0.4, p=760.0, seed=8):
+    """Mixture of 2 Gaussian heads: centres U[L/4, 3L/4]^3, sigma U[0.005, 0.02] cm,
+    amplitude log-uniform in [1e18, 1e21]."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = _mesh(n, L)
+    I = np.zeros((n, n, n))
+    for _ in range(2):
+        c = rng.uniform(L / 4, 3 * L / 4, 3)
+        s = rng.uniform(0.005, 0.02)
+        a = 10.0 ** rng.uniform(18, 21)
+        I += a * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / s ** 2)
+    return Workload("two_heads_%d" % n, n, L, p, I)
+
+
+def streamer_channel(n=256, L=0.4, p=760.0, dtype=np.float32):
+    """Elongated streamer channel: a cylinder of radius 0.01 cm along z through
+    (L/2, L/2) for z in [L/8, 7L/8] (length 3 mm at L = 4 mm) with value 1e19, a
+    Gaussian head sigma = 0.008 cm and peak 1e21 at its upper end, and a background
+    of 1e15 (1e-6 of the peak)."""
+    c = centres(n, L).astype(np.float64)
+    X = c[:, None, None]
+    Y = c[None, :, None]
+    Z = c[None, None, :]
+    I = np.full((n, n, n), 1e15, dtype=dtype)
+    r2 = (X - L / 2) ** 2 + (Y - L / 2) ** 2           # (n, n, 1)
+    zin = (Z >= L / 8) & (Z <= 7 * L / 8)              # (1, 1, n)
+    cyl = (r2 <= 0.01 ** 2) & zin
+    I[np.broadcast_to(cyl, I.shape)] += dtype(1e19)
+    zh = 7 * L / 8
+    for i in range(n):   # slab by slab to bound memory at 256^3
+        d2 = (c[i] - L / 2) ** 2 + (Y[0] - L / 2) ** 2 + (Z[0] - zh) ** 2
+        I[i] += (1e21 * np.exp(-d2 / 0.008 ** 2)).astype(dtype)
+    return Workload("streamer_channel_%d" % n, n, L, p, I)
+
+
+def anisotropic_heads(n=64, L=0.4, seed=40000, p=760.0):
+    """1-4 anisotropic Gaussian heads: per-axis sigma U[0.003, 0.03] cm, a random
+    rotation (QR of a normal 3x3 matrix, signs fixed so det = +1), log-uniform
+    amplitude in [1e18, 1e21], centres U[L/4, 3L/4]^3."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = _mesh(n, L)
+    P = np.stack([X, Y, Z], -1)
+    I = np.zeros((n, n, n))
+    for _ in range(int(rng.integers(1, 5))):
+        s = rng.uniform(0.003, 0.03, 3)
+        Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+        Q = Q * np.sign(np.diag(R))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] = -Q[:, 0]
+        a = 10.0 ** rng.uniform(18, 21)
+        c = rng.uniform(L / 4, 3 * L / 4, 3)
+        d = (P - c) @ Q
+        I += a * np.exp(-((d / s) ** 2).sum(-1))
+    return Workload("anisotropic_heads_%d_%d" % (n, seed), n, L, p, I)
+
+
+def interacting_heads(k, n=128, L=0.4, steps=200, p=760.0):
+    """Step k of two sigma = 0.01 cm Gaussian heads (peak 1e20 each) at
+    (L/2, L/2, L/2 +- d_k/2), d_k shrinking linearly from 0.2 cm to 0.03 cm."""
+    d = 0.2 - 0.17 * k / (steps - 1)
+    X, Y, Z = _mesh(n, L)
+    c = L / 2
+    I = np.zeros((n, n, n))
+    for s in (-1, 1):
+        I += 1e20 * np.exp(-((X - c) ** 2 + (Y - c) ** 2 + (Z - c - s * d / 2) ** 2) / 0.01 ** 2)
+    return Workload("interacting_heads_%d_%d" % (n, k), n, L, p, I)
+
+
+def sample_targets(n_cells, count, seed):
+    """`count` distinct flat cell indices drawn without replacement."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_cells, size=min(count, n_cells), replace=False)).astype(np.int64)
