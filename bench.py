@@ -1,0 +1,216 @@
+"""Benchmark: target points/s of the KIFMM evaluation of the photoionization sum
+on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--precision fp32]
+
+One step = one kifmm_eval over the whole grid (permute in, P2M, M2M, M2L, L2L,
+L2P, P2P with the self cell, permute out) with the source already resident in
+HBM.  The operators are precomputed once before the timed region (per pressure)
+and their time is reported separately.  Accuracy is checked after the timed
+region against FP64 direct evaluation (direct_eval) at 4,096 seeded targets.
+
+Prints one JSON line (see the design doc for every field).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3e12  # FLOP/s, dense FP32 matrix, MI355X
+PEAK_BF16_MFMA = 2.5e15
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def near_pairs(nb, s):
+    """(target, source) pairs of the near field: leaves x existing neighbour leaves."""
+    per_axis = 3 * nb - 2 if nb > 1 else 1
+    return per_axis ** 3 * s * s
+
+
+def m2l_pairs(level):
+    """Number of (target box, interaction-list box) pairs at a level."""
+    n = 1 << level
+    i = np.arange(n)
+    total = 0
+    for o in np.ndindex(7, 7, 7):
+        o = np.array(o) - 3
+        if np.abs(o).max() <= 1:
+            continue
+        cnt = 1
+        for v in o:
+            ok = (np.abs((i + v) // 2 - i // 2) <= 1) & (i + v >= 0) & (i + v < n)
+            cnt *= int(ok.sum())
+        total += cnt
+    return total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--p", type=float, default=760.0, help="air pressure [Torr]")
+    ap.add_argument("--max-leaf", type=int, default=512)
+    ap.add_argument("--layout", default="nested", choices=["paper", "single", "nested"])
+    ap.add_argument("--rcond", type=float, default=1e-5)
+    ap.add_argument("--m0", type=int, default=5)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--variants", default="m2l_fp16,m2l_bf16",
+                    help="extra precisions timed after the headline one ('' for none)")
+    ap.add_argument("--check-targets", type=int, default=4096)
+    ap.add_argument("--cpu-targets", type=int, default=2048,
+                    help="targets of the oracle CPU baseline sample (0 = skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the evaluation would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_03515_amd import kifmm as K
+    from paper_2006_03515_amd import workloads
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    log("generating streamer channel %d^3" % args.n)
+    w = workloads.streamer_channel(n=args.n, L=0.4, p=args.p, dtype=np.float32)
+    I_host = np.ascontiguousarray(w.I.reshape(-1))
+    I = torch.from_numpy(I_host).to(dev)
+    grid = K.Grid.cube(w.n, w.L)
+    kern = K.Kernel(w.p_o2)
+    layout = {"paper": K.LAYOUT_PAPER, "single": K.LAYOUT_SINGLE, "nested": K.LAYOUT_NESTED}[args.layout]
+    opts = K.Opts(layout, args.m0, 10, args.rcond)
+
+    t0 = time.perf_counter()
+    tree = K.build_tree(grid, args.max_leaf)
+    ops = K.precompute_operators(tree, kern, opts)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    ranks = {l: ops.rank(l) for l in range(2, tree.depth + 1)}
+    log("tree depth %d, leaf %d^3, precompute %.2f s, ranks %s" % (tree.depth, tree.leaf_side, t_pre, ranks))
+
+    S = torch.empty_like(I)
+    stream = torch.cuda.current_stream()
+
+    def timed(precision, steps, warmup, profile):
+        for _ in range(warmup):
+            K.eval(tree, ops, I, w.prefactor, out=S, precision=precision)
+        torch.cuda.synchronize()
+        if profile:
+            ops.profile(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            K.eval(tree, ops, I, w.prefactor, out=S, precision=precision)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        prof = ops.profile_read() if profile else None
+        if profile:
+            ops.profile(False)
+        return ms, prof
+
+    # accuracy sample: FP64 direct at seeded targets (computed once)
+    tg = workloads.sample_targets(w.n ** 3, args.check_targets, seed=1009)
+    tgt = torch.from_numpy(tg).to(dev)
+    log("direct_eval FP64 at %d targets" % tg.size)
+    ref = K.direct_eval(grid, kern, I, w.prefactor, tgt, fp64=True).cpu().numpy()
+
+    def accuracy():
+        got = S[tgt].double().cpu().numpy()
+        return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    # headline precision: timed once without instrumentation, once with per-pass events
+    log("timing %s: %d warmup + %d steps" % (args.precision, args.warmup, args.steps))
+    ms, _ = timed(args.precision, args.steps, args.warmup, profile=False)
+    err = accuracy()
+    _, prof = timed(args.precision, args.steps, 1, profile=True)
+    log("%s: %.3f ms/step, rel-L2 %.3e" % (args.precision, ms, err))
+
+    N = w.n ** 3
+    nb, s = tree.grid.n[0] // tree.leaf_side, tree.leaf_side ** 3
+    p2p_flops = 2.0 * near_pairs(nb, s)
+    m2l_flops = sum(2.0 * m2l_pairs(l) * ranks[l][0] * ranks[l][1] for l in ranks)
+    pass_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}        # mean per launch
+    pass_step = {k: v[0] / args.steps for k, v in prof.items()}       # per step
+    calls_step = {k: v[1] / args.steps for k, v in prof.items()}
+    dom = max(("p2p", "m2l"), key=lambda k: pass_step[k])
+    if dom == "p2p":
+        flops_launch = p2p_flops
+        peak = PEAK_FP32_MFMA
+    else:
+        flops_launch = m2l_flops / max(calls_step["m2l"], 1)
+        peak = PEAK_FP32_MFMA if args.precision in ("fp32", "fp64") else PEAK_BF16_MFMA
+    achieved = flops_launch / (pass_ms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
+                "traffic": None, "flops_per_launch": flops_launch,
+                "avg_launch_ms": round(pass_ms[dom], 4)}
+
+    variants = {}
+    for v in [x for x in args.variants.split(",") if x]:
+        log("timing variant %s" % v)
+        vms, _ = timed(v, args.steps, args.warmup, profile=False)
+        variants[v] = {"value": N / (vms * 1e-3), "ms_per_step": round(vms, 4), "rel_l2": accuracy()}
+
+    cpu = None
+    if args.cpu_targets > 0:
+        from oracle import direct as odirect
+        ctg = workloads.sample_targets(N, args.cpu_targets, seed=77)
+        log("oracle CPU baseline: %d targets x %d sources" % (ctg.size, N))
+        Ih = I_host.reshape(w.n, w.n, w.n).astype(np.float64)
+        t1 = time.perf_counter()
+        odirect.direct_targets(Ih, (w.h,) * 3, w.p_o2, ctg, prefactor=w.prefactor)
+        dt = time.perf_counter() - t1
+        cpu = {"value": ctg.size / dt, "unit": "target points/s", "cores": odirect.num_threads(),
+               "kind": "oracle", "sample": "FP64 direct sum (C/OpenMP) at %d seeded targets of the "
+                                           "same %d^3 workload, %.1f s" % (ctg.size, w.n, dt)}
+
+    out = {
+        "metric": "target points/s at <=1e-4 rel-L2 vs FP64 direct (KIFMM evaluation)",
+        "value": N / (ms * 1e-3),
+        "unit": "target points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}.get(args.precision, "f32+" + args.precision),
+        "data": "synthetic",
+        "config": {"workload": "streamer_channel_%d" % w.n, "n": w.n, "L_cm": w.L, "p_torr": w.p,
+                   "p_o2_torr": w.p_o2, "layout": args.layout, "m0": args.m0, "check_edge": 10,
+                   "rcond": args.rcond, "max_leaf": args.max_leaf, "leaf_side": tree.leaf_side,
+                   "depth": tree.depth, "precision": args.precision, "parallelism": "none"},
+        "rel_l2_sampled": err,
+        "accuracy_ok": err <= 1e-4,
+        "pair_interactions_per_s": near_pairs(nb, s) / (ms * 1e-3),
+        "precompute_s": round(t_pre, 3),
+        "pass_ms_per_step": {k: round(v, 4) for k, v in pass_step.items()},
+        "m2l_flops_per_step": m2l_flops,
+        "p2p_flops_per_step": p2p_flops,
+        "roofline": roofline,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

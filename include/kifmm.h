@@ -1,0 +1,180 @@
+/*
+ * kifmm.h -- C ABI of libkifmm: kernel-independent fast multipole evaluation of
+ * the 3D photoionization integral on one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Lin, Zhuang, Cai, Zeng, Bao, "Accurate and efficient
+ * calculation of photoionization in streamer discharges using fast multipole
+ * method"):
+ *
+ *   Section 2.1, eq. (integral), (Ifun), (gfun):
+ *     S_ph(x) = int I(y) g(|x-y|) / (4 pi |x-y|^2) dy,
+ *     g(r)    = (exp(-chi_min pO2 r) - exp(-chi_max pO2 r)) / (r ln(chi_max/chi_min)).
+ *   Section 3, eq. (summation) and the discrete kernel G after it: on a uniform
+ *   grid of cell centres,
+ *     S_i = prefactor * sum_j G(x_i, y_j) I_j (hx hy hz),
+ *   G = g/(4 pi R^2) off the diagonal (midpoint rule) and
+ *   G_ii = 3 g(rho) / (pi (hx^2+hy^2+hz^2)), rho = sqrt((hx^2+hy^2+hz^2)/12)
+ *   (2x2x2 Gauss-Legendre rule on the self cell).
+ *
+ * kifmm_eval approximates that sum by the kernel-independent FMM of Section 3
+ * (tree, upward pass eq. (s2m)/(m2m), downward pass eq. (m2l)/(l2l), target
+ * potential = local expansion + near-range direct sum, eq. (nearfar)).
+ * direct_eval computes the sum itself at chosen targets.
+ *
+ * Conventions
+ *   Units: cm and Torr; chi in 1/(cm Torr).
+ *   Arrays: C order [nx][ny][nz] (z fastest).  Cell (i,j,k) has centre
+ *   (x0 + (i+1/2) hx, y0 + (j+1/2) hy, z0 + (k+1/2) hz).
+ *   Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *   tensors); everything else is host memory that is read during the call only.
+ *   stream: a hipStream_t passed as void*; NULL means the legacy default stream.
+ *   Work is enqueued on `stream`; kifmm_eval and direct_eval return before it
+ *   finishes, never synchronise the device, and allocate no memory.
+ *   Inputs are never modified.
+ *
+ * Errors
+ *   Every int-returning function returns KIFMM_OK (0) or a negative code, and
+ *   never throws or aborts.  kifmm_last_error() returns a message for the last
+ *   failure on the calling thread (thread-local storage, valid until the next
+ *   failing call on that thread).
+ */
+#ifndef KIFMM_H
+#define KIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KIFMM_OK = 0,
+    KIFMM_EINVAL = -1,       /* null pointer, non-positive size/spacing/pressure, bad option */
+    KIFMM_EUNSUPPORTED = -2, /* valid request this library does not implement (e.g. non-cubic grid) */
+    KIFMM_EMISMATCH = -3,    /* operators used with a tree they were not built for */
+    KIFMM_ENOMEM = -4,       /* device allocation failed */
+    KIFMM_EHIP = -5          /* a HIP runtime call failed; message holds hipGetErrorString */
+};
+
+/* Uniform grid of cell centres (Section 4: V = V' = a box of equal cells). */
+typedef struct {
+    int32_t nx, ny, nz;   /* cells per axis, > 0 */
+    double x0, y0, z0;    /* lower corner [cm] */
+    double hx, hy, hz;    /* cell sizes [cm], > 0 */
+} kifmm_grid;
+
+/* Kernel parameters of eq. (gfun): a = chi_min * p_o2, b = chi_max * p_o2.
+ * The paper's values are chi_min = 0.035, chi_max = 2 (Section 2.1).
+ * Requires 0 < chi_min < chi_max and p_o2 > 0. */
+typedef struct {
+    double chi_min, chi_max, p_o2;
+} kifmm_kernel;
+
+/* Placement of the equivalent and check points (Section 3: multipole and local
+ * expansions, m0 points per side).  Radii are multiples of the box half-width r.
+ *   KIFMM_LAYOUT_PAPER : one surface each, m0 per edge; upward equivalent at
+ *                        1.05 r, upward check at 2.95 r, downward equivalent at
+ *                        2.95 r, downward check at 1.05 r.
+ *   KIFMM_LAYOUT_SINGLE: upward equivalent: m0 surface at 1.05 r; upward check:
+ *                        surfaces at 2.95 r, 4 r, 6 r with check_edge points per
+ *                        edge; downward equivalent: m0 surface at 2.95 r;
+ *                        downward check: check_edge^3 lattice on [-1.05 r, 1.05 r]^3.
+ *   KIFMM_LAYOUT_NESTED: as SINGLE plus a second m0 surface at 0.55 r (upward
+ *                        equivalent) and at 4 r (downward equivalent).
+ * rcond: singular values <= rcond * s_max are dropped from the pseudo-inverse.
+ * Expansions are carried as coefficients on the retained left singular vectors
+ * of the check-to-equivalent matrix (the backward-stable form of the
+ * pseudo-inverse, Section 3 remark on the pseudo-inverse). */
+enum { KIFMM_LAYOUT_PAPER = 0, KIFMM_LAYOUT_SINGLE = 1, KIFMM_LAYOUT_NESTED = 2 };
+typedef struct {
+    int32_t layout;       /* KIFMM_LAYOUT_* */
+    int32_t m0;           /* equivalent points per cube edge, 2..16 (paper: 6) */
+    int32_t check_edge;   /* check points per edge, layouts SINGLE/NESTED, 2..16 */
+    double rcond;         /* relative SVD cutoff, 0 < rcond < 1 */
+} kifmm_opts;
+
+/* Arithmetic of kifmm_eval.
+ *   KIFMM_FP64      : all passes in FP64; I_dev and S_dev are double*.
+ *   KIFMM_FP32      : all passes in FP32 (FP32 MFMA); float* I/O.
+ *   KIFMM_M2L_BF16  : as FP32 but the M2L translations take bfloat16 operands
+ *                     (FP32 accumulate); float* I/O.
+ *   KIFMM_M2L_FP16  : as FP32 but M2L in FP16 operands with per-level scaling. */
+enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_M2L_BF16 = 2, KIFMM_M2L_FP16 = 3 };
+
+typedef struct kifmm_tree_s *kifmm_tree;
+typedef struct kifmm_ops_s *kifmm_ops;
+
+/* Tree construction (Section 3, step 1 of the algorithm outline).
+ * Builds the complete octree of a cubic grid with n = 2^p cells per axis whose
+ * leaves are cubes of ell^3 cells, ell^3 <= max_leaf (the paper's m) with ell
+ * the largest power of two that fits; computes the Morton leaf order on the
+ * device.  Requires nx == ny == nz, hx == hy == hz (else KIFMM_EUNSUPPORTED),
+ * max_leaf >= 1.  Allocates device memory owned by the tree; *out is set only
+ * on success.  Synchronises `stream` before returning. */
+int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kifmm_tree *out);
+
+/* Operator precompute for one tree and one pressure (Section 3, eq. (s2m),
+ * (s2l), (m2m), (m2l), (l2l)).  In FP64 on the device: kernel matrices between
+ * point sets, truncated SVD (one-sided Jacobi) of the check-to-equivalent
+ * matrices of every level, the fused translation operators, the near-range
+ * matrices with the self-cell value; then FP32/BF16/FP16 copies.  Allocates
+ * device memory owned by the returned object.  Synchronises `stream`.
+ * opts may be NULL (defaults: SINGLE, m0 = 6, check_edge = 10, rcond = 1e-7). */
+int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel,
+                               const kifmm_opts *opts, void *stream, kifmm_ops *out);
+
+/* Retained SVD ranks of level `level` (2 <= level <= depth); returns 0 and
+ * writes k_up/k_down, or a negative code. depth is returned by kifmm_tree_info. */
+int kifmm_ops_rank(kifmm_ops ops, int32_t level, int32_t *k_up, int32_t *k_down);
+
+/* Tree shape: depth D (levels 0..D), leaf side ell in cells. */
+int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
+
+/* FMM evaluation: S_dev[i] ~= prefactor * sum_j G(x_i,y_j) I_dev[j] hx hy hz for
+ * every cell i.  I_dev and S_dev hold nx*ny*nz values, double for KIFMM_FP64 and
+ * float otherwise, in grid order; they must not overlap.  `ops` must come from
+ * `tree` (else KIFMM_EMISMATCH).  Uses the work buffers owned by `ops`, so
+ * calls sharing one ops object must be ordered on one stream. */
+int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor,
+               void *S_dev, int32_t precision, void *stream);
+
+/* Direct evaluation of the exact sum (Section 3, eq. (summation)):
+ * out_dev[t] = prefactor * sum_j G(x_t, y_j) I_dev[j] hx hy hz for the flat cell
+ * indices tgt_idx_dev[t] (device int64, each in [0, N)), or for every cell
+ * t = 0..N-1 when tgt_idx_dev is NULL (then n_tgt must equal N).  I_dev is float
+ * [N]; out_dev is double [n_tgt].  fp64_accumulate = 1 evaluates the kernel in
+ * FP64; 0 evaluates it in FP32 (distances from integer cell offsets).  Sums are
+ * always FP64, in a fixed order (bitwise repeatable).  Any grid is accepted.
+ * n_tgt = 0 is a no-op (out_dev may then be NULL).  Out-of-range indices are
+ * not checked on the device: the caller guarantees them. */
+int direct_eval(const kifmm_grid *grid, const kifmm_kernel *kernel, const float *I_dev,
+                double prefactor, const int64_t *tgt_idx_dev, int64_t n_tgt,
+                double *out_dev, int32_t fp64_accumulate, void *stream);
+
+/* Morton leaf order of the tree: perm_dev[p] = grid index of the cell stored at
+ * position p of the leaf-ordered layout (int64 [N], device).  For tests. */
+int kifmm_tree_permutation(kifmm_tree tree, int64_t *perm_dev, void *stream);
+
+/* Per-pass timing of kifmm_eval (instrumentation for benchmarks).
+ * kifmm_profile_enable(ops, 1) creates HIP events (on the current device) and
+ * from then on every kifmm_eval with `ops` records an event pair around each
+ * pass on the evaluation stream; (ops, 0) stops recording and clears the sums.
+ * kifmm_profile_read synchronises those events and returns, for each pass
+ * p < n (KIFMM_PASS_*), the summed elapsed milliseconds ms[p] and the number of
+ * kernel launches calls[p] since enabling (either array may be NULL).  While
+ * profiling is on, kifmm_eval may wait for old events when the event pool
+ * (4096 pairs) is nearly full; with profiling off it never waits. */
+enum { KIFMM_PASS_PERMUTE_IN = 0, KIFMM_PASS_P2M = 1, KIFMM_PASS_M2M = 2, KIFMM_PASS_M2L = 3,
+       KIFMM_PASS_L2L = 4, KIFMM_PASS_L2P = 5, KIFMM_PASS_P2P = 6, KIFMM_PASS_PERMUTE_OUT = 7,
+       KIFMM_NPASS = 8 };
+int kifmm_profile_enable(kifmm_ops ops, int32_t on);
+int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n);
+
+void kifmm_tree_destroy(kifmm_tree tree);  /* NULL is ignored */
+void kifmm_ops_destroy(kifmm_ops ops);     /* NULL is ignored */
+const char *kifmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KIFMM_H */

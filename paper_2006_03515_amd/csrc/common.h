@@ -1,0 +1,80 @@
+// Shared definitions of libkifmm (device helpers, error plumbing, internal
+// structures).  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kifmm.h"
+
+namespace kifmm {
+
+// ---------------------------------------------------------------- errors ----
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define KIFMM_HIP(call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------ Morton keys ---
+// 3D Morton key of box coordinates, bits interleaved ... x1 y1 z1 x0 y0 z0
+// (x most significant of each triple).  10 bits per axis.
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton_encode(uint32_t x, uint32_t y, uint32_t z) {
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+__host__ __device__ inline void morton_decode(uint32_t key, int &x, int &y, int &z) {
+    x = (int)compact3(key >> 2);
+    y = (int)compact3(key >> 1);
+    z = (int)compact3(key);
+}
+
+// ------------------------------------------------------------ structures ----
+struct Tree {
+    uint64_t magic;       // identifies the tree for ops/tree matching
+    int n;                // cells per axis
+    int ell;              // leaf side in cells
+    int nb;               // leaves per axis
+    int depth;            // D: levels 0..D, leaves at D
+    int s;                // points per leaf = ell^3
+    int64_t N;            // n^3
+    double h, x0, y0, z0;
+    int32_t *perm;        // device: perm[p] = grid index of leaf-ordered slot p
+};
+
+// One "tap GEMM" launch description: for every output box b of a class,
+//   out[b][0:M] (+)= sum over taps t of A[op_t] (M x K) * in[src(b, t)][0:K]
+enum SrcMode { SRC_SAME = 0, SRC_CHILD = 1, SRC_PARENT = 2, SRC_NBR = 3 };
+
+struct TapList {
+    int nclass;        // 1 or 8
+    int ntaps;         // taps per class (uniform)
+    int *op_dev;       // [nclass][ntaps] operator index
+    int *off_dev;      // [nclass][ntaps] packed offset or child index
+};
+
+}  // namespace kifmm
+
+struct kifmm_tree_s : kifmm::Tree {};

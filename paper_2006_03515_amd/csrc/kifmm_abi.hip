@@ -1,0 +1,920 @@
+// C ABI of libkifmm: argument checking, tree and operator objects, the
+// precompute orchestration and the evaluation schedule (Section 3, algorithm
+// outline: tree, upward pass, downward pass, target potential).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+#include "tapgemm.h"
+
+namespace kifmm {
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+int fail(int code, const std::string &m) {
+    g_err = m;
+    return code;
+}
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+    return KIFMM_EHIP;
+}
+
+// launchers defined in the other translation units
+int launch_direct(const kifmm_grid *, const kifmm_kernel *, const float *, double, const int64_t *,
+                  int64_t, double *, int, hipStream_t);
+int launch_morton_scatter(const Tree &, hipStream_t);
+template <typename T> int launch_permute_in(const Tree &, const T *, T *, hipStream_t);
+template <typename T> int launch_permute_out(const Tree &, const T *, T, T *, hipStream_t);
+int launch_perm_i64(const Tree &, int64_t *, hipStream_t);
+int launch_kmat(const double *, int, const double *, int, const double *, const double *, int, int,
+                const kifmm_kernel &, double, double *, hipStream_t);
+int launch_near(int, double, const int *, int, const kifmm_kernel &, double *, hipStream_t);
+int launch_jacobi_round(double *, double *, const int *, const int *, int, int, int, int64_t,
+                        int64_t, int, int, double, unsigned long long *, hipStream_t);
+int launch_colnorm(const double *, const int *, const int *, int, int64_t, int, int, double *,
+                   hipStream_t);
+int launch_svd_gather(const double *, const double *, int, int, int, int, int, const int *,
+                      const double *, double *, double *, hipStream_t);
+int launch_gemm_f64(int, int, int, const double *, int, int64_t, const double *, int, int64_t,
+                    double *, int, int64_t, int, hipStream_t);
+template <typename T>
+int launch_cast_pad(const double *, int, int, int64_t, T *, int, int, int64_t, int, double,
+                    hipStream_t);
+
+static std::atomic<uint64_t> g_magic{0x6b69666d6d000001ull};
+
+template <typename T>
+static int dmalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return KIFMM_OK;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(KIFMM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                      " bytes failed: " + hipGetErrorString(e));
+    }
+    return KIFMM_OK;
+}
+
+#define KIFMM_TRY(x)                 \
+    do {                             \
+        int rc_ = (x);               \
+        if (rc_ != KIFMM_OK) return rc_; \
+    } while (0)
+
+static int pad_to(int v, int m) { return (v + m - 1) / m * m; }
+
+// ------------------------------------------------------------- point sets --
+// Points of an m x m x m lattice on [-rad, rad]^3 lying on its boundary.
+static void cube_surface(int m, double rad, std::vector<double> &out) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < m; ++k) {
+                if (!(i == 0 || j == 0 || k == 0 || i == m - 1 || j == m - 1 || k == m - 1)) continue;
+                const double t = 2.0 * rad / (m - 1);
+                out.push_back(-rad + i * t);
+                out.push_back(-rad + j * t);
+                out.push_back(-rad + k * t);
+            }
+}
+static void cube_lattice(int m, double rad, std::vector<double> &out) {
+    const double t = 2.0 * rad / (m - 1);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < m; ++k) {
+                out.push_back(-rad + i * t);
+                out.push_back(-rad + j * t);
+                out.push_back(-rad + k * t);
+            }
+}
+struct PointSets {
+    std::vector<double> yu, xu, yd, xd;  // xyz triples, relative to the box centre
+};
+static PointSets make_point_sets(const kifmm_opts &o, double r) {
+    PointSets p;
+    if (o.layout == KIFMM_LAYOUT_PAPER) {
+        cube_surface(o.m0, 1.05 * r, p.yu);
+        cube_surface(o.m0, 2.95 * r, p.xu);
+        cube_surface(o.m0, 2.95 * r, p.yd);
+        cube_surface(o.m0, 1.05 * r, p.xd);
+        return p;
+    }
+    for (double f : {2.95, 4.0, 6.0}) cube_surface(o.check_edge, f * r, p.xu);
+    cube_lattice(o.check_edge, 1.05 * r, p.xd);
+    cube_surface(o.m0, 1.05 * r, p.yu);
+    cube_surface(o.m0, 2.95 * r, p.yd);
+    if (o.layout == KIFMM_LAYOUT_NESTED) {
+        cube_surface(o.m0, 0.55 * r, p.yu);
+        cube_surface(o.m0, 4.0 * r, p.yd);
+    }
+    return p;
+}
+
+static int pack_off(int x, int y, int z) { return ((x + 16) << 10) | ((y + 16) << 5) | (z + 16); }
+
+// the 316 offsets of possible interaction-list members: [-3,3]^3 minus [-1,1]^3
+static std::vector<int> m2l_offsets() {
+    std::vector<int> o;
+    for (int x = -3; x <= 3; ++x)
+        for (int y = -3; y <= 3; ++y)
+            for (int z = -3; z <= 3; ++z)
+                if (std::max({std::abs(x), std::abs(y), std::abs(z)}) >= 2) {
+                    o.push_back(x);
+                    o.push_back(y);
+                    o.push_back(z);
+                }
+    return o;
+}
+
+static int floordiv2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+}  // namespace kifmm
+
+using namespace kifmm;
+
+// ---------------------------------------------------------------- ops type --
+struct kifmm_ops_s {
+    uint64_t tree_magic = 0;
+    int D = 0, ell = 0, s = 0, nb = 0;
+    int KU = 0, KD = 0;
+    std::vector<int> ku, kd;           // retained ranks per level
+    kifmm_kernel kern{};
+    kifmm_opts opts{};
+    // operators
+    float *p2m32 = nullptr, *m2m32 = nullptr, *m2l32 = nullptr, *l2l32 = nullptr, *l2p32 = nullptr,
+          *p2p32 = nullptr;
+    double *p2m64 = nullptr, *m2m64 = nullptr, *m2l64 = nullptr, *l2l64 = nullptr,
+           *l2p64 = nullptr, *p2p64 = nullptr;
+    __bf16 *m2lbf = nullptr;
+    _Float16 *m2lh = nullptr;
+    std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
+    int *taps = nullptr;               // all tap tables
+    TapList t_single{}, t_m2m{}, t_l2l{}, t_m2l{}, t_p2p{};
+    // work buffers (sized for FP64)
+    double *q = nullptr, *Sp = nullptr;
+    std::vector<double *> cu, cd;
+    float *amax = nullptr;
+    int n_amax = 256;
+    // per-pass timing (kifmm_profile_enable)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;        // pool of events, recorded in pairs
+    std::vector<int> ev_pass;          // pass of each recorded pair
+    int ev_used = 0;
+    double prof_ms[KIFMM_NPASS] = {};
+    int64_t prof_calls[KIFMM_NPASS] = {};
+};
+
+static void drain_profile(kifmm_ops o) {
+    for (int i = 0; i < o->ev_used; ++i) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(o->ev[2 * i + 1]);
+        if (hipEventElapsedTime(&ms, o->ev[2 * i], o->ev[2 * i + 1]) == hipSuccess) {
+            o->prof_ms[o->ev_pass[i]] += ms;
+            o->prof_calls[o->ev_pass[i]] += 1;
+        }
+    }
+    o->ev_used = 0;
+}
+
+static void clear_profile(kifmm_ops o) {
+    for (hipEvent_t e : o->ev) (void)hipEventDestroy(e);
+    o->ev.clear();
+    o->ev_pass.clear();
+    o->ev_used = 0;
+    o->prof = false;
+    for (int p = 0; p < KIFMM_NPASS; ++p) { o->prof_ms[p] = 0; o->prof_calls[p] = 0; }
+}
+
+// scoped event pair around one launch (no-op unless profiling is enabled and a
+// free pair is left in the pool)
+struct PassTimer {
+    kifmm_ops o;
+    int slot = -1;
+    hipStream_t st;
+    PassTimer(kifmm_ops ops, int pass, hipStream_t s) : o(ops), st(s) {
+        if (!o->prof || 2 * (o->ev_used + 1) > (int)o->ev.size()) return;
+        slot = o->ev_used++;
+        o->ev_pass[slot] = pass;
+        (void)hipEventRecord(o->ev[2 * slot], st);
+    }
+    ~PassTimer() {
+        if (slot >= 0) (void)hipEventRecord(o->ev[2 * slot + 1], st);
+    }
+};
+
+static void free_ops(kifmm_ops o) {
+    if (!o) return;
+    clear_profile(o);
+    void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
+                    o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lh,
+                    o->taps,  o->q,     o->Sp,    o->amax};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (double *p : o->cu)
+        if (p) (void)hipFree(p);
+    for (double *p : o->cd)
+        if (p) (void)hipFree(p);
+    delete o;
+}
+
+// ------------------------------------------------------------------ checks --
+static int check_grid(const kifmm_grid *g) {
+    if (!g) return fail(KIFMM_EINVAL, "grid is NULL");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(KIFMM_EINVAL, "grid sizes must be > 0");
+    if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0)) return fail(KIFMM_EINVAL, "cell sizes must be > 0");
+    if (!std::isfinite(g->hx) || !std::isfinite(g->hy) || !std::isfinite(g->hz))
+        return fail(KIFMM_EINVAL, "cell sizes must be finite");
+    return KIFMM_OK;
+}
+static int check_kernel(const kifmm_kernel *k) {
+    if (!k) return fail(KIFMM_EINVAL, "kernel is NULL");
+    if (!(k->chi_min > 0) || !(k->chi_max > k->chi_min) || !std::isfinite(k->chi_max))
+        return fail(KIFMM_EINVAL, "need 0 < chi_min < chi_max");
+    if (!(k->p_o2 > 0) || !std::isfinite(k->p_o2)) return fail(KIFMM_EINVAL, "p_o2 must be > 0");
+    return KIFMM_OK;
+}
+
+extern "C" {
+
+const char *kifmm_last_error(void) { return g_err.c_str(); }
+
+int direct_eval(const kifmm_grid *grid, const kifmm_kernel *kernel, const float *I_dev,
+                double prefactor, const int64_t *tgt_idx_dev, int64_t n_tgt, double *out_dev,
+                int32_t fp64_accumulate, void *stream) {
+    KIFMM_TRY(check_grid(grid));
+    KIFMM_TRY(check_kernel(kernel));
+    if (n_tgt < 0) return fail(KIFMM_EINVAL, "n_tgt must be >= 0");
+    if (n_tgt == 0) return KIFMM_OK;
+    if (!I_dev || (!out_dev && n_tgt > 0)) return fail(KIFMM_EINVAL, "I_dev and out_dev must be non-NULL");
+    const int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (!tgt_idx_dev && n_tgt != N) return fail(KIFMM_EINVAL, "tgt_idx_dev NULL requires n_tgt == N");
+    if (!std::isfinite(prefactor)) return fail(KIFMM_EINVAL, "prefactor must be finite");
+    const char *ib = (const char *)I_dev, *ob = (const char *)out_dev;
+    if (n_tgt > 0 && ob < ib + N * sizeof(float) && ib < ob + n_tgt * sizeof(double))
+        return fail(KIFMM_EINVAL, "I_dev and out_dev overlap");
+    return launch_direct(grid, kernel, I_dev, prefactor, tgt_idx_dev, n_tgt, out_dev,
+                         fp64_accumulate ? 1 : 0, (hipStream_t)stream);
+}
+
+int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kifmm_tree *out) {
+    if (!out) return fail(KIFMM_EINVAL, "out is NULL");
+    KIFMM_TRY(check_grid(grid));
+    if (max_leaf < 1) return fail(KIFMM_EINVAL, "max_leaf must be >= 1");
+    if (grid->nx != grid->ny || grid->nx != grid->nz)
+        return fail(KIFMM_EUNSUPPORTED, "only cubic grids (nx == ny == nz) are supported");
+    if (grid->hx != grid->hy || grid->hx != grid->hz)
+        return fail(KIFMM_EUNSUPPORTED, "only cubic cells (hx == hy == hz) are supported");
+    const int n = grid->nx;
+    if (n & (n - 1)) return fail(KIFMM_EUNSUPPORTED, "n must be a power of two");
+    if (n > 1024) return fail(KIFMM_EUNSUPPORTED, "n must be <= 1024");
+    int ell = 1;
+    while (2 * ell <= n && (int64_t)(2 * ell) * (2 * ell) * (2 * ell) <= max_leaf) ell *= 2;
+    if (ell < 4)
+        return fail(KIFMM_EUNSUPPORTED, "leaves must hold at least 4^3 cells (n >= 4, max_leaf >= 64)");
+    kifmm_tree t = new (std::nothrow) kifmm_tree_s();
+    if (!t) return fail(KIFMM_ENOMEM, "host allocation failed");
+    t->magic = g_magic.fetch_add(1);
+    t->n = n;
+    t->ell = ell;
+    t->nb = n / ell;
+    t->depth = 0;
+    while ((1 << t->depth) < t->nb) ++t->depth;
+    t->s = ell * ell * ell;
+    t->N = (int64_t)n * n * n;
+    t->h = grid->hx;
+    t->x0 = grid->x0;
+    t->y0 = grid->y0;
+    t->z0 = grid->z0;
+    t->perm = nullptr;
+    int rc = dmalloc(&t->perm, (size_t)t->N);
+    if (rc == KIFMM_OK) rc = launch_morton_scatter(*t, (hipStream_t)stream);
+    if (rc == KIFMM_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (rc != KIFMM_OK) {
+        if (t->perm) (void)hipFree(t->perm);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return KIFMM_OK;
+}
+
+int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side) {
+    if (!tree) return fail(KIFMM_EINVAL, "tree is NULL");
+    if (depth) *depth = tree->depth;
+    if (leaf_side) *leaf_side = tree->ell;
+    return KIFMM_OK;
+}
+
+int kifmm_tree_permutation(kifmm_tree tree, int64_t *perm_dev, void *stream) {
+    if (!tree || !perm_dev) return fail(KIFMM_EINVAL, "tree and perm_dev must be non-NULL");
+    return launch_perm_i64(*tree, perm_dev, (hipStream_t)stream);
+}
+
+void kifmm_tree_destroy(kifmm_tree tree) {
+    if (!tree) return;
+    if (tree->perm) (void)hipFree(tree->perm);
+    delete tree;
+}
+
+void kifmm_ops_destroy(kifmm_ops ops) { free_ops(ops); }
+
+int kifmm_ops_rank(kifmm_ops ops, int32_t level, int32_t *k_up, int32_t *k_down) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    if (level < 2 || level > ops->D) return fail(KIFMM_EINVAL, "level out of range");
+    if (k_up) *k_up = ops->ku[level];
+    if (k_down) *k_down = ops->kd[level];
+    return KIFMM_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------- precompute --
+namespace {
+
+struct DevBuf {  // scoped FP64 scratch for the precompute
+    std::vector<void *> ptrs;
+    ~DevBuf() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    int get(T **p, size_t count) {
+        int rc = dmalloc(p, count);
+        if (rc == KIFMM_OK && *p) ptrs.push_back(*p);
+        return rc;
+    }
+};
+
+template <typename T>
+int upload(DevBuf &db, const std::vector<T> &h, T **d, hipStream_t st) {
+    KIFMM_TRY(db.get(d, h.size()));
+    KIFMM_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return KIFMM_OK;
+}
+
+// truncated SVDs of a batch of same-shape matrices G(X_b, Y_b) (m x n).
+// Output per batch item: UT (k x m) and W = V S^-1 (n x k), FP64 device.
+struct Factor {
+    double *UT = nullptr, *W = nullptr;
+    int k = 0, m = 0, n = 0;
+};
+
+int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::vector<const double *> &Y,
+                 int m, int n, const kifmm_kernel &kern, double h, double rcond,
+                 std::vector<Factor> &out, hipStream_t st) {
+    const int B = (int)X.size();
+    const int npad = n + (n & 1);
+    double *A, *V;
+    KIFMM_TRY(db.get(&A, (size_t)B * npad * m));
+    KIFMM_TRY(db.get(&V, (size_t)B * npad * npad));
+    std::vector<double> eye((size_t)npad * npad, 0.0);
+    for (int i = 0; i < npad; ++i) eye[(size_t)i * npad + i] = 1.0;
+    for (int b = 0; b < B; ++b) {
+        KIFMM_HIP(hipMemsetAsync(A + (size_t)b * npad * m, 0, sizeof(double) * npad * m, st));
+        // column j of G(X, Y) stored contiguously: transposed kernel matrix
+        KIFMM_TRY(launch_kmat(X[b], m, Y[b], n, nullptr, nullptr, 1, 1, kern, h,
+                              A + (size_t)b * npad * m, st));
+        KIFMM_HIP(hipMemcpyAsync(V + (size_t)b * npad * npad, eye.data(), eye.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+    }
+    std::vector<int> md(B, m), nd(B, n);
+    int *mdd, *ndd;
+    KIFMM_TRY(upload(db, md, &mdd, st));
+    KIFMM_TRY(upload(db, nd, &ndd, st));
+    unsigned long long *offd;
+    KIFMM_TRY(db.get(&offd, (size_t)B));
+    const double tol = 1e-13;
+    std::vector<unsigned long long> zeros(B, 0), offh(B);
+    bool converged = false;
+    for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+        KIFMM_HIP(hipMemcpyAsync(offd, zeros.data(), B * sizeof(unsigned long long),
+                                 hipMemcpyHostToDevice, st));
+        for (int r = 0; r < npad - 1; ++r)
+            KIFMM_TRY(launch_jacobi_round(A, V, mdd, ndd, npad, m, npad, (int64_t)npad * m,
+                                          (int64_t)npad * npad, B, r, tol, offd, st));
+        KIFMM_HIP(hipMemcpyAsync(offh.data(), offd, B * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st));
+        KIFMM_HIP(hipStreamSynchronize(st));
+        converged = true;
+        for (int b = 0; b < B; ++b) {
+            double v;
+            std::memcpy(&v, &offh[b], sizeof(double));
+            if (v > tol) converged = false;
+        }
+    }
+    if (!converged) return fail(KIFMM_EHIP, "Jacobi SVD did not converge in 40 sweeps");
+    double *sig;
+    KIFMM_TRY(db.get(&sig, (size_t)B * npad));
+    KIFMM_TRY(launch_colnorm(A, mdd, ndd, m, (int64_t)npad * m, npad, B, sig, st));
+    std::vector<double> sh((size_t)B * npad);
+    KIFMM_HIP(hipMemcpyAsync(sh.data(), sig, sh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    KIFMM_HIP(hipStreamSynchronize(st));
+    out.assign(B, Factor());
+    for (int b = 0; b < B; ++b) {
+        std::vector<int> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        const double *s = sh.data() + (size_t)b * npad;
+        std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return s[i] > s[j]; });
+        const double smax = s[order[0]];
+        int k = 0;
+        while (k < n && s[order[k]] > rcond * smax) ++k;
+        if (k == 0) return fail(KIFMM_EINVAL, "kernel matrix is zero at this pressure/size");
+        std::vector<double> sk(k);
+        for (int i = 0; i < k; ++i) sk[i] = s[order[i]];
+        order.resize(k);
+        int *ordd;
+        double *skd;
+        KIFMM_TRY(upload(db, order, &ordd, st));
+        KIFMM_TRY(upload(db, sk, &skd, st));
+        Factor &f = out[b];
+        f.k = k; f.m = m; f.n = n;
+        KIFMM_TRY(db.get(&f.UT, (size_t)k * m));
+        KIFMM_TRY(db.get(&f.W, (size_t)n * k));
+        KIFMM_TRY(launch_svd_gather(A + (size_t)b * npad * m, V + (size_t)b * npad * npad, m, npad,
+                                    m, n, k, ordd, skd, f.UT, f.W, st));
+    }
+    return KIFMM_OK;
+}
+
+// batch of operators  UT (k1 x m, shared) . G(X + sx_b, Y + sy_b) (m x n) . W (n x k2, shared or null)
+int fused_ops(DevBuf &db, const double *UT, int k1, const double *X, int m, const double *Y, int n,
+              const double *W, int k2, const double *sx, const double *sy, int batch,
+              const kifmm_kernel &kern, double h, double *out, hipStream_t st) {
+    double *G, *T1;
+    KIFMM_TRY(db.get(&G, (size_t)batch * m * n));
+    KIFMM_TRY(launch_kmat(X, m, Y, n, sx, sy, batch, 0, kern, h, G, st));
+    if (UT && W) {
+        KIFMM_TRY(db.get(&T1, (size_t)batch * k1 * n));
+        KIFMM_TRY(launch_gemm_f64(k1, n, m, UT, m, 0, G, n, (int64_t)m * n, T1, n, (int64_t)k1 * n,
+                                  batch, st));
+        KIFMM_TRY(launch_gemm_f64(k1, k2, n, T1, n, (int64_t)k1 * n, W, k2, 0, out, k2,
+                                  (int64_t)k1 * k2, batch, st));
+    } else if (UT) {
+        KIFMM_TRY(launch_gemm_f64(k1, n, m, UT, m, 0, G, n, (int64_t)m * n, out, n, (int64_t)k1 * n,
+                                  batch, st));
+    } else {
+        KIFMM_TRY(launch_gemm_f64(m, k2, n, G, n, (int64_t)m * n, W, k2, 0, out, k2, (int64_t)m * k2,
+                                  batch, st));
+    }
+    return KIFMM_OK;
+}
+
+template <typename T>
+int store(const double *src, int M, int K, int batch, T *dst, int Mp, int Kp, double scale,
+          hipStream_t st) {
+    return launch_cast_pad<T>(src, M, K, (int64_t)M * K, dst, Mp, Kp, (int64_t)Mp * Kp, batch, scale, st);
+}
+
+int store_both(const double *src, int M, int K, int batch, float *d32, double *d64, int Mp, int Kp,
+               hipStream_t st) {
+    KIFMM_TRY(store<float>(src, M, K, batch, d32, Mp, Kp, 1.0, st));
+    KIFMM_TRY(store<double>(src, M, K, batch, d64, Mp, Kp, 1.0, st));
+    return KIFMM_OK;
+}
+
+int max_abs_host(const double *d, size_t count, double *out, hipStream_t st) {
+    std::vector<double> h(count);
+    KIFMM_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    KIFMM_HIP(hipStreamSynchronize(st));
+    double m = 0;
+    for (double v : h) m = std::max(m, std::fabs(v));
+    *out = m;
+    return KIFMM_OK;
+}
+
+int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
+    DevBuf db;
+    const int D = o->D, s = o->s, ell = o->ell;
+    const double h = tree->h, Lside = tree->h * tree->n;
+    const kifmm_kernel &kern = o->kern;
+    o->ku.assign(D + 1, 0);
+    o->kd.assign(D + 1, 0);
+
+    // near-range matrices (27 taps) -- always needed
+    std::vector<int> nbr;
+    for (int x = -1; x <= 1; ++x)
+        for (int y = -1; y <= 1; ++y)
+            for (int z = -1; z <= 1; ++z) {
+                nbr.push_back(x);
+                nbr.push_back(y);
+                nbr.push_back(z);
+            }
+    int *nbrd;
+    KIFMM_TRY(upload(db, nbr, &nbrd, st));
+    double *p2p;
+    KIFMM_TRY(db.get(&p2p, (size_t)27 * s * s));
+    KIFMM_TRY(launch_near(ell, h, nbrd, 27, kern, p2p, st));
+    KIFMM_TRY(dmalloc(&o->p2p32, (size_t)27 * s * s));
+    KIFMM_TRY(dmalloc(&o->p2p64, (size_t)27 * s * s));
+    KIFMM_TRY(store_both(p2p, s, s, 27, o->p2p32, o->p2p64, s, s, st));
+
+    // tap tables
+    std::vector<int> taps;
+    auto add_list = [&](TapList &tl, int nclass, int ntaps, const std::vector<int> &op,
+                        const std::vector<int> &off) {
+        tl.nclass = nclass;
+        tl.ntaps = ntaps;
+        tl.op_dev = (int *)(size_t)taps.size();  // offset, fixed up after upload
+        taps.insert(taps.end(), op.begin(), op.end());
+        tl.off_dev = (int *)(size_t)taps.size();
+        taps.insert(taps.end(), off.begin(), off.end());
+    };
+    {
+        std::vector<int> op(27), off(27);
+        for (int t = 0; t < 27; ++t) {
+            op[t] = t;
+            off[t] = pack_off(nbr[3 * t], nbr[3 * t + 1], nbr[3 * t + 2]);
+        }
+        add_list(o->t_p2p, 1, 27, op, off);
+        add_list(o->t_single, 1, 1, {0}, {0});
+        std::vector<int> c8(8);
+        std::iota(c8.begin(), c8.end(), 0);
+        add_list(o->t_m2m, 1, 8, c8, c8);
+        add_list(o->t_l2l, 8, 1, c8, std::vector<int>(8, 0));
+    }
+    const std::vector<int> m2lo = m2l_offsets();
+    const int n316 = (int)m2lo.size() / 3;
+    {
+        std::vector<int> op, off;
+        int ntaps = -1;
+        for (int p = 0; p < 8; ++p) {
+            const int par[3] = {(p >> 2) & 1, (p >> 1) & 1, p & 1};
+            int cnt = 0;
+            for (int t = 0; t < n316; ++t) {
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    const int f = floordiv2(par[a] + m2lo[3 * t + a]);
+                    if (f < -1 || f > 1) ok = false;
+                }
+                if (!ok) continue;
+                op.push_back(t);
+                off.push_back(pack_off(m2lo[3 * t], m2lo[3 * t + 1], m2lo[3 * t + 2]));
+                ++cnt;
+            }
+            if (ntaps < 0) ntaps = cnt;
+            if (cnt != ntaps) return fail(KIFMM_EINVAL, "internal: uneven interaction lists");
+        }
+        add_list(o->t_m2l, 8, ntaps, op, off);
+    }
+    KIFMM_TRY(dmalloc(&o->taps, taps.size()));
+    KIFMM_HIP(hipMemcpyAsync(o->taps, taps.data(), taps.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    for (TapList *tl : {&o->t_p2p, &o->t_single, &o->t_m2m, &o->t_l2l, &o->t_m2l}) {
+        tl->op_dev = o->taps + (size_t)tl->op_dev;
+        tl->off_dev = o->taps + (size_t)tl->off_dev;
+    }
+
+    // work buffers
+    KIFMM_TRY(dmalloc(&o->q, (size_t)tree->N));
+    KIFMM_TRY(dmalloc(&o->Sp, (size_t)tree->N));
+    KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
+    o->cu.assign(D + 1, nullptr);
+    o->cd.assign(D + 1, nullptr);
+    if (D < 2) {
+        KIFMM_HIP(hipStreamSynchronize(st));
+        return KIFMM_OK;
+    }
+
+    // point sets per level, relative to the box centre
+    std::vector<PointSets> ps(D + 1);
+    std::vector<double *> yu(D + 1), xu(D + 1), yd(D + 1), xd(D + 1);
+    for (int l = 2; l <= D; ++l) {
+        const double r = Lside / std::ldexp(1.0, l + 1);
+        ps[l] = make_point_sets(o->opts, r);
+        KIFMM_TRY(upload(db, ps[l].yu, &yu[l], st));
+        KIFMM_TRY(upload(db, ps[l].xu, &xu[l], st));
+        KIFMM_TRY(upload(db, ps[l].yd, &yd[l], st));
+        KIFMM_TRY(upload(db, ps[l].xd, &xd[l], st));
+    }
+    const int nyu = (int)ps[2].yu.size() / 3, nxu = (int)ps[2].xu.size() / 3;
+    const int nyd = (int)ps[2].yd.size() / 3, nxd = (int)ps[2].xd.size() / 3;
+
+    // truncated SVDs of the check-to-equivalent matrices, every level
+    std::vector<const double *> X, Y;
+    for (int l = 2; l <= D; ++l) { X.push_back(xu[l]); Y.push_back(yu[l]); }
+    std::vector<Factor> fu, fd;
+    KIFMM_TRY(batched_tsvd(db, X, Y, nxu, nyu, kern, h, o->opts.rcond, fu, st));
+    X.clear(); Y.clear();
+    for (int l = 2; l <= D; ++l) { X.push_back(xd[l]); Y.push_back(yd[l]); }
+    KIFMM_TRY(batched_tsvd(db, X, Y, nxd, nyd, kern, h, o->opts.rcond, fd, st));
+    int kumax = 0, kdmax = 0;
+    for (int l = 2; l <= D; ++l) {
+        o->ku[l] = fu[l - 2].k;
+        o->kd[l] = fd[l - 2].k;
+        kumax = std::max(kumax, o->ku[l]);
+        kdmax = std::max(kdmax, o->kd[l]);
+    }
+    const int KU = pad_to(kumax, 32), KD = pad_to(kdmax, 32);
+    o->KU = KU;
+    o->KD = KD;
+    auto UTu = [&](int l) { return fu[l - 2].UT; };
+    auto Wu = [&](int l) { return fu[l - 2].W; };
+    auto UTd = [&](int l) { return fd[l - 2].UT; };
+    auto Wd = [&](int l) { return fd[l - 2].W; };
+
+    // leaf cell centres relative to the leaf centre, C order
+    std::vector<double> P;
+    for (int i = 0; i < ell; ++i)
+        for (int j = 0; j < ell; ++j)
+            for (int k = 0; k < ell; ++k) {
+                P.push_back((i + 0.5) * h - 0.5 * ell * h);
+                P.push_back((j + 0.5) * h - 0.5 * ell * h);
+                P.push_back((k + 0.5) * h - 0.5 * ell * h);
+            }
+    double *Pd;
+    KIFMM_TRY(upload(db, P, &Pd, st));
+
+    // P2M (eq. (s2m)): U_u^T G(x^u, leaf cells)       k_u x s
+    {
+        double *tmp;
+        KIFMM_TRY(db.get(&tmp, (size_t)o->ku[D] * s));
+        KIFMM_TRY(fused_ops(db, UTu(D), o->ku[D], xu[D], nxu, Pd, s, nullptr, 0, nullptr, nullptr, 1,
+                            kern, h, tmp, st));
+        KIFMM_TRY(dmalloc(&o->p2m32, (size_t)KU * s));
+        KIFMM_TRY(dmalloc(&o->p2m64, (size_t)KU * s));
+        KIFMM_TRY(store_both(tmp, o->ku[D], s, 1, o->p2m32, o->p2m64, KU, s, st));
+    }
+    // L2P: G(leaf cells, y^d) V_d S^-1                  s x k_d
+    {
+        double *tmp;
+        KIFMM_TRY(db.get(&tmp, (size_t)s * o->kd[D]));
+        KIFMM_TRY(fused_ops(db, nullptr, 0, Pd, s, yd[D], nyd, Wd(D), o->kd[D], nullptr, nullptr, 1,
+                            kern, h, tmp, st));
+        KIFMM_TRY(dmalloc(&o->l2p32, (size_t)s * KD));
+        KIFMM_TRY(dmalloc(&o->l2p64, (size_t)s * KD));
+        KIFMM_TRY(store_both(tmp, s, o->kd[D], 1, o->l2p32, o->l2p64, s, KD, st));
+    }
+    // child centre offsets at a level of half-width r: (2c - 1) r per axis
+    auto child_shifts = [&](double r) {
+        std::vector<double> v;
+        for (int c = 0; c < 8; ++c) {
+            v.push_back((2 * ((c >> 2) & 1) - 1) * r);
+            v.push_back((2 * ((c >> 1) & 1) - 1) * r);
+            v.push_back((2 * (c & 1) - 1) * r);
+        }
+        return v;
+    };
+    // M2M (eq. (m2m)), levels 2..D-1: U_u^T(l) G(x^u(l), y^u(l+1) + child) W_u(l+1)
+    if (D >= 3) {
+        KIFMM_TRY(dmalloc(&o->m2m32, (size_t)(D - 2) * 8 * KU * KU));
+        KIFMM_TRY(dmalloc(&o->m2m64, (size_t)(D - 2) * 8 * KU * KU));
+        KIFMM_TRY(dmalloc(&o->l2l32, (size_t)(D - 2) * 8 * KD * KD));
+        KIFMM_TRY(dmalloc(&o->l2l64, (size_t)(D - 2) * 8 * KD * KD));
+        for (int l = 2; l <= D - 1; ++l) {
+            const double rc = Lside / std::ldexp(1.0, l + 2);
+            double *sh, *tmp;
+            KIFMM_TRY(upload(db, child_shifts(rc), &sh, st));
+            KIFMM_TRY(db.get(&tmp, (size_t)8 * o->ku[l] * o->ku[l + 1]));
+            KIFMM_TRY(fused_ops(db, UTu(l), o->ku[l], xu[l], nxu, yu[l + 1], nyu, Wu(l + 1),
+                                o->ku[l + 1], nullptr, sh, 8, kern, h, tmp, st));
+            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
+            KIFMM_TRY(store_both(tmp, o->ku[l], o->ku[l + 1], 8, o->m2m32 + so, o->m2m64 + so, KU, KU, st));
+        }
+        // L2L (eq. (l2l)), levels 3..D: U_d^T(l) G(x^d(l) + child, y^d(l-1)) W_d(l-1)
+        for (int l = 3; l <= D; ++l) {
+            const double r = Lside / std::ldexp(1.0, l + 1);
+            double *sh, *tmp;
+            KIFMM_TRY(upload(db, child_shifts(r), &sh, st));
+            KIFMM_TRY(db.get(&tmp, (size_t)8 * o->kd[l] * o->kd[l - 1]));
+            KIFMM_TRY(fused_ops(db, UTd(l), o->kd[l], xd[l], nxd, yd[l - 1], nyd, Wd(l - 1),
+                                o->kd[l - 1], sh, nullptr, 8, kern, h, tmp, st));
+            const size_t so = (size_t)(l - 3) * 8 * KD * KD;
+            KIFMM_TRY(store_both(tmp, o->kd[l], o->kd[l - 1], 8, o->l2l32 + so, o->l2l64 + so, KD, KD, st));
+        }
+    }
+    // M2L (eq. (m2l)), levels 2..D, 316 offsets: U_d^T G(x^d, y^u + 2 r o) W_u
+    {
+        const size_t per = (size_t)n316 * KD * KU;
+        KIFMM_TRY(dmalloc(&o->m2l32, (size_t)(D - 1) * per));
+        KIFMM_TRY(dmalloc(&o->m2l64, (size_t)(D - 1) * per));
+        KIFMM_TRY(dmalloc(&o->m2lbf, (size_t)(D - 1) * per));
+        KIFMM_TRY(dmalloc(&o->m2lh, (size_t)(D - 1) * per));
+        o->m2l_scale.assign(D + 1, 1.0f);
+        double *G, *T1, *tmp, *sh;
+        const size_t maxk = (size_t)std::max(kumax, kdmax);
+        KIFMM_TRY(db.get(&G, (size_t)n316 * nxd * nyu));
+        KIFMM_TRY(db.get(&T1, (size_t)n316 * maxk * nyu));
+        KIFMM_TRY(db.get(&tmp, (size_t)n316 * maxk * maxk));
+        KIFMM_TRY(db.get(&sh, (size_t)3 * n316));
+        for (int l = 2; l <= D; ++l) {
+            const double r = Lside / std::ldexp(1.0, l + 1);
+            std::vector<double> shifts(3 * n316);
+            for (int i = 0; i < 3 * n316; ++i) shifts[i] = 2.0 * r * m2lo[i];
+            KIFMM_HIP(hipMemcpyAsync(sh, shifts.data(), shifts.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, st));
+            const int kd = o->kd[l], ku = o->ku[l];
+            KIFMM_TRY(launch_kmat(xd[l], nxd, yu[l], nyu, nullptr, sh, n316, 0, kern, h, G, st));
+            KIFMM_TRY(launch_gemm_f64(kd, nyu, nxd, UTd(l), nxd, 0, G, nyu, (int64_t)nxd * nyu, T1,
+                                      nyu, (int64_t)kd * nyu, n316, st));
+            KIFMM_TRY(launch_gemm_f64(kd, ku, nyu, T1, nyu, (int64_t)kd * nyu, Wu(l), ku, 0, tmp, ku,
+                                      (int64_t)kd * ku, n316, st));
+            const size_t so = (size_t)(l - 2) * per;
+            KIFMM_TRY(store_both(tmp, kd, ku, n316, o->m2l32 + so, o->m2l64 + so, KD, KU, st));
+            double mx;
+            KIFMM_TRY(max_abs_host(tmp, (size_t)n316 * kd * ku, &mx, st));
+            if (!(mx > 0)) mx = 1.0;
+            o->m2l_scale[l] = (float)mx;
+            KIFMM_TRY(store<__bf16>(tmp, kd, ku, n316, o->m2lbf + so, KD, KU, 1.0 / mx, st));
+            KIFMM_TRY(store<_Float16>(tmp, kd, ku, n316, o->m2lh + so, KD, KU, 1.0 / mx, st));
+        }
+    }
+    for (int l = 2; l <= D; ++l) {
+        const size_t nbx = (size_t)1 << (3 * l);
+        KIFMM_TRY(dmalloc(&o->cu[l], nbx * KU));
+        KIFMM_TRY(dmalloc(&o->cd[l], nbx * KD));
+    }
+    KIFMM_HIP(hipStreamSynchronize(st));
+    return KIFMM_OK;
+}
+
+// ------------------------------------------------------------- evaluation --
+template <typename TA, typename T>
+TapArgs<TA, T, T> tap(const TA *A, int64_t a_stride, int M, int K, const T *in, int64_t in_ld, T *out,
+                      int64_t out_ld, int mode, int nl, const TapList &tl, int cls_stride,
+                      int64_t n_per_class, int accumulate) {
+    TapArgs<TA, T, T> p{};
+    p.A = A; p.a_stride = a_stride; p.M = M; p.K = K;
+    p.in = in; p.in_ld = in_ld; p.out = out; p.out_ld = out_ld;
+    p.mode = mode; p.nl = nl; p.nclass = tl.nclass; p.cls_stride = cls_stride;
+    p.n_per_class = n_per_class; p.tap_op = tl.op_dev; p.tap_off = tl.off_dev; p.ntaps = tl.ntaps;
+    p.accumulate = accumulate;
+    p.amax = nullptr; p.n_amax = 0; p.op_scale = 1.0f;
+    return p;
+}
+
+int run(const TapArgs<float, float, float> &p, hipStream_t st) { return run_tap_f32(p, st); }
+int run(const TapArgs<double, double, double> &p, hipStream_t st) { return run_tap_f64(p, st); }
+
+template <typename T>
+struct OpSet {
+    const T *p2m, *m2m, *m2l, *l2l, *l2p, *p2p;
+};
+
+template <typename T>
+int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, int precision,
+               hipStream_t st) {
+    OpSet<T> ops;
+    if constexpr (sizeof(T) == 8) ops = {o->p2m64, o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64};
+    else ops = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32};
+    T *q = (T *)o->q, *Sp = (T *)o->Sp;
+    const int D = o->D, s = o->s, nb = o->nb, KU = o->KU, KD = o->KD;
+    const int64_t nleaf = (int64_t)nb * nb * nb;
+    {
+        PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
+        KIFMM_TRY(launch_permute_in<T>(*t, I, q, st));
+    }
+    if (D >= 2) {
+        T *cuD = (T *)o->cu[D];
+        {
+            PassTimer pt(o, KIFMM_PASS_P2M, st);
+            KIFMM_TRY(run(tap<T, T>(ops.p2m, 0, KU, s, q, s, cuD, KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0), st));
+        }
+        for (int l = D - 1; l >= 2; --l) {
+            const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
+            PassTimer pt(o, KIFMM_PASS_M2M, st);
+            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU,
+                                 SRC_CHILD, 0, o->t_m2m, 1, (int64_t)1 << (3 * l), 0), st));
+        }
+        const size_t per = (size_t)316 * KD * KU;
+        for (int l = 2; l <= D; ++l) {
+            const int64_t nper = (int64_t)1 << (3 * (l - 1));
+            if (l > 2) {
+                const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
+                PassTimer pt(o, KIFMM_PASS_L2L, st);
+                KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD,
+                                     SRC_PARENT, 0, o->t_l2l, 8, nper, 0), st));
+            }
+            const int acc = l > 2 ? 1 : 0;
+            PassTimer pt(o, KIFMM_PASS_M2L, st);
+            if constexpr (sizeof(T) == 4) {
+                if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16) {
+                    const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
+                    KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
+                    const size_t so = (size_t)(l - 2) * per;
+                    const int64_t ldA = (int64_t)KD * KU;
+                    if (precision == KIFMM_M2L_BF16) {
+                        auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
+                                                    (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8,
+                                                    nper, acc);
+                        p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+                        KIFMM_TRY(run_tap_lp<__bf16>(p, st));
+                    } else {
+                        auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
+                                                      (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8,
+                                                      nper, acc);
+                        p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+                        KIFMM_TRY(run_tap_lp<_Float16>(p, st));
+                    }
+                    continue;
+                }
+            }
+            const T *A = ops.m2l + (size_t)(l - 2) * per;
+            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KU, KD, KU, (T *)o->cu[l], KU, (T *)o->cd[l], KD, SRC_NBR,
+                                 1 << l, o->t_m2l, 8, nper, acc), st));
+        }
+        PassTimer pt(o, KIFMM_PASS_L2P, st);
+        KIFMM_TRY(run(tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1,
+                             nleaf, 0), st));
+    }
+    {
+        PassTimer pt(o, KIFMM_PASS_P2P, st);
+        KIFMM_TRY(run(tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, Sp, s, SRC_NBR, nb, o->t_p2p, 1, nleaf,
+                         D >= 2 ? 1 : 0), st));
+    }
+    const T scale = (T)(prefactor * t->h * t->h * t->h);
+    PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
+    KIFMM_TRY(launch_permute_out<T>(*t, Sp, scale, S, st));
+    return KIFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, const kifmm_opts *opts,
+                               void *stream, kifmm_ops *out) {
+    if (!tree || !out) return fail(KIFMM_EINVAL, "tree and out must be non-NULL");
+    KIFMM_TRY(check_kernel(kernel));
+    kifmm_opts o;
+    if (opts) o = *opts;
+    else { o.layout = KIFMM_LAYOUT_SINGLE; o.m0 = 6; o.check_edge = 10; o.rcond = 1e-7; }
+    if (o.layout < 0 || o.layout > 2) return fail(KIFMM_EINVAL, "unknown layout");
+    if (o.m0 < 2 || o.m0 > 16) return fail(KIFMM_EINVAL, "m0 must be in [2, 16]");
+    if (o.layout != KIFMM_LAYOUT_PAPER && (o.check_edge < 2 || o.check_edge > 16))
+        return fail(KIFMM_EINVAL, "check_edge must be in [2, 16]");
+    if (!(o.rcond > 0 && o.rcond < 1)) return fail(KIFMM_EINVAL, "rcond must be in (0, 1)");
+    kifmm_ops ops = new (std::nothrow) kifmm_ops_s();
+    if (!ops) return fail(KIFMM_ENOMEM, "host allocation failed");
+    ops->tree_magic = tree->magic;
+    ops->D = tree->depth;
+    ops->ell = tree->ell;
+    ops->s = tree->s;
+    ops->nb = tree->nb;
+    ops->kern = *kernel;
+    ops->opts = o;
+    int rc = build_ops(tree, ops, (hipStream_t)stream);
+    if (rc != KIFMM_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        free_ops(ops);
+        return rc;
+    }
+    *out = ops;
+    return KIFMM_OK;
+}
+
+int kifmm_profile_enable(kifmm_ops ops, int32_t on) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    clear_profile(ops);
+    if (!on) return KIFMM_OK;
+    const int pairs = 4096;
+    ops->ev.resize(2 * pairs);
+    ops->ev_pass.assign(pairs, 0);
+    for (auto &e : ops->ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            e = nullptr;
+            ops->ev.resize(&e - ops->ev.data());
+            clear_profile(ops);
+            return hip_fail(r, "hipEventCreate");
+        }
+    }
+    ops->prof = true;
+    return KIFMM_OK;
+}
+
+int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    drain_profile(ops);
+    for (int p = 0; p < n && p < KIFMM_NPASS; ++p) {
+        if (ms) ms[p] = ops->prof_ms[p];
+        if (calls) calls[p] = ops->prof_calls[p];
+    }
+    return KIFMM_OK;
+}
+
+int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor, void *S_dev,
+               int32_t precision, void *stream) {
+    if (!tree || !ops) return fail(KIFMM_EINVAL, "tree and ops must be non-NULL");
+    if (ops->tree_magic != tree->magic) return fail(KIFMM_EMISMATCH, "ops were built for another tree");
+    if (!I_dev || !S_dev) return fail(KIFMM_EINVAL, "I_dev and S_dev must be non-NULL");
+    if (!std::isfinite(prefactor)) return fail(KIFMM_EINVAL, "prefactor must be finite");
+    if (precision < KIFMM_FP64 || precision > KIFMM_M2L_FP16) return fail(KIFMM_EINVAL, "unknown precision");
+    const size_t esz = precision == KIFMM_FP64 ? 8 : 4;
+    const char *ib = (const char *)I_dev, *sb = (const char *)S_dev;
+    const size_t bytes = (size_t)tree->N * esz;
+    if (sb < ib + bytes && ib < sb + bytes) return fail(KIFMM_EINVAL, "I_dev and S_dev overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (ops->prof && 2 * (ops->ev_used + 64) > (int)ops->ev.size()) drain_profile(ops);
+    if (precision == KIFMM_FP64)
+        return eval_typed<double>(tree, ops, (const double *)I_dev, (double *)S_dev, prefactor, precision, st);
+    return eval_typed<float>(tree, ops, (const float *)I_dev, (float *)S_dev, prefactor, precision, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Launch description of the tap-GEMM engine (see tapgemm.hip).
+#pragma once
+#include "common.h"
+
+namespace kifmm {
+
+template <typename TA, typename TI, typename TO>
+struct TapArgs {
+    const TA *A;          // operators, op i at A + i * a_stride, row-major M x K
+    int64_t a_stride;
+    int M, K;             // padded rows / columns
+    const TI *in;         // in[src * in_ld + k]
+    int64_t in_ld;
+    TO *out;              // out[b * out_ld + row]
+    int64_t out_ld;
+    int mode;             // SrcMode
+    int nl;               // boxes per axis of the source level (SRC_NBR)
+    int nclass;           // gridDim.z
+    int cls_stride;       // output box = cls_stride * j + class
+    int64_t n_per_class;
+    const int *tap_op;    // [nclass][ntaps]
+    const int *tap_off;   // [nclass][ntaps]
+    int ntaps;
+    int accumulate;       // 0: out = sum, 1: out += sum
+    const float *amax;    // low precision: partial maxima of |in|
+    int n_amax;
+    float op_scale;       // low precision: A was stored divided by op_scale
+};
+
+int run_tap_f32(const TapArgs<float, float, float> &p, hipStream_t st);
+int run_tap_f32_valu(const TapArgs<float, float, float> &p, hipStream_t st);
+int run_tap_f64(const TapArgs<double, double, double> &p, hipStream_t st);
+template <typename TL>
+int run_tap_lp(const TapArgs<TL, float, float> &p, hipStream_t st);
+int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st);
+
+}  // namespace kifmm

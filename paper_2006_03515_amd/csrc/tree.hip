@@ -1,0 +1,99 @@
+// Octree over a uniform n^3 grid (Section 3, tree construction step).
+//
+// The complete octree with ell^3-cell leaves is visited in pre-order by the
+// Morton order of the leaves.  Every cell gets the key
+//     key = morton(leaf coordinates) * ell^3 + (C-order index inside the leaf)
+// Keys are distinct and cover [0, N) exactly, so sorting the cells by key is a
+// single scatter perm[key] = cell (a counting sort whose buckets hold one cell
+// each).  The layouts used by the evaluation (q and S in leaf order) index
+// through perm.
+#include "common.h"
+
+namespace kifmm {
+
+namespace {
+
+__global__ void morton_scatter_kernel(int n, int ell, int lg_ell, int64_t N, int32_t *perm) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < N;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g / ((int64_t)n * n));
+        const int j = (int)((g / n) % n);
+        const int k = (int)(g % n);
+        const uint32_t leaf = morton_encode(i >> lg_ell, j >> lg_ell, k >> lg_ell);
+        const int mask = ell - 1;
+        const int64_t local = (((int64_t)(i & mask) * ell) + (j & mask)) * ell + (k & mask);
+        const int64_t key = (int64_t)leaf * ((int64_t)ell * ell * ell) + local;
+        perm[key] = (int32_t)g;
+    }
+}
+
+// q[p] = I[perm[p]] (FP32 or FP64 in, same type out)
+template <typename T>
+__global__ void permute_in_kernel(const T *__restrict__ I, const int32_t *__restrict__ perm,
+                                  int64_t N, T *__restrict__ q) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x)
+        q[p] = I[perm[p]];
+}
+
+// S[perm[p]] = scale * Sp[p]
+template <typename T>
+__global__ void permute_out_kernel(const T *__restrict__ Sp, const int32_t *__restrict__ perm,
+                                   int64_t N, T scale, T *__restrict__ S) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x)
+        S[perm[p]] = Sp[p] * scale;
+}
+
+__global__ void perm_to_i64_kernel(const int32_t *perm, int64_t N, int64_t *out) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x)
+        out[p] = perm[p];
+}
+
+unsigned grid_for(int64_t N) {
+    int64_t b = (N + 255) / 256;
+    return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+}  // namespace
+
+int launch_morton_scatter(const Tree &t, hipStream_t st) {
+    int lg = 0;
+    while ((1 << lg) < t.ell) ++lg;
+    hipLaunchKernelGGL(morton_scatter_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.n, t.ell,
+                       lg, t.N, t.perm);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+template <typename T>
+int launch_permute_in(const Tree &t, const T *I, T *q, hipStream_t st) {
+    hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.perm,
+                       t.N, q);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+template <typename T>
+int launch_permute_out(const Tree &t, const T *Sp, T scale, T *S, hipStream_t st) {
+    hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, t.perm,
+                       t.N, scale, S);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int launch_perm_i64(const Tree &t, int64_t *out, hipStream_t st) {
+    hipLaunchKernelGGL(perm_to_i64_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.perm, t.N,
+                       out);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+template int launch_permute_in<float>(const Tree &, const float *, float *, hipStream_t);
+template int launch_permute_in<double>(const Tree &, const double *, double *, hipStream_t);
+template int launch_permute_out<float>(const Tree &, const float *, float, float *, hipStream_t);
+template int launch_permute_out<double>(const Tree &, const double *, double, double *,
+                                        hipStream_t);
+
+}  // namespace kifmm

@@ -1,0 +1,76 @@
+"""direct_eval (HIP) against the FP64 oracle (Section 3, eq. (summation))."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as odirect
+from paper_2006_03515_amd import workloads
+from tests.gpu_common import gauss, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2006_03515_amd import kifmm
+    return kifmm
+
+
+def _run(K, I, h, p_o2, tg=None, fp64=True, prefactor=1.0):
+    grid = K.Grid(I.shape, h)
+    It = torch.tensor(np.ascontiguousarray(I, dtype=np.float32), device="cuda").reshape(-1)
+    tgt = None if tg is None else torch.tensor(tg, dtype=torch.int64, device="cuda")
+    out = K.direct_eval(grid, K.Kernel(p_o2), It, prefactor, tgt, fp64=fp64)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("p_o2", [150.0, 19.74, 1.974])
+def test_direct_fp64_sampled_targets(K, p_o2):
+    n, L = 32, 0.1
+    I = gauss(n, L).astype(np.float32).astype(np.float64)   # same input both sides
+    h = (L / n,) * 3
+    tg = workloads.sample_targets(n ** 3, 256, seed=11)
+    ref = odirect.direct_targets(I, h, p_o2, tg, prefactor=0.5)
+    got = _run(K, I, h, p_o2, tg, fp64=True, prefactor=0.5)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+def test_direct_fp32_kernel_within_1e6(K):
+    n, L = 32, 0.1
+    I = gauss(n, L).astype(np.float32).astype(np.float64)
+    h = (L / n,) * 3
+    tg = workloads.sample_targets(n ** 3, 256, seed=12)
+    ref = odirect.direct_targets(I, h, 150.0, tg)
+    got = _run(K, I, h, 150.0, tg, fp64=False)
+    assert np.max(np.abs(got / ref - 1)) < 1e-6
+
+
+def test_direct_all_targets_ragged_anisotropic(K):
+    rng = np.random.default_rng(7)
+    I = rng.random((7, 5, 9)).astype(np.float32).astype(np.float64)
+    h = (2e-3, 1e-3, 1.5e-3)
+    ref = odirect.direct_numpy(I, h, 19.74)
+    got = _run(K, I, h, 19.74, None, fp64=True)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+def test_direct_wide_rows(K):
+    # nz larger than the 256-thread row split, odd sizes
+    rng = np.random.default_rng(8)
+    I = rng.random((3, 2, 300)).astype(np.float32).astype(np.float64)
+    h = (1e-3, 1e-3, 1e-3)
+    tg = np.array([0, 5, 299, 1799, 900], dtype=np.int64)
+    ref = odirect.direct_targets(I, h, 150.0, tg)
+    np.testing.assert_allclose(_run(K, I, h, 150.0, tg), ref, rtol=1e-12)
+
+
+def test_direct_empty_targets_and_repeatable(K):
+    n, L = 16, 0.1
+    I = gauss(n, L)
+    h = (L / n,) * 3
+    assert _run(K, I, h, 150.0, np.zeros(0, dtype=np.int64)).size == 0
+    tg = workloads.sample_targets(n ** 3, 64, seed=3)
+    a = _run(K, I, h, 150.0, tg, fp64=False)
+    b = _run(K, I, h, 150.0, tg, fp64=False)
+    assert np.array_equal(a, b)

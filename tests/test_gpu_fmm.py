@@ -1,0 +1,122 @@
+"""kifmm_eval (HIP) against the oracle: the exact discrete sum (direct / FFT)
+and the plain FP64 KIFMM of Section 3."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as odirect
+from oracle import kifmm_ref
+from tests.gpu_common import gauss, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+LAY = {"paper": 0, "single": 1, "nested": 2}
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2006_03515_amd import kifmm
+    return kifmm
+
+
+def fmm(K, I, L, p_o2, max_leaf, layout="single", rcond=1e-7, precision="fp32", m0=6,
+        check_edge=10, prefactor=1.0, ops_out=None):
+    n = I.shape[0]
+    grid = K.Grid.cube(n, L)
+    tree = K.build_tree(grid, max_leaf)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(LAY[layout], m0, check_edge, rcond))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    It = torch.tensor(np.ascontiguousarray(I), dtype=dt, device="cuda").reshape(-1)
+    S = K.eval(tree, ops, It, prefactor, precision=precision)
+    torch.cuda.synchronize()
+    if ops_out is not None:
+        ops_out.append((tree, ops))
+    return S.cpu().numpy().reshape(I.shape).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def g32():
+    n, L = 32, 0.1
+    I = gauss(n, L).astype(np.float32).astype(np.float64)
+    return I, L, {p: odirect.fft_full(I, (L / n,) * 3, p) for p in (150.0, 1.974)}
+
+
+def test_depth_one_is_direct(K):
+    n, L = 16, 0.1
+    I = gauss(n, L).astype(np.float32).astype(np.float64)
+    ref = odirect.fft_full(I, (L / n,) * 3, 150.0)
+    assert rel_l2(fmm(K, I, L, 150.0, 512, precision="fp64"), ref) < 1e-13
+    assert rel_l2(fmm(K, I, L, 150.0, 512, precision="fp32"), ref) < 1e-6
+
+
+@pytest.mark.parametrize("layout,rcond", [("single", 1e-7), ("nested", 1e-10), ("paper", 1e-7)])
+def test_fp64_matches_oracle_fmm(K, g32, layout, rcond):
+    I, L, refs = g32
+    got = fmm(K, I, L, 150.0, 64, layout=layout, rcond=rcond, precision="fp64")
+    ora = kifmm_ref.evaluate(I, L, 150.0, ell=4, layout=layout, rcond=rcond)
+    e_ora = rel_l2(ora, refs[150.0])
+    e_got = rel_l2(got, refs[150.0])
+    assert rel_l2(got, ora) < max(1e-8, 0.05 * e_ora)
+    assert e_got < 1.05 * e_ora + 1e-9
+
+
+@pytest.mark.parametrize("p_o2", [150.0, 1.974])
+def test_fp32_nested_within_1e6_of_direct(K, g32, p_o2):
+    I, L, refs = g32
+    got = fmm(K, I, L, p_o2, 64, layout="nested", rcond=1e-10, precision="fp32")
+    assert rel_l2(got, refs[p_o2]) < 1e-6
+
+
+def test_fp32_is_fp64_up_to_rounding(K, g32):
+    I, L, _ = g32
+    a = fmm(K, I, L, 19.74, 64, layout="single", precision="fp32")
+    b = fmm(K, I, L, 19.74, 64, layout="single", precision="fp64")
+    assert rel_l2(a, b) < 1e-6
+
+
+@pytest.mark.parametrize("precision,tol_direct,tol_fp32", [("m2l_bf16", 1e-3, 1e-3), ("m2l_fp16", 1e-4, 1e-4)])
+def test_low_precision_m2l(K, g32, precision, tol_direct, tol_fp32, record_property):
+    # nested layout: truncation ~2e-7, so the error measured is the M2L rounding
+    I, L, refs = g32
+    lo = fmm(K, I, L, 150.0, 64, layout="nested", rcond=1e-10, precision=precision)
+    hi = fmm(K, I, L, 150.0, 64, layout="nested", rcond=1e-10, precision="fp32")
+    e_d, e_f = rel_l2(lo, refs[150.0]), rel_l2(lo, hi)
+    record_property("rel_l2_vs_direct", e_d)
+    print("%s: rel-L2 vs direct %.3e, vs fp32 FMM %.3e" % (precision, e_d, e_f))
+    assert e_d < tol_direct
+    assert e_f < tol_fp32
+
+
+def test_ranks_match_numpy_svd(K):
+    n, L, p_o2 = 32, 0.1, 19.74
+    from oracle import kernel as ok
+    keep = []
+    I = gauss(n, L)
+    fmm(K, I, L, p_o2, 64, layout="single", rcond=1e-7, precision="fp32", ops_out=keep)
+    tree, ops = keep[0]
+    for lev in range(2, tree.depth + 1):
+        r = L / 2 ** (lev + 1)
+        yu, xu, yd, xd = kifmm_ref.point_sets("single", 6, 10, r)
+        su = np.linalg.svd(kifmm_ref.gmat(xu, yu, p_o2), compute_uv=False)
+        sd = np.linalg.svd(kifmm_ref.gmat(xd, yd, p_o2), compute_uv=False)
+        ku, kd = ops.rank(lev)
+        assert abs(ku - int((su > 1e-7 * su[0]).sum())) <= 1
+        assert abs(kd - int((sd > 1e-7 * sd[0]).sum())) <= 1
+
+
+def test_linearity_and_mismatch(K):
+    n, L = 32, 0.1
+    rng = np.random.default_rng(1)
+    u = rng.random((n, n, n))
+    v = rng.random((n, n, n))
+    keep = []
+    su = fmm(K, u, L, 150.0, 64, precision="fp64", ops_out=keep)
+    sv = fmm(K, v, L, 150.0, 64, precision="fp64")
+    suv = fmm(K, u + 2 * v, L, 150.0, 64, precision="fp64")
+    assert rel_l2(suv, su + 2 * sv) < 1e-12
+    tree, ops = keep[0]
+    other = K.build_tree(K.Grid.cube(n, L), 64)
+    x = torch.zeros(n ** 3, dtype=torch.float32, device="cuda")
+    with pytest.raises(K.KifmmError) as e:
+        K.eval(other, ops, x, 1.0)
+    assert e.value.code == K.EMISMATCH
