@@ -98,8 +98,17 @@ typedef struct {
  *   KIFMM_FP32      : all passes in FP32 (FP32 MFMA); float* I/O.
  *   KIFMM_M2L_BF16  : as FP32 but the M2L translations take bfloat16 operands
  *                     (FP32 accumulate); float* I/O.
- *   KIFMM_M2L_FP16  : as FP32 but M2L in FP16 operands with per-level scaling. */
-enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_M2L_BF16 = 2, KIFMM_M2L_FP16 = 3 };
+ *   KIFMM_M2L_FP16  : as FP32 but M2L in FP16 operands; operators and inputs
+ *                     are scaled by their maximum magnitude per level.
+ *   KIFMM_M2L_BF16X3: as FP32 but M2L in split bfloat16: each operand is the sum
+ *                     of two bfloat16 numbers (high part + rounding residual)
+ *                     and three bfloat16 products are accumulated in FP32
+ *                     (about 16 significant bits per operand).
+ *   KIFMM_BF16X3    : the near field (P2P) and M2L both in split bfloat16; the
+ *                     near-range matrices, self cell included, are computed in
+ *                     FP64 and then split.  Other passes FP32. */
+enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_M2L_BF16 = 2, KIFMM_M2L_FP16 = 3, KIFMM_M2L_BF16X3 = 4,
+       KIFMM_BF16X3 = 5 };
 
 typedef struct kifmm_tree_s *kifmm_tree;
 typedef struct kifmm_ops_s *kifmm_ops;
@@ -134,7 +143,10 @@ int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
  * every cell i.  I_dev and S_dev hold nx*ny*nz values, double for KIFMM_FP64 and
  * float otherwise, in grid order; they must not overlap.  `ops` must come from
  * `tree` (else KIFMM_EMISMATCH).  Uses the work buffers owned by `ops`, so
- * calls sharing one ops object must be ordered on one stream. */
+ * calls sharing one ops object must be ordered on one stream.  The near field
+ * runs on a second stream owned by `ops`, forked from and joined back into
+ * `stream` with events; when the call returns, all its work is ordered on
+ * `stream`. */
 int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor,
                void *S_dev, int32_t precision, void *stream);
 

@@ -45,6 +45,9 @@ int launch_gemm_f64(int, int, int, const double *, int, int64_t, const double *,
 template <typename T>
 int launch_cast_pad(const double *, int, int, int64_t, T *, int, int, int64_t, int, double,
                     hipStream_t);
+int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, int64_t, int, double,
+                       hipStream_t);
+template <typename T> int launch_permute_out2(const Tree &, const T *, const T *, T, T *, hipStream_t);
 
 static std::atomic<uint64_t> g_magic{0x6b69666d6d000001ull};
 
@@ -151,16 +154,24 @@ struct kifmm_ops_s {
           *p2p32 = nullptr;
     double *p2m64 = nullptr, *m2m64 = nullptr, *m2l64 = nullptr, *l2l64 = nullptr,
            *l2p64 = nullptr, *p2p64 = nullptr;
-    __bf16 *m2lbf = nullptr;
+    __bf16 *m2lbf = nullptr, *m2lbf_lo = nullptr;   // split BF16: high and low parts
+    __bf16 *p2pbf = nullptr, *p2pbf_lo = nullptr;
+    float p2p_scale = 1.0f;            // max |near-range matrix entry| (split BF16 storage divisor)
+    float *amax_q = nullptr;           // partial maxima of |q| (split BF16 near field)
     _Float16 *m2lh = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
     TapList t_single{}, t_m2m{}, t_l2l{}, t_m2l{}, t_p2p{};
     // work buffers (sized for FP64)
-    double *q = nullptr, *Sp = nullptr;
+    double *q = nullptr, *Sp = nullptr, *SpN = nullptr;   // leaf-ordered sources, far / near field
     std::vector<double *> cu, cd;
     float *amax = nullptr;
     int n_amax = 256;
+    float *part = nullptr;             // tap-group partial sums of the M2L launches
+    int64_t part_capacity = 0;         // floats
+    // the near field runs on a second stream, joined by events
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // per-pass timing (kifmm_profile_enable)
     bool prof = false;
     std::vector<hipEvent_t> ev;        // pool of events, recorded in pairs
@@ -211,15 +222,20 @@ struct PassTimer {
 static void free_ops(kifmm_ops o) {
     if (!o) return;
     clear_profile(o);
+    if (o->side) (void)hipStreamSynchronize(o->side);
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
-                    o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lh,
-                    o->taps,  o->q,     o->Sp,    o->amax};
+                    o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
+                    o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
+                    o->p2pbf, o->p2pbf_lo, o->amax_q};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
         if (p) (void)hipFree(p);
     for (double *p : o->cd)
         if (p) (void)hipFree(p);
+    if (o->fork) (void)hipEventDestroy(o->fork);
+    if (o->join) (void)hipEventDestroy(o->join);
+    if (o->side) (void)hipStreamDestroy(o->side);
     delete o;
 }
 
@@ -515,6 +531,17 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(dmalloc(&o->p2p32, (size_t)27 * s * s));
     KIFMM_TRY(dmalloc(&o->p2p64, (size_t)27 * s * s));
     KIFMM_TRY(store_both(p2p, s, s, 27, o->p2p32, o->p2p64, s, s, st));
+    {
+        double mx;
+        KIFMM_TRY(max_abs_host(p2p, (size_t)27 * s * s, &mx, st));
+        if (!(mx > 0)) mx = 1.0;
+        o->p2p_scale = (float)mx;
+        KIFMM_TRY(dmalloc(&o->p2pbf, (size_t)27 * s * s));
+        KIFMM_TRY(dmalloc(&o->p2pbf_lo, (size_t)27 * s * s));
+        KIFMM_TRY(store<__bf16>(p2p, s, s, 27, o->p2pbf, s, s, 1.0 / mx, st));
+        KIFMM_TRY(launch_cast_pad_lo(p2p, s, s, (int64_t)s * s, o->p2pbf_lo, s, s, (int64_t)s * s, 27,
+                                     1.0 / mx, st));
+    }
 
     // tap tables
     std::vector<int> taps;
@@ -574,7 +601,12 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     // work buffers
     KIFMM_TRY(dmalloc(&o->q, (size_t)tree->N));
     KIFMM_TRY(dmalloc(&o->Sp, (size_t)tree->N));
+    KIFMM_TRY(dmalloc(&o->SpN, (size_t)tree->N));
+    KIFMM_HIP(hipStreamCreateWithFlags(&o->side, hipStreamNonBlocking));
+    KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
+    KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
+    KIFMM_TRY(dmalloc(&o->amax_q, (size_t)o->n_amax));
     o->cu.assign(D + 1, nullptr);
     o->cd.assign(D + 1, nullptr);
     if (D < 2) {
@@ -695,6 +727,7 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(dmalloc(&o->m2l32, (size_t)(D - 1) * per));
         KIFMM_TRY(dmalloc(&o->m2l64, (size_t)(D - 1) * per));
         KIFMM_TRY(dmalloc(&o->m2lbf, (size_t)(D - 1) * per));
+        KIFMM_TRY(dmalloc(&o->m2lbf_lo, (size_t)(D - 1) * per));
         KIFMM_TRY(dmalloc(&o->m2lh, (size_t)(D - 1) * per));
         o->m2l_scale.assign(D + 1, 1.0f);
         double *G, *T1, *tmp, *sh;
@@ -722,6 +755,8 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             if (!(mx > 0)) mx = 1.0;
             o->m2l_scale[l] = (float)mx;
             KIFMM_TRY(store<__bf16>(tmp, kd, ku, n316, o->m2lbf + so, KD, KU, 1.0 / mx, st));
+            KIFMM_TRY(launch_cast_pad_lo(tmp, kd, ku, (int64_t)kd * ku, o->m2lbf_lo + so, KD, KU,
+                                         (int64_t)KD * KU, n316, 1.0 / mx, st));
             KIFMM_TRY(store<_Float16>(tmp, kd, ku, n316, o->m2lh + so, KD, KU, 1.0 / mx, st));
         }
     }
@@ -730,6 +765,17 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(dmalloc(&o->cu[l], nbx * KU));
         KIFMM_TRY(dmalloc(&o->cd[l], nbx * KD));
     }
+    // scratch for the tap-group split of the M2L launches: up to 64 M floats
+    // (the launcher uses fewer groups when a split would not fit)
+    int64_t need = 0;
+    for (int l = 2; l <= D; ++l) {
+        const int64_t nbx = (int64_t)1 << (3 * l);
+        const int64_t base = ((nbx / 8 + 63) / 64) * ((KD + 127) / 128) * 8;
+        int64_t g = std::min<int64_t>(o->t_m2l.ntaps, (2048 + base - 1) / base);
+        need = std::max(need, g * nbx * KD);
+    }
+    o->part_capacity = std::min<int64_t>(need, (int64_t)64 << 20);
+    KIFMM_TRY(dmalloc(&o->part, (size_t)o->part_capacity));
     KIFMM_HIP(hipStreamSynchronize(st));
     return KIFMM_OK;
 }
@@ -740,12 +786,15 @@ TapArgs<TA, T, T> tap(const TA *A, int64_t a_stride, int M, int K, const T *in, 
                       int64_t out_ld, int mode, int nl, const TapList &tl, int cls_stride,
                       int64_t n_per_class, int accumulate) {
     TapArgs<TA, T, T> p{};
-    p.A = A; p.a_stride = a_stride; p.M = M; p.K = K;
+    p.A = A; p.A2 = nullptr; p.a_stride = a_stride; p.M = M; p.K = K;
     p.in = in; p.in_ld = in_ld; p.out = out; p.out_ld = out_ld;
     p.mode = mode; p.nl = nl; p.nclass = tl.nclass; p.cls_stride = cls_stride;
-    p.n_per_class = n_per_class; p.tap_op = tl.op_dev; p.tap_off = tl.off_dev; p.ntaps = tl.ntaps;
+    p.n_per_class = n_per_class; p.n_boxes = n_per_class * tl.nclass;
+    p.tap_op = tl.op_dev; p.tap_off = tl.off_dev; p.ntaps = tl.ntaps;
     p.accumulate = accumulate;
+    p.part = nullptr; p.part_capacity = 0; p.groups = 1;
     p.amax = nullptr; p.n_amax = 0; p.op_scale = 1.0f;
+    p.pass = PASS_GENERIC;
     return p;
 }
 
@@ -757,81 +806,136 @@ struct OpSet {
     const T *p2m, *m2m, *m2l, *l2l, *l2p, *p2p;
 };
 
+// M2L of one level (eq. (m2l)) into cd[l], in the requested arithmetic
+template <typename T>
+int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, hipStream_t st) {
+    const int KU = o->KU, KD = o->KD;
+    const int64_t nper = (int64_t)1 << (3 * (l - 1));
+    const size_t per = (size_t)316 * KD * KU;
+    const size_t so = (size_t)(l - 2) * per;
+    if constexpr (sizeof(T) == 4) {
+        if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16X3 ||
+            precision == KIFMM_BF16X3) {
+            const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
+            KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
+            const int64_t ldA = (int64_t)KD * KU;
+            if (precision == KIFMM_M2L_FP16) {
+                auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
+                                              (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
+                p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+                p.part = o->part; p.part_capacity = o->part_capacity;
+                p.pass = PASS_M2L;
+                return run_tap_lp<_Float16>(p, false, st);
+            }
+            auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
+                                        (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
+            p.A2 = o->m2lbf_lo + so;
+            p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+            p.part = o->part; p.part_capacity = o->part_capacity;
+            p.pass = PASS_M2L;
+            return run_tap_lp<__bf16>(p, precision == KIFMM_M2L_BF16X3 || precision == KIFMM_BF16X3, st);
+        }
+    }
+    auto p = tap<T, T>(ops.m2l + so, (int64_t)KD * KU, KD, KU, (T *)o->cu[l], KU, (T *)o->cd[l], KD, SRC_NBR,
+                       1 << l, o->t_m2l, 8, nper, acc);
+    if constexpr (sizeof(T) == 4) {
+        p.part = o->part;
+        p.part_capacity = o->part_capacity;
+    }
+    p.pass = PASS_M2L;
+    return run(p, st);
+}
+
+// near field (eq. (nearfar), direct part, with the self cell) of every leaf into out
+template <typename T>
+int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision, hipStream_t st) {
+    const int s = o->s, nb = o->nb;
+    const int64_t nleaf = (int64_t)nb * nb * nb;
+    if constexpr (sizeof(T) == 4) {
+        if (precision == KIFMM_BF16X3) {
+            KIFMM_TRY(run_amax((const float *)q, nleaf * s, o->amax_q, o->n_amax, st));
+            auto p = tap<__bf16, float>(o->p2pbf, (int64_t)s * s, s, s, (const float *)q, s, (float *)out, s,
+                                        SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
+            p.A2 = o->p2pbf_lo;
+            p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
+            p.pass = PASS_P2P;
+            return run_tap_lp<__bf16>(p, true, st);
+        }
+    }
+    auto p = tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, out, s, SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
+    p.pass = PASS_P2P;
+    return run(p, st);
+}
+
+// Schedule (Section 3, algorithm outline):
+//   stream st : permute in -> [fork] -> P2M -> M2M (l = D-1..2) -> for l = 2..D:
+//               L2L (l > 2) then M2L -> L2P -> [wait join] -> permute out (far + near)
+//   side      : [wait fork] -> P2P with the self cell -> [join]
 template <typename T>
 int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, int precision,
                hipStream_t st) {
     OpSet<T> ops;
     if constexpr (sizeof(T) == 8) ops = {o->p2m64, o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64};
     else ops = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32};
-    T *q = (T *)o->q, *Sp = (T *)o->Sp;
+    T *q = (T *)o->q, *Sp = (T *)o->Sp, *SpN = (T *)o->SpN;
     const int D = o->D, s = o->s, nb = o->nb, KU = o->KU, KD = o->KD;
     const int64_t nleaf = (int64_t)nb * nb * nb;
+    const T scale = (T)(prefactor * t->h * t->h * t->h);
     {
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, q, st));
     }
-    if (D >= 2) {
-        T *cuD = (T *)o->cu[D];
+    if (D < 2) {   // every leaf is in every other leaf's near range
         {
-            PassTimer pt(o, KIFMM_PASS_P2M, st);
-            KIFMM_TRY(run(tap<T, T>(ops.p2m, 0, KU, s, q, s, cuD, KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0), st));
+            PassTimer pt(o, KIFMM_PASS_P2P, st);
+            KIFMM_TRY(p2p_pass<T>(o, ops, q, Sp, precision, st));
         }
-        for (int l = D - 1; l >= 2; --l) {
-            const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
-            PassTimer pt(o, KIFMM_PASS_M2M, st);
-            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU,
-                                 SRC_CHILD, 0, o->t_m2m, 1, (int64_t)1 << (3 * l), 0), st));
+        PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
+        return launch_permute_out<T>(*t, Sp, scale, S, st);
+    }
+    // near field on the side stream
+    KIFMM_HIP(hipEventRecord(o->fork, st));
+    KIFMM_HIP(hipStreamWaitEvent(o->side, o->fork, 0));
+    {
+        PassTimer pt(o, KIFMM_PASS_P2P, o->side);
+        KIFMM_TRY(p2p_pass<T>(o, ops, q, SpN, precision, o->side));
+    }
+    KIFMM_HIP(hipEventRecord(o->join, o->side));
+    // far field: upward pass, downward pass, local expansion at the cells
+    {
+        PassTimer pt(o, KIFMM_PASS_P2M, st);
+        KIFMM_TRY(run(tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1,
+                                nleaf, 0), st));
+    }
+    for (int l = D - 1; l >= 2; --l) {
+        const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
+        PassTimer pt(o, KIFMM_PASS_M2M, st);
+        auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
+                           o->t_m2m, 1, (int64_t)1 << (3 * l), 0);
+        if constexpr (sizeof(T) == 4) {
+            p.part = o->part;
+            p.part_capacity = o->part_capacity;
         }
-        const size_t per = (size_t)316 * KD * KU;
-        for (int l = 2; l <= D; ++l) {
-            const int64_t nper = (int64_t)1 << (3 * (l - 1));
-            if (l > 2) {
-                const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
-                PassTimer pt(o, KIFMM_PASS_L2L, st);
-                KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD,
-                                     SRC_PARENT, 0, o->t_l2l, 8, nper, 0), st));
-            }
-            const int acc = l > 2 ? 1 : 0;
-            PassTimer pt(o, KIFMM_PASS_M2L, st);
-            if constexpr (sizeof(T) == 4) {
-                if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16) {
-                    const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
-                    KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
-                    const size_t so = (size_t)(l - 2) * per;
-                    const int64_t ldA = (int64_t)KD * KU;
-                    if (precision == KIFMM_M2L_BF16) {
-                        auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
-                                                    (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8,
-                                                    nper, acc);
-                        p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
-                        KIFMM_TRY(run_tap_lp<__bf16>(p, st));
-                    } else {
-                        auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
-                                                      (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8,
-                                                      nper, acc);
-                        p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
-                        KIFMM_TRY(run_tap_lp<_Float16>(p, st));
-                    }
-                    continue;
-                }
-            }
-            const T *A = ops.m2l + (size_t)(l - 2) * per;
-            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KU, KD, KU, (T *)o->cu[l], KU, (T *)o->cd[l], KD, SRC_NBR,
-                                 1 << l, o->t_m2l, 8, nper, acc), st));
+        KIFMM_TRY(run(p, st));
+    }
+    for (int l = 2; l <= D; ++l) {
+        if (l > 2) {
+            const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
+            PassTimer pt(o, KIFMM_PASS_L2L, st);
+            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD,
+                                    SRC_PARENT, 0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), 0), st));
         }
-        PassTimer pt(o, KIFMM_PASS_L2P, st);
-        KIFMM_TRY(run(tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1,
-                             nleaf, 0), st));
+        PassTimer pt(o, KIFMM_PASS_M2L, st);
+        KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > 2 ? 1 : 0, st));
     }
     {
-        PassTimer pt(o, KIFMM_PASS_P2P, st);
-        KIFMM_TRY(run(tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, Sp, s, SRC_NBR, nb, o->t_p2p, 1, nleaf,
-                         D >= 2 ? 1 : 0), st));
+        PassTimer pt(o, KIFMM_PASS_L2P, st);
+        KIFMM_TRY(run(tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1,
+                                nleaf, 0), st));
     }
-    const T scale = (T)(prefactor * t->h * t->h * t->h);
+    KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
     PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
-    KIFMM_TRY(launch_permute_out<T>(*t, Sp, scale, S, st));
-    return KIFMM_OK;
+    return launch_permute_out2<T>(*t, Sp, SpN, scale, S, st);
 }
 
 }  // namespace
@@ -905,7 +1009,7 @@ int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefact
     if (ops->tree_magic != tree->magic) return fail(KIFMM_EMISMATCH, "ops were built for another tree");
     if (!I_dev || !S_dev) return fail(KIFMM_EINVAL, "I_dev and S_dev must be non-NULL");
     if (!std::isfinite(prefactor)) return fail(KIFMM_EINVAL, "prefactor must be finite");
-    if (precision < KIFMM_FP64 || precision > KIFMM_M2L_FP16) return fail(KIFMM_EINVAL, "unknown precision");
+    if (precision < KIFMM_FP64 || precision > KIFMM_BF16X3) return fail(KIFMM_EINVAL, "unknown precision");
     const size_t esz = precision == KIFMM_FP64 ? 8 : 4;
     const char *ib = (const char *)I_dev, *sb = (const char *)S_dev;
     const size_t bytes = (size_t)tree->N * esz;

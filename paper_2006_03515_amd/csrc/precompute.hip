@@ -223,6 +223,20 @@ __global__ void cast_pad(const double *__restrict__ src, int M, int K, int64_t s
     }
 }
 
+// low part of a split-BF16 operand: dst = bf16(v - float(bf16(v))), v = scale * src
+__global__ void cast_pad_lo(const double *__restrict__ src, int M, int K, int64_t sS,
+                            __bf16 *__restrict__ dst, int Mp, int Kp, int64_t sD, double scale) {
+    const int b = blockIdx.y;
+    const int64_t total = (int64_t)Mp * Kp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / Kp), j = (int)(e % Kp);
+        const double v = (i < M && j < K) ? src[b * sS + (int64_t)i * K + j] * scale : 0.0;
+        const float hi = (float)(__bf16)(float)v;
+        dst[b * sD + e] = (__bf16)(float)(v - (double)hi);
+    }
+}
+
 unsigned blocks_for(int64_t total) {
     int64_t b = (total + 255) / 256;
     return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -305,6 +319,14 @@ int launch_cast_pad(const double *src, int M, int K, int64_t sS, T *dst, int Mp,
                     int64_t sD, int batch, double scale, hipStream_t st) {
     hipLaunchKernelGGL(cast_pad<T>, dim3(blocks_for((int64_t)Mp * Kp), batch), dim3(256), 0, st,
                        src, M, K, sS, dst, Mp, Kp, sD, scale);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int launch_cast_pad_lo(const double *src, int M, int K, int64_t sS, __bf16 *dst, int Mp, int Kp,
+                       int64_t sD, int batch, double scale, hipStream_t st) {
+    hipLaunchKernelGGL(cast_pad_lo, dim3(blocks_for((int64_t)Mp * Kp), batch), dim3(256), 0, st, src, M,
+                       K, sS, dst, Mp, Kp, sD, scale);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }

@@ -7,6 +7,7 @@ namespace kifmm {
 template <typename TA, typename TI, typename TO>
 struct TapArgs {
     const TA *A;          // operators, op i at A + i * a_stride, row-major M x K
+    const TA *A2;         // split-BF16: low parts of A (same layout), else unused
     int64_t a_stride;
     int M, K;             // padded rows / columns
     const TI *in;         // in[src * in_ld + k]
@@ -15,23 +16,31 @@ struct TapArgs {
     int64_t out_ld;
     int mode;             // SrcMode
     int nl;               // boxes per axis of the source level (SRC_NBR)
-    int nclass;           // gridDim.z
+    int nclass;           // number of output classes
     int cls_stride;       // output box = cls_stride * j + class
     int64_t n_per_class;
+    int64_t n_boxes;      // nclass * n_per_class (size of the output in boxes)
     const int *tap_op;    // [nclass][ntaps]
     const int *tap_off;   // [nclass][ntaps]
     int ntaps;
     int accumulate;       // 0: out = sum, 1: out += sum
+    float *part;          // scratch for tap-group partial sums (may be null: no split)
+    int64_t part_capacity;// floats available at part
+    int groups;           // set by the launcher
     const float *amax;    // low precision: partial maxima of |in|
     int n_amax;
     float op_scale;       // low precision: A was stored divided by op_scale
+    int pass;             // PASS_* below: selects a separately named kernel instance
 };
 
+// Kernel instances are compiled once per pass kind so that profilers report the
+// near field and the M2L translations under their own names.
+enum { PASS_GENERIC = 0, PASS_P2P = 1, PASS_M2L = 2 };
+
 int run_tap_f32(const TapArgs<float, float, float> &p, hipStream_t st);
-int run_tap_f32_valu(const TapArgs<float, float, float> &p, hipStream_t st);
 int run_tap_f64(const TapArgs<double, double, double> &p, hipStream_t st);
 template <typename TL>
-int run_tap_lp(const TapArgs<TL, float, float> &p, hipStream_t st);
+int run_tap_lp(const TapArgs<TL, float, float> &p, bool x3, hipStream_t st);
 int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st);
 
 }  // namespace kifmm

@@ -12,12 +12,28 @@
 //   P2P         class 0, 27 taps,  src = neighbour leaf, A = near-range matrix
 // Boxes outside the grid contribute nothing (their src is -1 and loads zeros).
 //
+// Work split: a workgroup owns an output tile (BM rows x 64 boxes of one class)
+// and a group of taps.  When the tap list is split over G groups (to put enough
+// workgroups on the 256 CUs at coarse levels) each group writes an FP32 partial
+// sum to scratch and reduce_partials adds the groups in a fixed order in FP64,
+// so results do not depend on scheduling.
+//
 // Kernels:
-//   tapgemm_mfma_f32   FP32 on MFMA (v_mfma_f32_16x16x4f32), 64 x 64 output tile
-//   tapgemm_mfma_lp    BF16 / FP16 operands (v_mfma_f32_16x16x32_{bf16,f16}),
-//                      FP32 accumulate; the input vectors are scaled by a
-//                      device-side factor and rounded to nearest-even on load
-//   tapgemm_valu<T>    LDS-tiled VALU version for FP64 (and any T)
+//   tapgemm_f32<BM>   FP32 on MFMA (v_mfma_f32_16x16x4f32)
+//   tapgemm_lp<TL,X3> BF16 or FP16 operands on v_mfma_f32_16x16x32_{bf16,f16}
+//                     with FP32 accumulation; inputs scaled by 1/max|in| and
+//                     rounded to nearest-even when staged.  X3: split BF16 --
+//                     A = A_hi + A_lo and B = B_hi + B_lo, three products
+//                     A_hi B_hi + A_hi B_lo + A_lo B_hi (about 16 mantissa bits)
+//   tapgemm_valu<T>   LDS-tiled VALU version for FP64 (and any T)
+//
+// Inside a 32-wide K chunk the reduction index is permuted so that lane group
+// q = lane / 16 owns k = 8q .. 8q+7: one 16-byte LDS read then feeds several
+// MFMA steps (the products are summed in any order, so A and B only have to use
+// the same permutation).  MFMA partial sums are folded into FP64 totals after
+// every chunk (8 chained FP32 steps), so long near-field and M2L sums keep the
+// rounding of one short chain.  The next chunk's global loads are issued before
+// the current chunk's MFMAs (register prefetch).
 #include "common.h"
 #include "tapgemm.h"
 
@@ -48,203 +64,306 @@ __device__ inline int64_t source_box(int mode, int64_t b, int off, int nl) {
     }
 }
 
-constexpr int BM = 64, BN = 64, BK = 16, PADK = 4;
-constexpr int kFoldK = 32;
+constexpr int BN = 64;     // boxes per tile
+constexpr int BK = 32;     // reduction chunk
+constexpr int APAD = 4;    // LDS row padding (floats)
 
-__global__ __launch_bounds__(256) void tapgemm_mfma_f32(TapArgs<float, float, float> p) {
-    __shared__ float As[BM][BK + PADK];
-    __shared__ float Bs[BN][BK + PADK];
-    __shared__ int64_t srcs[BN];
-    const int cls = blockIdx.z;
+__device__ inline float comp(const float4 &v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+template <int BM, int PASS>
+__global__ __launch_bounds__(256) void tapgemm_f32(TapArgs<float, float, float> p) {
+    constexpr int IM = BM / 32;          // 16-row blocks per wave (waves: 2 x 2)
+    constexpr int JN = 2;                // 16-box blocks per wave
+    constexpr int AR = BM / 32;          // float4 loads of A per thread per chunk
+    __shared__ float As[BM][BK + APAD];
+    __shared__ float Bs[BN][BK + APAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = p.groups;
+    const int cls = blockIdx.z / G, grp = blockIdx.z % G;
+    const int tpg = (p.ntaps + G - 1) / G;
+    const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
     const int64_t j0 = (int64_t)blockIdx.x * BN;
     const int m0 = blockIdx.y * BM;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    // MFMA partial sums run over at most kFoldK reduction elements (kFoldK / 4
-    // chained FP32 steps) before they are added into FP64 totals, which keeps
-    // the rounding of long near-field and M2L sums at the level of one short chain.
-    floatx4 acc[2][2];
-    double tot[2][2][4];
+    const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
+    const int KC = p.K / BK;
+    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
+
+    floatx4 acc[IM][JN];
+    double tot[IM][JN][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < JN; ++j) {
             acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) tot[i][j][v] = 0.0;
         }
-    auto fold = [&]() {
+
+    // loader: rows r*32 + tid/8, k = (tid%8)*4 .. +3 of the chunk
+    const int lrow = tid >> 3, lk = (tid & 7) * 4;
+    float4 ra[AR], rb[2];
+    int64_t lsrc[2] = {-1, -1};
+    const float *Aop = p.A;
+    auto load = [&](int it) {
+        const int t = t0 + it / KC, kc = it % KC;
+        if (kc == 0) {
+            const int op = p.tap_op[cls * p.ntaps + t];
+            const int off = p.tap_off[cls * p.ntaps + t];
+            Aop = p.A + (int64_t)op * p.a_stride;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int r = 0; r < 2; ++r) {
+                const int64_t j = j0 + r * 32 + lrow;
+                lsrc[r] = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+            }
+        }
+        const int k = kc * BK + lk;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+        for (int r = 0; r < AR; ++r) {
+            const int row = m0 + r * 32 + lrow;
+            ra[r] = row < p.M ? *(const float4 *)(Aop + (int64_t)row * p.K + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            rb[r] = lsrc[r] >= 0 ? *(const float4 *)(p.in + lsrc[r] * p.in_ld + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+
+    if (total > 0) load(0);
+    const int q = lane >> 4, c16 = lane & 15;
+    for (int it = 0; it < total; ++it) {
+        __syncthreads();   // the previous chunk's fragments have been read
+#pragma unroll
+        for (int r = 0; r < AR; ++r) *(float4 *)&As[r * 32 + lrow][lk] = ra[r];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) *(float4 *)&Bs[r * 32 + lrow][lk] = rb[r];
+        __syncthreads();
+        if (it + 1 < total) load(it + 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {   // k = 8q + 4h .. 8q + 4h + 3
+            float4 af[IM], bfr[JN];
+#pragma unroll
+            for (int i = 0; i < IM; ++i) af[i] = *(const float4 *)&As[wr + 16 * i + c16][8 * q + 4 * h];
+#pragma unroll
+            for (int j = 0; j < JN; ++j) bfr[j] = *(const float4 *)&Bs[wc + 16 * j + c16][8 * q + 4 * h];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < IM; ++i)
+#pragma unroll
+                    for (int j = 0; j < JN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(comp(af[i], e), comp(bfr[j], e),
+                                                                        acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tot[i][j][v] += (double)acc[i][j][v];
                 acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
-    };
-
-    const int lr = tid >> 2, lk = (tid & 3) * 4;  // loader coordinates
-    for (int t = 0; t < p.ntaps; ++t) {
-        const int op = p.tap_op[cls * p.ntaps + t];
-        const int off = p.tap_off[cls * p.ntaps + t];
-        __syncthreads();  // all readers of the previous tap's srcs are done
-        int64_t s = -1;
-        if (tid < BN) {
-            const int64_t j = j0 + tid;
-            if (j < p.n_per_class) s = source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl);
-            srcs[tid] = s;
-        }
-        if (!__syncthreads_or(s >= 0)) continue;
-        const float *Aop = p.A + (int64_t)op * p.a_stride;
-        const int64_t mysrc = srcs[lr];
-        for (int k0 = 0; k0 < p.K; k0 += BK) {
-            float4 av = make_float4(0.f, 0.f, 0.f, 0.f), bv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (m0 + lr < p.M) av = *(const float4 *)(Aop + (int64_t)(m0 + lr) * p.K + k0 + lk);
-            if (mysrc >= 0) bv = *(const float4 *)(p.in + mysrc * p.in_ld + k0 + lk);
-            __syncthreads();
-            *(float4 *)&As[lr][lk] = av;
-            *(float4 *)&Bs[lr][lk] = bv;
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                const int kl = kk + (lane >> 4);
-                float a0 = As[wr + (lane & 15)][kl], a1 = As[wr + 16 + (lane & 15)][kl];
-                float b0 = Bs[wc + (lane & 15)][kl], b1 = Bs[wc + 16 + (lane & 15)][kl];
-                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-            }
-            if (((k0 + BK) % kFoldK) == 0 || k0 + BK >= p.K) fold();
-        }
     }
     // D layout of 16x16x4: lane holds rows 4*(lane/16)+v, column lane%16
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
+        for (int jj = 0; jj < JN; ++jj) {
             const int row = m0 + wr + 16 * i + 4 * (lane >> 4);
             const int64_t j = j0 + wc + 16 * jj + (lane & 15);
             if (row < p.M && j < p.n_per_class) {
                 const int64_t b = (int64_t)p.cls_stride * j + cls;
-                float *o = p.out + b * p.out_ld + row;
                 double v0 = tot[i][jj][0], v1 = tot[i][jj][1], v2 = tot[i][jj][2], v3 = tot[i][jj][3];
-                if (p.accumulate) {
-                    const float4 old = *(const float4 *)o;
-                    v0 += old.x; v1 += old.y; v2 += old.z; v3 += old.w;
+                float *o;
+                if (G > 1) {
+                    o = p.part + ((int64_t)grp * p.n_boxes + b) * p.out_ld + row;
+                } else {
+                    o = p.out + b * p.out_ld + row;
+                    if (p.accumulate) {
+                        const float4 old = *(const float4 *)o;
+                        v0 += old.x; v1 += old.y; v2 += old.z; v3 += old.w;
+                    }
                 }
                 *(float4 *)o = make_float4((float)v0, (float)v1, (float)v2, (float)v3);
             }
         }
 }
 
-// Low-precision operands: A pre-rounded to TL, input FP32 scaled and rounded on load.
-template <typename TL>
-struct LPVec;
+// out[e] = (accumulate ? out[e] : 0) + sum_g part[g][e], FP64 sum in g order
+__global__ void reduce_partials(const float *__restrict__ part, int G, int64_t n, int accumulate,
+                                float *__restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double s = accumulate ? (double)out[e] : 0.0;
+        for (int g = 0; g < G; ++g) s += (double)part[(int64_t)g * n + e];
+        out[e] = (float)s;
+    }
+}
+
+// ------------------------------------------------------- low precision ----
+template <typename TL> struct LPVec;
 template <> struct LPVec<__bf16> { typedef bf16x8 type; };
 template <> struct LPVec<_Float16> { typedef halfx8 type; };
 
+template <typename TL>
+__device__ inline floatx4 mfma_lp(const typename LPVec<TL>::type &a, const typename LPVec<TL>::type &b, floatx4 c) {
+    if constexpr (std::is_same<TL, __bf16>::value) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
 constexpr int LBK = 32, LPAD = 8;
 
-template <typename TL>
-__global__ __launch_bounds__(256) void tapgemm_mfma_lp(TapArgs<TL, float, float> p) {
+// BM = 128 rows x 64 boxes; per 32-wide chunk one MFMA step per block (x3 for split BF16)
+template <typename TL, bool X3, int PASS>
+__global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
     typedef typename LPVec<TL>::type vec8;
-    __shared__ TL As[BM][LBK + LPAD];
-    __shared__ TL Bs[BN][LBK + LPAD];
-    __shared__ int64_t srcs[BN];
+    constexpr int BM = 128, IM = 4, JN = 2, NA = X3 ? 2 : 1;
+    __shared__ TL As[NA][BM][LBK + LPAD];
+    __shared__ TL Bs[NA][BN][LBK + LPAD];
     __shared__ float in_scale_sh;
-    const int cls = blockIdx.z;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = p.groups;
+    const int cls = blockIdx.z / G, grp = blockIdx.z % G;
+    const int tpg = (p.ntaps + G - 1) / G;
+    const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
     const int64_t j0 = (int64_t)blockIdx.x * BN;
     const int m0 = blockIdx.y * BM;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    // input scale = 1 / max|in|, from per-block partial maxima
+    const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
+    const int KC = p.K / LBK;
+    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
     if (tid == 0) {
         float mx = 0.f;
         for (int i = 0; i < p.n_amax; ++i) mx = fmaxf(mx, p.amax[i]);
         in_scale_sh = mx > 0.f ? 1.0f / mx : 1.0f;
     }
-    floatx4 acc[2][2];
+    floatx4 acc[IM][JN];
+    double tot[IM][JN][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < JN; ++j) {
+            acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tot[i][j][v] = 0.0;
+        }
     __syncthreads();
     const float sin = in_scale_sh;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-    for (int t = 0; t < p.ntaps; ++t) {
-        const int op = p.tap_op[cls * p.ntaps + t];
-        const int off = p.tap_off[cls * p.ntaps + t];
-        __syncthreads();  // all readers of the previous tap's srcs are done
-        int64_t s = -1;
-        if (tid < BN) {
-            const int64_t j = j0 + tid;
-            if (j < p.n_per_class) s = source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl);
-            srcs[tid] = s;
+    // loader: A rows r*64 + tid/4 (8 values at k = (tid%4)*8); B box tid/4
+    const int lrow = tid >> 2, lk = (tid & 3) * 8;
+    vec8 ra[2][NA], rb[NA];
+    int64_t lsrc = -1;
+    const TL *Ahi = p.A, *Alo = p.A2;
+    auto load = [&](int it) {
+        const int t = t0 + it / KC, kc = it % KC;
+        if (kc == 0) {
+            const int op = p.tap_op[cls * p.ntaps + t];
+            const int off = p.tap_off[cls * p.ntaps + t];
+            Ahi = p.A + (int64_t)op * p.a_stride;
+            if (X3) Alo = p.A2 + (int64_t)op * p.a_stride;
+            const int64_t j = j0 + lrow;
+            lsrc = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
         }
-        if (!__syncthreads_or(s >= 0)) continue;
-        const TL *Aop = p.A + (int64_t)op * p.a_stride;
-        const int64_t mysrc = srcs[lr];
-        for (int k0 = 0; k0 < p.K; k0 += LBK) {
-            vec8 av, bv;
-            if (m0 + lr < p.M) av = *(const vec8 *)(Aop + (int64_t)(m0 + lr) * p.K + k0 + lk);
-            else for (int e = 0; e < 8; ++e) av[e] = (TL)0.f;
-            if (mysrc >= 0) {
-                const float4 x0 = *(const float4 *)(p.in + mysrc * p.in_ld + k0 + lk);
-                const float4 x1 = *(const float4 *)(p.in + mysrc * p.in_ld + k0 + lk + 4);
-                bv[0] = (TL)(x0.x * sin); bv[1] = (TL)(x0.y * sin);
-                bv[2] = (TL)(x0.z * sin); bv[3] = (TL)(x0.w * sin);
-                bv[4] = (TL)(x1.x * sin); bv[5] = (TL)(x1.y * sin);
-                bv[6] = (TL)(x1.z * sin); bv[7] = (TL)(x1.w * sin);
+        const int k = kc * LBK + lk;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int row = m0 + r * 64 + lrow;
+            if (row < p.M) {
+                ra[r][0] = *(const vec8 *)(Ahi + (int64_t)row * p.K + k);
+                if (X3) ra[r][NA - 1] = *(const vec8 *)(Alo + (int64_t)row * p.K + k);
             } else {
-                for (int e = 0; e < 8; ++e) bv[e] = (TL)0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    ra[r][0][e] = (TL)0.f;
+                    ra[r][NA - 1][e] = (TL)0.f;
+                }
             }
-            __syncthreads();
-            *(vec8 *)&As[lr][lk] = av;
-            *(vec8 *)&Bs[lr][lk] = bv;
-            __syncthreads();
-            const int kl = 8 * (lane >> 4);
-            const vec8 a0 = *(const vec8 *)&As[wr + (lane & 15)][kl];
-            const vec8 a1 = *(const vec8 *)&As[wr + 16 + (lane & 15)][kl];
-            const vec8 b0 = *(const vec8 *)&Bs[wc + (lane & 15)][kl];
-            const vec8 b1 = *(const vec8 *)&Bs[wc + 16 + (lane & 15)][kl];
-            if constexpr (std::is_same<TL, __bf16>::value) {
-                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
-            } else {
-                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (lsrc >= 0) {
+            const float4 x0 = *(const float4 *)(p.in + lsrc * p.in_ld + k);
+            const float4 x1 = *(const float4 *)(p.in + lsrc * p.in_ld + k + 4);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = (e < 4 ? comp(x0, e) : comp(x1, e - 4)) * sin;
+                const TL hi = (TL)v;
+                rb[0][e] = hi;
+                if (X3) rb[NA - 1][e] = (TL)(v - (float)hi);
             }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                rb[0][e] = (TL)0.f;
+                rb[NA - 1][e] = (TL)0.f;
+            }
+        }
+    };
+    if (total > 0) load(0);
+    const int kl = 8 * (lane >> 4), c16 = lane & 15;
+    for (int it = 0; it < total; ++it) {
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < NA; ++h) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) *(vec8 *)&As[h][r * 64 + lrow][lk] = ra[r][h];
+            *(vec8 *)&Bs[h][lrow][lk] = rb[h];
+        }
+        __syncthreads();
+        if (it + 1 < total) load(it + 1);
+        vec8 af[NA][IM], bfr[NA][JN];
+#pragma unroll
+        for (int h = 0; h < NA; ++h) {
+#pragma unroll
+            for (int i = 0; i < IM; ++i) af[h][i] = *(const vec8 *)&As[h][wr + 16 * i + c16][kl];
+#pragma unroll
+            for (int j = 0; j < JN; ++j) bfr[h][j] = *(const vec8 *)&Bs[h][wc + 16 * j + c16][kl];
+        }
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
+                acc[i][j] = mfma_lp<TL>(af[0][i], bfr[0][j], acc[i][j]);
+                if (X3) {
+                    acc[i][j] = mfma_lp<TL>(af[0][i], bfr[NA - 1][j], acc[i][j]);
+                    acc[i][j] = mfma_lp<TL>(af[NA - 1][i], bfr[0][j], acc[i][j]);
+                }
+            }
+        if ((it & 3) == 3 || it + 1 == total) {
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+                for (int j = 0; j < JN; ++j) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) tot[i][j][v] += (double)acc[i][j][v];
+                    acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
         }
     }
-    const float oscale = p.op_scale / sin;
+    const double oscale = (double)p.op_scale / (double)sin;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
+        for (int jj = 0; jj < JN; ++jj) {
             const int row = m0 + wr + 16 * i + 4 * (lane >> 4);
             const int64_t j = j0 + wc + 16 * jj + (lane & 15);
             if (row < p.M && j < p.n_per_class) {
                 const int64_t b = (int64_t)p.cls_stride * j + cls;
-                float *o = p.out + b * p.out_ld + row;
-                floatx4 v = acc[i][jj];
-                v[0] *= oscale; v[1] *= oscale; v[2] *= oscale; v[3] *= oscale;
-                if (p.accumulate) {
-                    const float4 old = *(const float4 *)o;
-                    v[0] += old.x; v[1] += old.y; v[2] += old.z; v[3] += old.w;
+                double v0 = tot[i][jj][0] * oscale, v1 = tot[i][jj][1] * oscale;
+                double v2 = tot[i][jj][2] * oscale, v3 = tot[i][jj][3] * oscale;
+                float *o;
+                if (G > 1) {
+                    o = p.part + ((int64_t)grp * p.n_boxes + b) * p.out_ld + row;
+                } else {
+                    o = p.out + b * p.out_ld + row;
+                    if (p.accumulate) {
+                        const float4 old = *(const float4 *)o;
+                        v0 += old.x; v1 += old.y; v2 += old.z; v3 += old.w;
+                    }
                 }
-                *(float4 *)o = make_float4(v[0], v[1], v[2], v[3]);
+                *(float4 *)o = make_float4((float)v0, (float)v1, (float)v2, (float)v3);
             }
         }
 }
 
 // Generic LDS-tiled VALU version: 64 rows x 32 boxes per workgroup, each thread
-// 4 rows x 2 boxes.
+// 4 rows x 2 boxes.  No tap split.
 constexpr int VM = 64, VN = 32, VK = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void tapgemm_valu(TapArgs<T, T, T> p) {
@@ -318,41 +437,81 @@ __global__ void amax_partial(const float *__restrict__ x, int64_t n, float *__re
     if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
 
+constexpr int64_t kTargetWGs = 2048;   // about 8 workgroups per CU
+
 template <typename TA, typename TI, typename TO>
-dim3 grid_of(const TapArgs<TA, TI, TO> &p, int bn, int bm) {
-    return dim3((unsigned)((p.n_per_class + bn - 1) / bn), (unsigned)((p.M + bm - 1) / bm), p.nclass);
+int choose_groups(const TapArgs<TA, TI, TO> &p, int bm) {
+    if (!p.part || p.ntaps <= 1) return 1;
+    const int64_t base = ((p.n_per_class + BN - 1) / BN) * ((p.M + bm - 1) / bm) * p.nclass;
+    int64_t g = (kTargetWGs + base - 1) / base;
+    if (g > p.ntaps) g = p.ntaps;
+    // the scratch must hold g partial outputs
+    while (g > 1 && g * p.n_boxes * p.out_ld > p.part_capacity) --g;
+    if (g <= 1) return 1;
+    // equal-size groups: no empty trailing group
+    const int tpg = (p.ntaps + (int)g - 1) / (int)g;
+    return (p.ntaps + tpg - 1) / tpg;
+}
+
+template <typename TA, typename TI, typename TO, typename F>
+int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st) {
+    p.groups = choose_groups(p, bm);
+    dim3 grid((unsigned)((p.n_per_class + BN - 1) / BN), (unsigned)((p.M + bm - 1) / bm),
+              (unsigned)(p.nclass * p.groups));
+    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p);
+    KIFMM_HIP(hipGetLastError());
+    if (p.groups > 1) {
+        const int64_t n = p.n_boxes * p.out_ld;
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(reduce_partials, dim3((unsigned)blocks), dim3(256), 0, st, (const float *)p.part,
+                           p.groups, n, p.accumulate, (float *)p.out);
+        KIFMM_HIP(hipGetLastError());
+    }
+    return KIFMM_OK;
 }
 
 }  // namespace
 
+template <int PASS>
+int run_f32_pass(const TapArgs<float, float, float> &p, hipStream_t st) {
+    if (p.M >= 128) return launch_split(p, 128, tapgemm_f32<128, PASS>, st);
+    return launch_split(p, 64, tapgemm_f32<64, PASS>, st);
+}
+
 int run_tap_f32(const TapArgs<float, float, float> &p, hipStream_t st) {
-    if (p.K % BK != 0) return fail(KIFMM_EINVAL, "tap GEMM: K not a multiple of 16");
-    hipLaunchKernelGGL(tapgemm_mfma_f32, grid_of(p, BN, BM), dim3(256), 0, st, p);
+    if (p.K % BK != 0) return fail(KIFMM_EINVAL, "tap GEMM: K not a multiple of 32");
+    if (p.pass == PASS_P2P) return run_f32_pass<PASS_P2P>(p, st);
+    if (p.pass == PASS_M2L) return run_f32_pass<PASS_M2L>(p, st);
+    return run_f32_pass<PASS_GENERIC>(p, st);
+}
+
+int run_tap_f64(const TapArgs<double, double, double> &p0, hipStream_t st) {
+    TapArgs<double, double, double> p = p0;
+    p.groups = 1;
+    dim3 grid((unsigned)((p.n_per_class + VN - 1) / VN), (unsigned)((p.M + VM - 1) / VM), p.nclass);
+    hipLaunchKernelGGL(tapgemm_valu<double>, grid, dim3(256), 0, st, p);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
-int run_tap_f64(const TapArgs<double, double, double> &p, hipStream_t st) {
-    hipLaunchKernelGGL(tapgemm_valu<double>, grid_of(p, VN, VM), dim3(256), 0, st, p);
-    KIFMM_HIP(hipGetLastError());
-    return KIFMM_OK;
-}
-
-int run_tap_f32_valu(const TapArgs<float, float, float> &p, hipStream_t st) {
-    hipLaunchKernelGGL(tapgemm_valu<float>, grid_of(p, VN, VM), dim3(256), 0, st, p);
-    KIFMM_HIP(hipGetLastError());
-    return KIFMM_OK;
+template <typename TL, bool X3>
+int run_lp_pass(const TapArgs<TL, float, float> &p, hipStream_t st) {
+    if (p.pass == PASS_P2P) return launch_split(p, 128, tapgemm_lp<TL, X3, PASS_P2P>, st);
+    return launch_split(p, 128, tapgemm_lp<TL, X3, PASS_M2L>, st);
 }
 
 template <typename TL>
-int run_tap_lp(const TapArgs<TL, float, float> &p, hipStream_t st) {
+int run_tap_lp(const TapArgs<TL, float, float> &p, bool x3, hipStream_t st) {
     if (p.K % LBK != 0) return fail(KIFMM_EINVAL, "tap GEMM (low precision): K not a multiple of 32");
-    hipLaunchKernelGGL(tapgemm_mfma_lp<TL>, grid_of(p, BN, BM), dim3(256), 0, st, p);
-    KIFMM_HIP(hipGetLastError());
-    return KIFMM_OK;
+    if (x3) {
+        if constexpr (std::is_same<TL, __bf16>::value) return run_lp_pass<TL, true>(p, st);
+        else return fail(KIFMM_EUNSUPPORTED, "split operands are implemented for bfloat16 only");
+    }
+    return run_lp_pass<TL, false>(p, st);
 }
-template int run_tap_lp<__bf16>(const TapArgs<__bf16, float, float> &, hipStream_t);
-template int run_tap_lp<_Float16>(const TapArgs<_Float16, float, float> &, hipStream_t);
+template int run_tap_lp<__bf16>(const TapArgs<__bf16, float, float> &, bool, hipStream_t);
+template int run_tap_lp<_Float16>(const TapArgs<_Float16, float, float> &, bool, hipStream_t);
 
 int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st) {
     hipLaunchKernelGGL(amax_partial, dim3(nparts), dim3(256), 0, st, x, n, part);

@@ -45,6 +45,16 @@ __global__ void permute_out_kernel(const T *__restrict__ Sp, const int32_t *__re
         S[perm[p]] = Sp[p] * scale;
 }
 
+// S[perm[p]] = scale * (Sa[p] + Sb[p])  (far field + near field)
+template <typename T>
+__global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb,
+                                    const int32_t *__restrict__ perm, int64_t N, T scale,
+                                    T *__restrict__ S) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x)
+        S[perm[p]] = (Sa[p] + Sb[p]) * scale;
+}
+
 __global__ void perm_to_i64_kernel(const int32_t *perm, int64_t N, int64_t *out) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
@@ -82,6 +92,18 @@ int launch_permute_out(const Tree &t, const T *Sp, T scale, T *S, hipStream_t st
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
+
+template <typename T>
+int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, T *S, hipStream_t st) {
+    hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.perm,
+                       t.N, scale, S);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+template int launch_permute_out2<float>(const Tree &, const float *, const float *, float, float *,
+                                        hipStream_t);
+template int launch_permute_out2<double>(const Tree &, const double *, const double *, double,
+                                         double *, hipStream_t);
 
 int launch_perm_i64(const Tree &t, int64_t *out, hipStream_t st) {
     hipLaunchKernelGGL(perm_to_i64_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.perm, t.N,

@@ -74,7 +74,8 @@ def test_fp32_is_fp64_up_to_rounding(K, g32):
     assert rel_l2(a, b) < 1e-6
 
 
-@pytest.mark.parametrize("precision,tol_direct,tol_fp32", [("m2l_bf16", 1e-3, 1e-3), ("m2l_fp16", 1e-4, 1e-4)])
+@pytest.mark.parametrize("precision,tol_direct,tol_fp32", [("m2l_bf16", 1e-3, 1e-3), ("m2l_fp16", 1e-4, 1e-4),
+                                                         ("m2l_bf16x3", 1e-5, 1e-5), ("bf16x3", 1e-5, 1e-5)])
 def test_low_precision_m2l(K, g32, precision, tol_direct, tol_fp32, record_property):
     # nested layout: truncation ~2e-7, so the error measured is the M2L rounding
     I, L, refs = g32
@@ -120,3 +121,27 @@ def test_linearity_and_mismatch(K):
     with pytest.raises(K.KifmmError) as e:
         K.eval(other, ops, x, 1.0)
     assert e.value.code == K.EMISMATCH
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("m2l_bf16x3", 1e-5), ("bf16x3", 1e-5)])
+def test_leaf512_depth3_vs_direct(K, precision, tol):
+    # 64^3 on 4 mm, leaves of 8^3 cells: three levels, tap-group split at levels 2-3
+    from paper_2006_03515_amd import workloads
+    w = workloads.two_heads_random(n=64, L=0.4, seed=8)
+    I = w.I.astype(np.float32).astype(np.float64)
+    ref = odirect.fft_full(I, (w.h,) * 3, w.p_o2)
+    got = fmm(K, I, w.L, w.p_o2, 512, layout="nested", rcond=1e-10, precision=precision)
+    print("%s leaf 512: rel-L2 vs direct %.3e" % (precision, rel_l2(got, ref)))
+    assert rel_l2(got, ref) < tol
+
+
+def test_repeated_calls_bitwise_equal(K, g32):
+    I, L, _ = g32
+    keep = []
+    a = fmm(K, I, L, 150.0, 64, layout="nested", precision="fp32", ops_out=keep)
+    tree, ops = keep[0]
+    It = torch.tensor(np.ascontiguousarray(I), dtype=torch.float32, device="cuda").reshape(-1)
+    for _ in range(3):
+        b = K.eval(tree, ops, It, 1.0, precision="fp32")
+    torch.cuda.synchronize()
+    assert np.array_equal(a, b.cpu().numpy().reshape(I.shape).astype(np.float64))
