@@ -182,6 +182,79 @@ enum { KIFMM_PASS_PERMUTE_IN = 0, KIFMM_PASS_P2M = 1, KIFMM_PASS_M2M = 2, KIFMM_
 int kifmm_profile_enable(kifmm_ops ops, int32_t on);
 int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate (not in the paper): kernels of a 3D convolutional network
+ * that maps a coarse source field to S_ph, trained on pairs made by kifmm_eval
+ * and used with kifmm_eval / direct_eval as judge and fallback.
+ *
+ * Activations: FP32, channels-last, voxels of an n^3 grid (n a power of two) in
+ * Morton order per sample: x[(s * n^3 + morton(i, j, k)) * C + c].  Weights:
+ * FP32 masters [taps][co][ci]; the layer kernels read copies made by
+ * kifmm_nn_prepare_weights (FP32 or BF16, forward [taps][co][ci] and transposed
+ * [taps][ci][co] for the data gradient).  bf16 = 1 runs the products on BF16
+ * MFMA with FP32 accumulation (inputs rounded to nearest-even when staged);
+ * bf16 = 0 on FP32 MFMA.  Products of one output are summed in FP32 over at
+ * most 8 MFMA steps and then in FP64.
+ * Layer kinds (taps in C order):
+ *   KIFMM_NN_CONV3  3x3x3 stride 1 zero padding, 27 taps (dz, dy, dx) in {-1,0,1}^3
+ *   KIFMM_NN_DOWN2  2x2x2 stride 2 (n -> n/2), 8 taps = child parity (pz, py, px)
+ *   KIFMM_NN_UP2    transposed 2x2x2 stride 2 (n -> 2n), 8 taps = child parity
+ *   KIFMM_NN_POINT  1x1x1
+ * n_in is the grid side of the layer input.  ci (the reduction) must be a
+ * multiple of 32 and co a multiple of 16 (32 for the weight gradient).
+ * work / work_floats: optional device scratch for split reductions (the calls
+ * allocate nothing; with too little scratch they use fewer workgroups).
+ * All calls enqueue on `stream` and return before the work ends. */
+enum { KIFMM_NN_CONV3 = 0, KIFMM_NN_DOWN2 = 1, KIFMM_NN_UP2 = 2, KIFMM_NN_POINT = 3 };
+/* y (+)= layer(x) */
+int kifmm_nn_layer_forward(int32_t kind, int32_t batch, int32_t n_in, const float *x, int32_t ci,
+                           const void *w, int32_t co, float *y, int32_t accumulate, int32_t bf16,
+                           float *work, int64_t work_floats, void *stream);
+/* dx (+)= layer^T(dy) with the transposed weights wt [taps][ci][co] */
+int kifmm_nn_layer_backward_data(int32_t kind, int32_t batch, int32_t n_in, const float *dy, int32_t co,
+                                 const void *wt, int32_t ci, float *dx, int32_t accumulate, int32_t bf16,
+                                 float *work, int64_t work_floats, void *stream);
+/* dw [taps][co][ci] = dL/dw given the layer input x and dL/dy (overwritten) */
+int kifmm_nn_layer_backward_weight(int32_t kind, int32_t batch, int32_t n_in, const float *x, int32_t ci,
+                                   const float *dy, int32_t co, float *dw, int32_t bf16, float *work,
+                                   int64_t work_floats, void *stream);
+/* w_fwd = cast(w) [taps][co][ci], w_bwd = cast(w)^T [taps][ci][co] (either may be NULL) */
+int kifmm_nn_prepare_weights(int32_t taps, int32_t co, int32_t ci, const float *w, void *w_fwd,
+                             void *w_bwd, int32_t bf16, void *stream);
+/* y = leaky(y + bias) in place (bias [c] or NULL; alpha = 1 gives the identity) */
+int kifmm_nn_bias_act(int64_t nvox, int32_t c, float *y, const float *bias, float alpha, void *stream);
+/* dy <- dy * leaky'(.) (using the sign of the post-activation y) and dbias = sum of
+ * the result over voxels (fixed-order reduction; work >= min(1024, nvox/256) * c floats) */
+int kifmm_nn_bias_act_backward(int64_t nvox, int32_t c, const float *y, float *dy, float *dbias,
+                               float alpha, float *work, int64_t work_floats, void *stream);
+/* Squared relative L2 loss of channel 0 of y (Morton, row length ld) against the
+ * grid-ordered target t, per sample, averaged over the batch: loss[0] = mean,
+ * loss[1 + s] = per sample (double, device).  dy (optional, layout of y) gets
+ * dL/dy (zero outside channel 0).  work >= batch * (2 * min(256, n^3/256) + 1) doubles. */
+int kifmm_nn_rel_l2_loss(int32_t batch, int32_t n, const float *y, int32_t ld, const float *t, float *dy,
+                         double *loss, double *work, int64_t work_doubles, void *stream);
+/* Adam step `step` (>= 1) on n FP32 master weights */
+int kifmm_nn_adam(int64_t n, float *w, const float *g, float *m, float *v, int32_t step, float lr,
+                  float b1, float b2, float eps, void *stream);
+/* network input: 27-neighbourhood of scale[s] * grid[s] (grid order) as 32 channels
+ * (the last 5 zero) in Morton order; scale may be NULL (1) */
+int kifmm_nn_pack_input(int32_t batch, int32_t n, const float *grid, const float *scale, float *feat,
+                        void *stream);
+/* grid[s][g] = scale[s] * y[(s n^3 + morton(g)) * ld] (channel 0) */
+int kifmm_nn_unpack_output(int32_t batch, int32_t n, const float *y, int32_t ld, const float *scale,
+                           float *grid, void *stream);
+/* out[s] = max |x_s| over per_sample values, or its reciprocal (1 for a zero field) */
+int kifmm_nn_max_abs(int32_t batch, int64_t per_sample, const float *x, float *out, int32_t reciprocal,
+                     float *work, int64_t work_floats, void *stream);
+/* 2x2x2 block means of a (2 n_coarse)^3 grid-ordered field */
+int kifmm_nn_coarsen2(int32_t batch, int32_t n_coarse, const float *fine, float *coarse, void *stream);
+/* trilinear interpolation from cell centres of an n_coarse^3 field to those of the
+ * (2 n_coarse)^3 field, clamped at the boundary */
+int kifmm_nn_upsample2(int32_t batch, int32_t n_coarse, const float *coarse, float *fine, void *stream);
+/* out[0] = ||scale * S[tgt] - ref|| / ||ref|| (one workgroup, fixed order) */
+int kifmm_nn_sampled_rel_err(int64_t n_tgt, const float *S, const int64_t *tgt, const double *ref,
+                             double scale, double *out, void *stream);
+
 void kifmm_tree_destroy(kifmm_tree tree);  /* NULL is ignored */
 void kifmm_ops_destroy(kifmm_ops ops);     /* NULL is ignored */
 const char *kifmm_last_error(void);

@@ -124,3 +124,41 @@ def adam(w, g, m, v, k, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** k)
     vh = v / (1 - b2 ** k)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def coarsen2(f):
+    """2x2x2 block means of an [n, n, n] field (n even)."""
+    n = f.shape[0] // 2
+    return f.reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+
+
+def upsample2(c):
+    """Trilinear interpolation of an m^3 field of cell-centre values to the cell
+    centres of the (2m)^3 refinement; fine centre i sits at coarse coordinate
+    (i + 1/2)/2 - 1/2, clamped to [0, m-1] (constant extension at the faces)."""
+    m = c.shape[0]
+    x = np.clip((np.arange(2 * m) + 0.5) / 2 - 0.5, 0, m - 1)
+    i0 = np.floor(x).astype(int)
+    i1 = np.minimum(i0 + 1, m - 1)
+    w = x - i0
+    out = c
+    for ax in range(3):
+        a = np.take(out, i0, axis=ax)
+        b = np.take(out, i1, axis=ax)
+        shape = [1, 1, 1]
+        shape[ax] = -1
+        out = a * (1 - w.reshape(shape)) + b * w.reshape(shape)
+    return out
+
+
+def neighbourhood27(f):
+    """[n, n, n] -> [32, n, n, n]: channel (dz+1)*9 + (dy+1)*3 + (dx+1) holds f at
+    offset (dz, dy, dx) (zero outside the grid), channels 27..31 zero."""
+    out = np.zeros((32,) + f.shape)
+    c = 0
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                out[c] = _shifted(f[None], dz, dy, dx)[0]
+                c += 1
+    return out

@@ -17,6 +17,12 @@ void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
+#define KIFMM_TRY_(x)                         \
+    do {                                      \
+        int rc_ = (x);                        \
+        if (rc_ != KIFMM_OK) return rc_;      \
+    } while (0)
+
 #define KIFMM_HIP(call)                                   \
     do {                                                  \
         hipError_t e_ = (call);                           \

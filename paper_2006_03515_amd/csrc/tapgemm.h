@@ -20,7 +20,7 @@ struct TapArgs {
     int cls_stride;       // output box = cls_stride * j + class
     int64_t n_per_class;
     int64_t n_boxes;      // nclass * n_per_class (size of the output in boxes)
-    const int *tap_op;    // [nclass][ntaps]
+    const int *tap_op;    // [nclass][ntaps]; null: use inl_op / inl_off
     const int *tap_off;   // [nclass][ntaps]
     int ntaps;
     int accumulate;       // 0: out = sum, 1: out += sum
@@ -31,6 +31,24 @@ struct TapArgs {
     int n_amax;
     float op_scale;       // low precision: A was stored divided by op_scale
     int pass;             // PASS_* below: selects a separately named kernel instance
+    int inl_op[32];       // tap table passed by value (nclass * ntaps <= 32)
+    int inl_off[32];
+};
+
+// Weight gradient of a tap GEMM: dW[t] (M x K) = sum_j dY[b_j] (M) . X[src_j]^T (K),
+// b_j = cls_stride * j + cls(t), cls(t) = class_is_tap ? t : 0, src_j = src(b_j, t).
+struct WgradArgs {
+    const float *dy;      // dy[b * M + m]
+    const float *x;       // x[src * K + k]
+    float *dw;            // dw[t][M][K]
+    int M, K;
+    int mode, nl, cls_stride, class_is_tap;
+    int64_t n_per_class;
+    int ntaps;
+    int tap_off[32];
+    float *part;          // scratch for voxel-group partials
+    int64_t part_capacity;
+    int groups;           // set by the launcher
 };
 
 // Kernel instances are compiled once per pass kind so that profilers report the
@@ -42,5 +60,6 @@ int run_tap_f64(const TapArgs<double, double, double> &p, hipStream_t st);
 template <typename TL>
 int run_tap_lp(const TapArgs<TL, float, float> &p, bool x3, hipStream_t st);
 int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st);
+int run_wgrad(WgradArgs p, bool bf16, hipStream_t st);
 
 }  // namespace kifmm

@@ -53,16 +53,22 @@ __device__ inline int64_t source_box(int mode, int64_t b, int off, int nl) {
         case SRC_CHILD: return 8 * b + off;
         case SRC_PARENT: return b >> 3;
         default: {
+            // b = sample * nl^3 + morton(x, y, z); neighbours stay inside the sample
+            int lg = 0;
+            while ((1 << lg) < nl) ++lg;
+            const int64_t base = (b >> (3 * lg)) << (3 * lg);
             int x, y, z;
-            morton_decode((uint32_t)b, x, y, z);
+            morton_decode((uint32_t)(b - base), x, y, z);
             x += ((off >> 10) & 31) - 16;
             y += ((off >> 5) & 31) - 16;
             z += (off & 31) - 16;
             if (x < 0 || y < 0 || z < 0 || x >= nl || y >= nl || z >= nl) return -1;
-            return (int64_t)morton_encode(x, y, z);
+            return base + (int64_t)morton_encode(x, y, z);
         }
     }
 }
+
+__device__ inline int tap_op_of(const int *tab, const int *inl, int i) { return tab ? tab[i] : inl[i]; }
 
 constexpr int BN = 64;     // boxes per tile
 constexpr int BK = 32;     // reduction chunk
@@ -109,8 +115,8 @@ __global__ __launch_bounds__(256) void tapgemm_f32(TapArgs<float, float, float> 
     auto load = [&](int it) {
         const int t = t0 + it / KC, kc = it % KC;
         if (kc == 0) {
-            const int op = p.tap_op[cls * p.ntaps + t];
-            const int off = p.tap_off[cls * p.ntaps + t];
+            const int op = tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t);
+            const int off = tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t);
             Aop = p.A + (int64_t)op * p.a_stride;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -213,10 +219,11 @@ __device__ inline floatx4 mfma_lp(const typename LPVec<TL>::type &a, const typen
 constexpr int LBK = 32, LPAD = 8;
 
 // BM = 128 rows x 64 boxes; per 32-wide chunk one MFMA step per block (x3 for split BF16)
-template <typename TL, bool X3, int PASS>
+template <typename TL, bool X3, int PASS, int BM>
 __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
     typedef typename LPVec<TL>::type vec8;
-    constexpr int BM = 128, IM = 4, JN = 2, NA = X3 ? 2 : 1;
+    constexpr int IM = BM / 32, JN = 2, NA = X3 ? 2 : 1;
+    constexpr int AR = BM >= 64 ? BM / 64 : 1;   // A row passes of the loader (64 rows each)
     __shared__ TL As[NA][BM][LBK + LPAD];
     __shared__ TL Bs[NA][BN][LBK + LPAD];
     __shared__ float in_scale_sh;
@@ -249,14 +256,14 @@ __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
     const float sin = in_scale_sh;
     // loader: A rows r*64 + tid/4 (8 values at k = (tid%4)*8); B box tid/4
     const int lrow = tid >> 2, lk = (tid & 3) * 8;
-    vec8 ra[2][NA], rb[NA];
+    vec8 ra[AR][NA], rb[NA];
     int64_t lsrc = -1;
     const TL *Ahi = p.A, *Alo = p.A2;
     auto load = [&](int it) {
         const int t = t0 + it / KC, kc = it % KC;
         if (kc == 0) {
-            const int op = p.tap_op[cls * p.ntaps + t];
-            const int off = p.tap_off[cls * p.ntaps + t];
+            const int op = tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t);
+            const int off = tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t);
             Ahi = p.A + (int64_t)op * p.a_stride;
             if (X3) Alo = p.A2 + (int64_t)op * p.a_stride;
             const int64_t j = j0 + lrow;
@@ -264,9 +271,9 @@ __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
         }
         const int k = kc * LBK + lk;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < AR; ++r) {
             const int row = m0 + r * 64 + lrow;
-            if (row < p.M) {
+            if (row < p.M && r * 64 + lrow < BM) {
                 ra[r][0] = *(const vec8 *)(Ahi + (int64_t)row * p.K + k);
                 if (X3) ra[r][NA - 1] = *(const vec8 *)(Alo + (int64_t)row * p.K + k);
             } else {
@@ -302,7 +309,8 @@ __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
 #pragma unroll
         for (int h = 0; h < NA; ++h) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r) *(vec8 *)&As[h][r * 64 + lrow][lk] = ra[r][h];
+            for (int r = 0; r < AR; ++r)
+                if (r * 64 + lrow < BM) *(vec8 *)&As[h][r * 64 + lrow][lk] = ra[r][h];
             *(vec8 *)&Bs[h][lrow][lk] = rb[h];
         }
         __syncthreads();
@@ -376,8 +384,8 @@ __global__ __launch_bounds__(256) void tapgemm_valu(TapArgs<T, T, T> p) {
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
     T acc[4][2] = {};
     for (int t = 0; t < p.ntaps; ++t) {
-        const int op = p.tap_op[cls * p.ntaps + t];
-        const int off = p.tap_off[cls * p.ntaps + t];
+        const int op = tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t);
+        const int off = tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t);
         __syncthreads();
         if (tid < VN) {
             const int64_t j = j0 + tid;
@@ -423,6 +431,124 @@ __global__ __launch_bounds__(256) void tapgemm_valu(TapArgs<T, T, T> p) {
                 *o = p.accumulate ? *o + acc[i][jj] : acc[i][jj];
             }
         }
+}
+
+// ----------------------------------------------------------- weight gradient ----
+// dW[t] (M x K) = sum_j dY[b_j] X[src_j]^T: a GEMM whose reduction runs over voxels.
+// Workgroup = one tap, one BW x BW tile of dW, one group of voxels; voxels are staged
+// 32 at a time, transposed into LDS (reduction index innermost), operands rounded to
+// TL (FP32 or BF16) and multiplied on MFMA with FP32 accumulation and FP64 folding.
+// Voxel groups write partials that reduce_partials adds in a fixed order.
+template <typename TL, int BW>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs p) {
+    constexpr int WK = 32, PAD = std::is_same<TL, float>::value ? 4 : 8;
+    constexpr int CPT = BW / 8;                 // channels per loader thread
+    constexpr int IMW = BW / 32;                // 16-blocks per wave per dimension
+    __shared__ TL As[BW][WK + PAD];
+    __shared__ TL Bs[BW][WK + PAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t = blockIdx.z, g = blockIdx.x;
+    const int tilesK = p.K / BW;
+    const int m0 = (blockIdx.y / tilesK) * BW, k0 = (blockIdx.y % tilesK) * BW;
+    const int cls = p.class_is_tap ? t : 0;
+    const int off = p.tap_off[t];
+    int64_t per = (p.n_per_class + p.groups - 1) / p.groups;
+    per = (per + WK - 1) / WK * WK;
+    const int64_t ja = (int64_t)g * per, jb = min(p.n_per_class, ja + per);
+    const int wr = (wave >> 1) * (BW / 2), wc = (wave & 1) * (BW / 2);
+    floatx4 acc[IMW][IMW];
+    double tot[IMW][IMW][4];
+#pragma unroll
+    for (int i = 0; i < IMW; ++i)
+#pragma unroll
+        for (int j = 0; j < IMW; ++j) {
+            acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tot[i][j][v] = 0.0;
+        }
+    const int kk = tid >> 3, cg = (tid & 7) * CPT;
+    const int q = lane >> 4, c16 = lane & 15;
+    int nchunk = 0;
+    for (int64_t j0 = ja; j0 < jb; j0 += WK, ++nchunk) {
+        float dv[CPT], xv[CPT];
+        const int64_t j = j0 + kk;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) { dv[e] = 0.f; xv[e] = 0.f; }
+        if (j < jb) {
+            const int64_t b = (int64_t)p.cls_stride * j + cls;
+            const int64_t src = source_box(p.mode, b, off, p.nl);
+#pragma unroll
+            for (int e = 0; e < CPT; e += 4) {
+                const float4 a = *(const float4 *)(p.dy + b * p.M + m0 + cg + e);
+                dv[e] = a.x; dv[e + 1] = a.y; dv[e + 2] = a.z; dv[e + 3] = a.w;
+            }
+            if (src >= 0) {
+#pragma unroll
+                for (int e = 0; e < CPT; e += 4) {
+                    const float4 a = *(const float4 *)(p.x + src * p.K + k0 + cg + e);
+                    xv[e] = a.x; xv[e + 1] = a.y; xv[e + 2] = a.z; xv[e + 3] = a.w;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            As[cg + e][kk] = (TL)dv[e];
+            Bs[cg + e][kk] = (TL)xv[e];
+        }
+        __syncthreads();
+        if constexpr (std::is_same<TL, float>::value) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float4 af[IMW], bfr[IMW];
+#pragma unroll
+                for (int i = 0; i < IMW; ++i) {
+                    af[i] = *(const float4 *)&As[wr + 16 * i + c16][8 * q + 4 * h];
+                    bfr[i] = *(const float4 *)&Bs[wc + 16 * i + c16][8 * q + 4 * h];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int i = 0; i < IMW; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < IMW; ++jj)
+                            acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(comp(af[i], e), comp(bfr[jj], e),
+                                                                             acc[i][jj], 0, 0, 0);
+            }
+        } else {
+            bf16x8 af[IMW], bfr[IMW];
+#pragma unroll
+            for (int i = 0; i < IMW; ++i) {
+                af[i] = *(const bf16x8 *)&As[wr + 16 * i + c16][8 * q];
+                bfr[i] = *(const bf16x8 *)&Bs[wc + 16 * i + c16][8 * q];
+            }
+#pragma unroll
+            for (int i = 0; i < IMW; ++i)
+#pragma unroll
+                for (int jj = 0; jj < IMW; ++jj)
+                    acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < IMW; ++i)
+#pragma unroll
+            for (int jj = 0; jj < IMW; ++jj) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tot[i][jj][v] += (double)acc[i][jj][v];
+                acc[i][jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    }
+    float *out = p.groups > 1 ? p.part + ((int64_t)g * p.ntaps + t) * p.M * p.K
+                              : p.dw + (int64_t)t * p.M * p.K;
+#pragma unroll
+    for (int i = 0; i < IMW; ++i)
+#pragma unroll
+        for (int jj = 0; jj < IMW; ++jj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wr + 16 * i + 4 * (lane >> 4) + v;
+                const int col = k0 + wc + 16 * jj + (lane & 15);
+                out[(int64_t)row * p.K + col] = (float)tot[i][jj][v];
+            }
 }
 
 // per-block partial max |x| over n values (for the low-precision input scale)
@@ -495,10 +621,18 @@ int run_tap_f64(const TapArgs<double, double, double> &p0, hipStream_t st) {
     return KIFMM_OK;
 }
 
+template <typename TL, bool X3, int PASS>
+int run_lp_bm(const TapArgs<TL, float, float> &p, hipStream_t st) {
+    if (p.M > 64) return launch_split(p, 128, tapgemm_lp<TL, X3, PASS, 128>, st);
+    if (p.M > 32) return launch_split(p, 64, tapgemm_lp<TL, X3, PASS, 64>, st);
+    return launch_split(p, 32, tapgemm_lp<TL, X3, PASS, 32>, st);
+}
+
 template <typename TL, bool X3>
 int run_lp_pass(const TapArgs<TL, float, float> &p, hipStream_t st) {
-    if (p.pass == PASS_P2P) return launch_split(p, 128, tapgemm_lp<TL, X3, PASS_P2P>, st);
-    return launch_split(p, 128, tapgemm_lp<TL, X3, PASS_M2L>, st);
+    if (p.pass == PASS_P2P) return run_lp_bm<TL, X3, PASS_P2P>(p, st);
+    if (p.pass == PASS_M2L) return run_lp_bm<TL, X3, PASS_M2L>(p, st);
+    return run_lp_bm<TL, X3, PASS_GENERIC>(p, st);
 }
 
 template <typename TL>
@@ -512,6 +646,37 @@ int run_tap_lp(const TapArgs<TL, float, float> &p, bool x3, hipStream_t st) {
 }
 template int run_tap_lp<__bf16>(const TapArgs<__bf16, float, float> &, bool, hipStream_t);
 template int run_tap_lp<_Float16>(const TapArgs<_Float16, float, float> &, bool, hipStream_t);
+
+int run_wgrad(WgradArgs p, bool bf16, hipStream_t st) {
+    if (p.M % 32 || p.K % 32) return fail(KIFMM_EINVAL, "weight gradient: channel counts must be multiples of 32");
+    const int bw = (p.M % 64 == 0 && p.K % 64 == 0) ? 64 : 32;
+    const int64_t tiles = (int64_t)(p.M / bw) * (p.K / bw);
+    const int64_t wsize = (int64_t)p.ntaps * p.M * p.K;
+    int64_t g = (kTargetWGs + tiles * p.ntaps - 1) / (tiles * p.ntaps);
+    const int64_t gmax = (p.n_per_class + 255) / 256;          // at least 256 voxels per group
+    if (g > gmax) g = gmax;
+    if (!p.part) g = 1;
+    while (g > 1 && g * wsize > p.part_capacity) --g;
+    if (g < 1) g = 1;
+    p.groups = (int)g;
+    dim3 grid((unsigned)g, (unsigned)tiles, (unsigned)p.ntaps);
+    if (bw == 64) {
+        if (bf16) hipLaunchKernelGGL((wgrad_kernel<__bf16, 64>), grid, dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((wgrad_kernel<float, 64>), grid, dim3(256), 0, st, p);
+    } else {
+        if (bf16) hipLaunchKernelGGL((wgrad_kernel<__bf16, 32>), grid, dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((wgrad_kernel<float, 32>), grid, dim3(256), 0, st, p);
+    }
+    KIFMM_HIP(hipGetLastError());
+    if (g > 1) {
+        int64_t blocks = (wsize + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(reduce_partials, dim3((unsigned)blocks), dim3(256), 0, st, (const float *)p.part,
+                           (int)g, wsize, 0, p.dw);
+        KIFMM_HIP(hipGetLastError());
+    }
+    return KIFMM_OK;
+}
 
 int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st) {
     hipLaunchKernelGGL(amax_partial, dim3(nparts), dim3(256), 0, st, x, n, part);

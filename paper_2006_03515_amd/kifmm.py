@@ -23,7 +23,13 @@ CHI_MIN, CHI_MAX = 0.035, 2.0
 
 EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "kifmm_tree_info",
            "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_tree_destroy",
-           "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read")
+           "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read",
+           "kifmm_nn_layer_forward", "kifmm_nn_layer_backward_data", "kifmm_nn_layer_backward_weight",
+           "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
+           "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
+           "kifmm_nn_max_abs", "kifmm_nn_coarsen2", "kifmm_nn_upsample2", "kifmm_nn_sampled_rel_err")
+NN_CONV3, NN_DOWN2, NN_UP2, NN_POINT = 0, 1, 2, 3
+NN_TAPS = {NN_CONV3: 27, NN_DOWN2: 8, NN_UP2: 8, NN_POINT: 1}
 PASSES = ("permute_in", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "permute_out")
 
 
@@ -69,9 +75,28 @@ def load_library(path=LIB_PATH):
     lib.kifmm_last_error.restype = ctypes.c_char_p
     lib.kifmm_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.kifmm_profile_read.argtypes = [P, P, P, ctypes.c_int32]
+    I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    nn = {
+        "kifmm_nn_layer_forward": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
+        "kifmm_nn_layer_backward_data": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
+        "kifmm_nn_layer_backward_weight": [I32, I32, I32, P, I32, P, I32, P, I32, P, I64, P],
+        "kifmm_nn_prepare_weights": [I32, I32, I32, P, P, P, I32, P],
+        "kifmm_nn_bias_act": [I64, I32, P, P, F32, P],
+        "kifmm_nn_bias_act_backward": [I64, I32, P, P, P, F32, P, I64, P],
+        "kifmm_nn_rel_l2_loss": [I32, I32, P, I32, P, P, P, P, I64, P],
+        "kifmm_nn_adam": [I64, P, P, P, P, I32, F32, F32, F32, F32, P],
+        "kifmm_nn_pack_input": [I32, I32, P, P, P, P],
+        "kifmm_nn_unpack_output": [I32, I32, P, I32, P, P, P],
+        "kifmm_nn_max_abs": [I32, I64, P, P, I32, P, I64, P],
+        "kifmm_nn_coarsen2": [I32, I32, P, P, P],
+        "kifmm_nn_upsample2": [I32, I32, P, P, P],
+        "kifmm_nn_sampled_rel_err": [I64, P, P, P, F64, P, P],
+    }
+    for f, a in nn.items():
+        getattr(lib, f).argtypes = a
     for f in ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "kifmm_tree_info",
               "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_profile_enable",
-              "kifmm_profile_read"):
+              "kifmm_profile_read") + tuple(nn):
         getattr(lib, f).restype = ctypes.c_int
     lib.kifmm_tree_destroy.restype = None
     lib.kifmm_ops_destroy.restype = None
@@ -226,3 +251,22 @@ def direct_eval(grid, kernel, I, prefactor=1.0, tgt_idx=None, out=None, fp64=Tru
                             float(prefactor), tp, int(n_tgt), ctypes.c_void_p(out.data_ptr()),
                             1 if fp64 else 0, _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------- surrogate layers
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+
+
+def nn_call(name, *args):
+    """Call a kifmm_nn_* entry point: tensors become device pointers, the last
+    argument is torch's current stream."""
+    conv = []
+    for a in args:
+        if isinstance(a, torch.Tensor):
+            conv.append(_p(a))
+        elif a is None:
+            conv.append(ctypes.c_void_p(None))
+        else:
+            conv.append(a)
+    _check(getattr(_lib, name)(*conv, _stream(None)))
