@@ -1,0 +1,253 @@
+"""Training and time-stepped serving of the learned surrogate.
+
+    python -m paper_2006_03515_amd.surrogate_tasks train [--n-train 2000] [--epochs 20] ...
+    python -m paper_2006_03515_amd.surrogate_tasks serve --checkpoint ck.npz [--steps 200] ...
+
+train: 2,000 seeded fields on a 64^3 grid (4 mm cube), each 1-4 anisotropic Gaussian
+heads (workloads.anisotropic_heads, seeds 40000 + i), targets S_ph from kifmm_eval on
+the GPU (nested layout, FP32) at 760 Torr, divided by max|I| per field (S is linear
+in I).  Adam on FP32 master weights, BF16 MFMA products, squared relative-L2 loss.
+200 held-out fields (seeds 42000 + i) are judged against the FMM.
+
+serve: 200 steps of two interacting heads on a 128^3 grid (workloads.interacting_heads).
+Per step: 2x2x2 block-mean coarsening to 64^3, surrogate inference, trilinear
+upsampling to 128^3, relative error at 1,024 sampled cells against direct_eval (the
+exact sum, FP32 kernel, FP64 sums), and kifmm_eval on the 128^3 grid whenever that
+error exceeds the tolerance.  The FMM-only loop is timed beside it.
+
+Both print one JSON line; progress goes to stderr.
+"""
+import argparse
+import json
+import multiprocessing
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+from . import workloads
+
+L_CM = 0.4
+P_TORR = 760.0
+OPTS = dict(layout=2, m0=5, check_edge=10, rcond=1e-5)
+
+
+def log(*a):
+    print("[surrogate]", *a, file=sys.stderr, flush=True)
+
+
+def _field(seed):
+    return workloads.anisotropic_heads(n=64, L=L_CM, seed=seed, p=P_TORR).I.astype(np.float32).ravel()
+
+
+def make_fields(seeds, workers=8):
+    if workers <= 1:
+        return np.stack([_field(s) for s in seeds])
+    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("fork")) as ex:
+        return np.stack(list(ex.map(_field, seeds, chunksize=16)))
+
+
+def fmm_normalised_targets(K, fields, n):
+    """kifmm_eval of every field with prefactor 1/max|I|: S / max|I| (FP32, grid order)."""
+    import torch
+    grid = K.Grid.cube(n, L_CM)
+    tree = K.build_tree(grid, 512)
+    ops = K.precompute_operators(tree, K.Kernel(workloads.p_o2_of(P_TORR)), K.Opts(**OPTS))
+    I = torch.from_numpy(fields).cuda()
+    T = torch.empty_like(I)
+    mx = np.abs(fields).max(axis=1).astype(np.float64)
+    for i in range(fields.shape[0]):
+        K.eval(tree, ops, I[i], 1.0 / mx[i], out=T[i], precision=K.FP32)
+    torch.cuda.synchronize()
+    return I, T
+
+
+def evaluate(net, I, T, n, batch=8):
+    """Relative L2 error (not squared) of the prediction against T for every field."""
+    errs = []
+    for b0 in range(0, I.shape[0], batch):
+        nb = min(batch, I.shape[0] - b0)
+        net.forward(I[b0:b0 + nb].reshape(-1), n, nb)
+        from . import kifmm as K
+        from .surrogate import HEAD_LD
+        K.nn_call("kifmm_nn_rel_l2_loss", nb, n, net._buffers(nb, n)["head"], HEAD_LD,
+                  T[b0:b0 + nb].reshape(-1), None, net.loss_buf, net.dwork, net.dwork.numel())
+        errs.extend(np.sqrt(net.loss_buf[1:1 + nb].cpu().numpy()).tolist())
+    return np.array(errs)
+
+
+def train(args):
+    n = 64
+    t0 = time.perf_counter()
+    log("generating %d + %d fields" % (args.n_train, args.n_test))
+    # CPU workers draw the inputs before this process loads the GPU runtime
+    train_f = make_fields(range(40000, 40000 + args.n_train), args.workers)
+    test_f = make_fields(range(42000, 42000 + args.n_test), args.workers)
+    t_gen = time.perf_counter() - t0
+    import torch
+    from . import kifmm as K
+    from .surrogate import Surrogate
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    Itr, Ttr = fmm_normalised_targets(K, train_f, n)
+    Ite, Tte = fmm_normalised_targets(K, test_f, n)
+    t_fmm = time.perf_counter() - t0
+    log("data: generation %.1f s, FMM targets %.1f s" % (t_gen, t_fmm))
+    net = Surrogate(seed=args.seed, bf16=not args.fp32)
+    e_init = evaluate(net, Ite, Tte, n)
+    rng = np.random.default_rng(args.seed)
+    nb = args.n_train // args.batch
+    total = args.epochs * nb
+    history = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    for ep in range(args.epochs):
+        order = rng.permutation(args.n_train)
+        losses = []
+        for b in range(nb):
+            idx = torch.from_numpy(np.sort(order[b * args.batch:(b + 1) * args.batch])).cuda()
+            lr = args.lr * 0.5 * (1 + np.cos(np.pi * it / total))
+            loss = net.loss_and_backward(Itr[idx].reshape(-1), Ttr[idx].reshape(-1), n, args.batch)
+            net.adam_step(lr)
+            losses.append(loss[0:1].clone())
+            it += 1
+        ep_loss = float(torch.cat(losses).mean().item())
+        history.append(ep_loss)
+        log("epoch %d: mean squared rel-L2 %.4e (lr %.2e, %.1f s)" % (ep, ep_loss, lr, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    e_test = evaluate(net, Ite, Tte, n)
+    e_train = evaluate(net, Itr[:200], Ttr[:200], n)
+    # inference time of one field vs one FMM evaluation at the same size
+    x = Ite[0].reshape(-1)
+    out = torch.empty_like(x)
+    for _ in range(3):
+        net.predict(x, n, 1, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        net.predict(x, n, 1, out)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t1) / 20
+    if args.checkpoint:
+        net.save(args.checkpoint)
+    rep = {"task": "surrogate_train", "grid": "64^3 / 4 mm", "p_torr": P_TORR, "n_train": args.n_train,
+           "n_test": args.n_test, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+           "params": net.nparams, "precision": "fp32" if args.fp32 else "bf16 (fp32 masters)",
+           "held_out_rel_l2": {"mean": float(e_test.mean()), "median": float(np.median(e_test)),
+                               "max": float(e_test.max()), "frac_below_1e-3": float((e_test < 1e-3).mean()),
+                               "frac_below_1e-2": float((e_test < 1e-2).mean())},
+           "untrained_rel_l2_mean": float(e_init.mean()), "train_rel_l2_mean": float(e_train.mean()),
+           "loss_history": history, "train_s": round(t_train, 2), "data_gen_s": round(t_gen, 2),
+           "fmm_targets_s": round(t_fmm, 2), "inference_ms_64": round(t_inf * 1e3, 3),
+           "samples_per_s": args.epochs * nb * args.batch / t_train}
+    print(json.dumps(rep), flush=True)
+    return rep
+
+
+def serve(args):
+    import torch
+    from . import kifmm as K
+    from .surrogate import Surrogate
+
+    torch.cuda.set_device(0)
+    n = 128
+    log("building %d sources" % args.steps)
+    src = np.stack([workloads.interacting_heads(k, n=n, L=L_CM, steps=args.steps, p=P_TORR).I.astype(np.float32)
+                    .ravel() for k in range(args.steps)])
+    Id = torch.from_numpy(src).cuda()
+    grid = K.Grid.cube(n, L_CM)
+    kern = K.Kernel(workloads.p_o2_of(P_TORR))
+    tree = K.build_tree(grid, 512)
+    ops = K.precompute_operators(tree, kern, K.Opts(**OPTS))
+    net = Surrogate(bf16=True)
+    if args.checkpoint:
+        net.load(args.checkpoint)
+    tg = torch.stack([torch.from_numpy(workloads.sample_targets(n ** 3, args.check_targets, seed=50000 + k))
+                      for k in range(args.steps)]).cuda()
+    coarse = torch.empty(64 ** 3, dtype=torch.float32, device="cuda")
+    s64 = torch.empty_like(coarse)
+    S = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    ref = torch.empty(args.check_targets, dtype=torch.float64, device="cuda")
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step_surrogate(k):
+        K.nn_call("kifmm_nn_coarsen2", 1, 64, Id[k], coarse)
+        net.predict(coarse, 64, 1, s64)
+        K.nn_call("kifmm_nn_upsample2", 1, 64, s64, S)
+        K.direct_eval(grid, kern, Id[k], 1.0, tg[k], out=ref, fp64=False)
+        K.nn_call("kifmm_nn_sampled_rel_err", args.check_targets, S, tg[k], ref, 1.0, err)
+        e = float(err.item())           # the one device -> host copy of the step
+        fb = e > args.tol
+        if fb:
+            K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
+        return e, fb
+
+    for k in range(3):   # warm-up
+        step_surrogate(k)
+        K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    errs, fbs = [], []
+    for k in range(args.steps):
+        e, fb = step_surrogate(k)
+        errs.append(e)
+        fbs.append(fb)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
+    torch.cuda.synchronize()
+    t_fmm = time.perf_counter() - t0
+    # error of the served field (surrogate or fallback) and of the FMM on the same samples
+    served, fmm_err = [], []
+    for k in range(0, args.steps, max(1, args.steps // 20)):
+        e, fb = step_surrogate(k)
+        K.direct_eval(grid, kern, Id[k], 1.0, tg[k], out=ref, fp64=False)
+        K.nn_call("kifmm_nn_sampled_rel_err", args.check_targets, S, tg[k], ref, 1.0, err)
+        served.append(float(err.item()))
+        K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
+        K.nn_call("kifmm_nn_sampled_rel_err", args.check_targets, S, tg[k], ref, 1.0, err)
+        fmm_err.append(float(err.item()))
+    errs = np.array(errs)
+    rep = {"task": "surrogate_serve", "grid": "128^3 / 4 mm, surrogate on 64^3", "steps": args.steps,
+           "tol": args.tol, "check_targets": args.check_targets,
+           "surrogate_path_steps_per_s": args.steps / t_sur, "fmm_only_steps_per_s": args.steps / t_fmm,
+           "fallback_rate": float(np.mean(fbs)),
+           "surrogate_rel_err": {"mean": float(errs.mean()), "median": float(np.median(errs)),
+                                 "min": float(errs.min()), "max": float(errs.max())},
+           "served_rel_err_max": float(np.max(served)), "fmm_rel_err_max": float(np.max(fmm_err)),
+           "checkpoint": args.checkpoint}
+    print(json.dumps(rep), flush=True)
+    return rep
+
+
+def main(argv=None):
+    """Command line entry; returns the report dict."""
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("train")
+    a.add_argument("--n-train", type=int, default=2000)
+    a.add_argument("--n-test", type=int, default=200)
+    a.add_argument("--epochs", type=int, default=20)
+    a.add_argument("--batch", type=int, default=8)
+    a.add_argument("--lr", type=float, default=1e-3)
+    a.add_argument("--seed", type=int, default=0)
+    a.add_argument("--workers", type=int, default=8)
+    a.add_argument("--fp32", action="store_true")
+    a.add_argument("--checkpoint", default="")
+    s = sub.add_parser("serve")
+    s.add_argument("--checkpoint", default="")
+    s.add_argument("--steps", type=int, default=200)
+    s.add_argument("--tol", type=float, default=1e-3)
+    s.add_argument("--check-targets", type=int, default=1024)
+    args = ap.parse_args(argv)
+    return train(args) if args.cmd == "train" else serve(args)
+
+
+if __name__ == "__main__":
+    main()

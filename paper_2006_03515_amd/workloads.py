@@ -8,6 +8,7 @@ Physical units: cm, Torr.  A source field is I(y) of eq. (Ifun) sampled at the
 cell centres x0 + (i + 1/2) h of an n^3 grid spanning [0, L]^3.
 """
 from dataclasses import dataclass
+from functools import lru_cache
 
 import numpy as np
 
@@ -55,11 +56,24 @@ def _mesh(n, L):
     return np.meshgrid(c, c, c, indexing="ij")
 
 
+@lru_cache(maxsize=4)
+def _points(n, L):
+    """(n^3, 3) cell centres in C order (cached, read-only)."""
+    P = np.stack(_mesh(n, L), -1).reshape(-1, 3)
+    P.setflags(write=False)
+    return P
+
+
+def _gauss_separable(n, L, c, sigma):
+    """exp(-|r - c|^2 / sigma^2) on the grid as an outer product of three 1D factors."""
+    x = centres(n, L)
+    ex, ey, ez = (np.exp(-((x - c[a]) / sigma) ** 2) for a in range(3))
+    return ex[:, None, None] * ey[None, :, None] * ez[None, None, :]
+
+
 def gaussian_peak(n=32, L=0.1, amp=1e20, sigma=0.01, p=760.0):
     """One Gaussian 1e20 exp(-|r-c|^2/sigma^2) at the cube centre (1 mm cube, 32^3)."""
-    X, Y, Z = _mesh(n, L)
-    c = L / 2
-    I = amp * np.exp(-((X - c) ** 2 + (Y - c) ** 2 + (Z - c) ** 2) / sigma ** 2)
+    I = amp * _gauss_separable(n, L, (L / 2,) * 3, sigma)
     return Workload("gaussian_peak_%d" % n, n, L, p, I)
 
 
@@ -67,13 +81,12 @@ def two_heads_random(n=128, L=0.4, p=760.0, seed=8):
     """Mixture of 2 Gaussian heads: centres U[L/4, 3L/4]^3, sigma U[0.005, 0.02] cm,
     amplitude log-uniform in [1e18, 1e21]."""
     rng = np.random.default_rng(seed)
-    X, Y, Z = _mesh(n, L)
     I = np.zeros((n, n, n))
     for _ in range(2):
         c = rng.uniform(L / 4, 3 * L / 4, 3)
         s = rng.uniform(0.005, 0.02)
         a = 10.0 ** rng.uniform(18, 21)
-        I += a * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / s ** 2)
+        I += a * _gauss_separable(n, L, c, s)
     return Workload("two_heads_%d" % n, n, L, p, I)
 
 
@@ -103,9 +116,8 @@ def anisotropic_heads(n=64, L=0.4, seed=40000, p=760.0):
     rotation (QR of a normal 3x3 matrix, signs fixed so det = +1), log-uniform
     amplitude in [1e18, 1e21], centres U[L/4, 3L/4]^3."""
     rng = np.random.default_rng(seed)
-    X, Y, Z = _mesh(n, L)
-    P = np.stack([X, Y, Z], -1)
-    I = np.zeros((n, n, n))
+    P = _points(n, L)
+    I = np.zeros(n ** 3)
     for _ in range(int(rng.integers(1, 5))):
         s = rng.uniform(0.003, 0.03, 3)
         Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
@@ -114,20 +126,20 @@ def anisotropic_heads(n=64, L=0.4, seed=40000, p=760.0):
             Q[:, 0] = -Q[:, 0]
         a = 10.0 ** rng.uniform(18, 21)
         c = rng.uniform(L / 4, 3 * L / 4, 3)
-        d = (P - c) @ Q
-        I += a * np.exp(-((d / s) ** 2).sum(-1))
-    return Workload("anisotropic_heads_%d_%d" % (n, seed), n, L, p, I)
+        d = (P - c) @ (Q / s)
+        d *= d
+        I += a * np.exp(-d.sum(-1))
+    return Workload("anisotropic_heads_%d_%d" % (n, seed), n, L, p, I.reshape(n, n, n))
 
 
 def interacting_heads(k, n=128, L=0.4, steps=200, p=760.0):
     """Step k of two sigma = 0.01 cm Gaussian heads (peak 1e20 each) at
     (L/2, L/2, L/2 +- d_k/2), d_k shrinking linearly from 0.2 cm to 0.03 cm."""
     d = 0.2 - 0.17 * k / (steps - 1)
-    X, Y, Z = _mesh(n, L)
     c = L / 2
     I = np.zeros((n, n, n))
     for s in (-1, 1):
-        I += 1e20 * np.exp(-((X - c) ** 2 + (Y - c) ** 2 + (Z - c - s * d / 2) ** 2) / 0.01 ** 2)
+        I += 1e20 * _gauss_separable(n, L, (c, c, c + s * d / 2), 0.01)
     return Workload("interacting_heads_%d_%d" % (n, k), n, L, p, I)
 
 
