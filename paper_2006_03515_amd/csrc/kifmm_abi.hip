@@ -407,10 +407,14 @@ int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::ve
     KIFMM_TRY(upload(db, nd, &ndd, st));
     unsigned long long *offd;
     KIFMM_TRY(db.get(&offd, (size_t)B));
-    const double tol = 1e-13;
+    // Column pairs are rotated while |a_p . a_q| > tol ||a_p|| ||a_q||.  The dot
+    // products of m-long FP64 columns carry rounding of order sqrt(m) * 1e-16, so tol
+    // sits above that floor; a last sweep whose worst pair is below 1e-10 is accepted.
+    const double tol = 1e-12;
     std::vector<unsigned long long> zeros(B, 0), offh(B);
     bool converged = false;
-    for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+    double worst = 0.0;
+    for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
         KIFMM_HIP(hipMemcpyAsync(offd, zeros.data(), B * sizeof(unsigned long long),
                                  hipMemcpyHostToDevice, st));
         for (int r = 0; r < npad - 1; ++r)
@@ -420,13 +424,16 @@ int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::ve
                                  hipMemcpyDeviceToHost, st));
         KIFMM_HIP(hipStreamSynchronize(st));
         converged = true;
+        worst = 0.0;
         for (int b = 0; b < B; ++b) {
             double v;
             std::memcpy(&v, &offh[b], sizeof(double));
+            worst = std::max(worst, v);
             if (v > tol) converged = false;
         }
     }
-    if (!converged) return fail(KIFMM_EHIP, "Jacobi SVD did not converge in 40 sweeps");
+    if (!converged && !(worst < 1e-10))
+        return fail(KIFMM_EHIP, "Jacobi SVD did not converge in 60 sweeps (worst pair " + std::to_string(worst) + ")");
     double *sig;
     KIFMM_TRY(db.get(&sig, (size_t)B * npad));
     KIFMM_TRY(launch_colnorm(A, mdd, ndd, m, (int64_t)npad * m, npad, B, sig, st));
