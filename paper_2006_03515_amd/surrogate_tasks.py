@@ -31,6 +31,7 @@ from . import workloads
 L_CM = 0.4
 P_TORR = 760.0
 OPTS = dict(layout=2, m0=5, check_edge=10, rcond=1e-5)
+LAST_NET = None   # the network of the last train() call in this process
 
 
 def log(*a):
@@ -134,6 +135,8 @@ def train(args):
     t_inf = (time.perf_counter() - t1) / 20
     if args.checkpoint:
         net.save(args.checkpoint)
+    global LAST_NET
+    LAST_NET = net
     rep = {"task": "surrogate_train", "grid": "64^3 / 4 mm", "p_torr": P_TORR, "n_train": args.n_train,
            "n_test": args.n_test, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
            "params": net.nparams, "precision": "fp32" if args.fp32 else "bf16 (fp32 masters)",
