@@ -158,6 +158,11 @@ struct kifmm_ops_s {
     __bf16 *p2pbf = nullptr, *p2pbf_lo = nullptr;
     float p2p_scale = 1.0f;            // max |near-range matrix entry| (split BF16 storage divisor)
     float *amax_q = nullptr;           // partial maxima of |q| (split BF16 near field)
+    // split low-precision copies of the inputs of the staged kernels, high parts then
+    // low parts: of q (near field, side stream) and of one level's multipole
+    // coefficients (M2L, main stream)
+    uint16_t *split_q = nullptr, *split_c = nullptr;
+    int64_t split_q_n = 0, split_c_n = 0;   // elements per part
     _Float16 *m2lh = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
@@ -226,7 +231,7 @@ static void free_ops(kifmm_ops o) {
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
-                    o->p2pbf, o->p2pbf_lo, o->amax_q};
+                    o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -772,6 +777,10 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(dmalloc(&o->cu[l], nbx * KU));
         KIFMM_TRY(dmalloc(&o->cd[l], nbx * KD));
     }
+    o->split_c_n = ((int64_t)1 << (3 * D)) * KU;
+    KIFMM_TRY(dmalloc(&o->split_c, (size_t)(2 * o->split_c_n)));
+    o->split_q_n = tree->N;
+    KIFMM_TRY(dmalloc(&o->split_q, (size_t)(2 * o->split_q_n)));
     // scratch for the tap-group split of the M2L launches: up to 64 M floats
     // (the launcher uses fewer groups when a split would not fit)
     int64_t need = 0;
@@ -788,13 +797,13 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- evaluation --
-template <typename TA, typename T>
-TapArgs<TA, T, T> tap(const TA *A, int64_t a_stride, int M, int K, const T *in, int64_t in_ld, T *out,
-                      int64_t out_ld, int mode, int nl, const TapList &tl, int cls_stride,
-                      int64_t n_per_class, int accumulate) {
-    TapArgs<TA, T, T> p{};
+template <typename TA, typename TI, typename TO>
+TapArgs<TA, TI, TO> tap(const TA *A, int64_t a_stride, int M, int K, const TI *in, int64_t in_ld, TO *out,
+                        int64_t out_ld, int mode, int nl, const TapList &tl, int cls_stride,
+                        int64_t n_per_class, int accumulate) {
+    TapArgs<TA, TI, TO> p{};
     p.A = A; p.A2 = nullptr; p.a_stride = a_stride; p.M = M; p.K = K;
-    p.in = in; p.in_ld = in_ld; p.out = out; p.out_ld = out_ld;
+    p.in = in; p.in2 = nullptr; p.in_ld = in_ld; p.out = out; p.out_ld = out_ld;
     p.mode = mode; p.nl = nl; p.nclass = tl.nclass; p.cls_stride = cls_stride;
     p.n_per_class = n_per_class; p.n_boxes = n_per_class * tl.nclass;
     p.tap_op = tl.op_dev; p.tap_off = tl.off_dev; p.ntaps = tl.ntaps;
@@ -826,6 +835,29 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
             KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
             const int64_t ldA = (int64_t)KD * KU;
+            const bool x3 = precision == KIFMM_M2L_BF16X3 || precision == KIFMM_BF16X3;
+            if (KD > 64) {   // staged kernel on the split coefficients
+                if (precision == KIFMM_M2L_FP16) {
+                    _Float16 *hi = (_Float16 *)o->split_c;
+                    KIFMM_TRY(run_split_lp<_Float16>((const float *)o->cu[l], ncu, o->amax, o->n_amax, hi, nullptr, st));
+                    auto p = tap<_Float16, _Float16>(o->m2lh + so, ldA, KD, KU, hi, KU, (float *)o->cd[l], KD, SRC_NBR,
+                                                     1 << l, o->t_m2l, 8, nper, acc);
+                    p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+                    p.part = o->part; p.part_capacity = o->part_capacity;
+                    p.pass = PASS_M2L;
+                    return run_tap_lp_staged<_Float16>(p, false, st);
+                }
+                __bf16 *hi = (__bf16 *)o->split_c, *lo = hi + o->split_c_n;
+                KIFMM_TRY(run_split_lp<__bf16>((const float *)o->cu[l], ncu, o->amax, o->n_amax, hi, x3 ? lo : nullptr, st));
+                auto p = tap<__bf16, __bf16>(o->m2lbf + so, ldA, KD, KU, hi, KU, (float *)o->cd[l], KD, SRC_NBR, 1 << l,
+                                             o->t_m2l, 8, nper, acc);
+                p.A2 = o->m2lbf_lo + so;
+                p.in2 = lo;
+                p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
+                p.part = o->part; p.part_capacity = o->part_capacity;
+                p.pass = PASS_M2L;
+                return run_tap_lp_staged<__bf16>(p, x3, st);
+            }
             if (precision == KIFMM_M2L_FP16) {
                 auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
                                               (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
@@ -840,7 +872,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
             p.part = o->part; p.part_capacity = o->part_capacity;
             p.pass = PASS_M2L;
-            return run_tap_lp<__bf16>(p, precision == KIFMM_M2L_BF16X3 || precision == KIFMM_BF16X3, st);
+            return run_tap_lp<__bf16>(p, x3, st);
         }
     }
     auto p = tap<T, T>(ops.m2l + so, (int64_t)KD * KU, KD, KU, (T *)o->cu[l], KU, (T *)o->cd[l], KD, SRC_NBR,
@@ -861,6 +893,17 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
     if constexpr (sizeof(T) == 4) {
         if (precision == KIFMM_BF16X3) {
             KIFMM_TRY(run_amax((const float *)q, nleaf * s, o->amax_q, o->n_amax, st));
+            if (s > 64) {   // staged kernel on the split sources
+                __bf16 *hi = (__bf16 *)o->split_q, *lo = hi + o->split_q_n;
+                KIFMM_TRY(run_split_lp<__bf16>((const float *)q, nleaf * s, o->amax_q, o->n_amax, hi, lo, st));
+                auto p = tap<__bf16, __bf16>(o->p2pbf, (int64_t)s * s, s, s, hi, s, (float *)out, s, SRC_NBR, nb,
+                                             o->t_p2p, 1, nleaf, 0);
+                p.A2 = o->p2pbf_lo;
+                p.in2 = lo;
+                p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
+                p.pass = PASS_P2P;
+                return run_tap_lp_staged<__bf16>(p, true, st);
+            }
             auto p = tap<__bf16, float>(o->p2pbf, (int64_t)s * s, s, s, (const float *)q, s, (float *)out, s,
                                         SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
             p.A2 = o->p2pbf_lo;

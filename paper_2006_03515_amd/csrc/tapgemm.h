@@ -11,6 +11,7 @@ struct TapArgs {
     int64_t a_stride;
     int M, K;             // padded rows / columns
     const TI *in;         // in[src * in_ld + k]
+    const TI *in2;        // staged low-precision kernel: low parts of the split input
     int64_t in_ld;
     TO *out;              // out[b * out_ld + row]
     int64_t out_ld;
@@ -60,6 +61,10 @@ int run_tap_f64(const TapArgs<double, double, double> &p, hipStream_t st);
 template <typename TL>
 int run_tap_lp(const TapArgs<TL, float, float> &p, bool x3, hipStream_t st);
 int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st);
+template <typename TL>
+int run_split_lp(const float *x, int64_t n, const float *amax, int n_amax, TL *hi, TL *lo, hipStream_t st);
+template <typename TL>
+int run_tap_lp_staged(const TapArgs<TL, TL, float> &p, bool x3, hipStream_t st);
 int run_wgrad(WgradArgs p, bool bf16, hipStream_t st);
 
 }  // namespace kifmm

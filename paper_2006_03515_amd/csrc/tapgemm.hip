@@ -13,37 +13,53 @@
 // Boxes outside the grid contribute nothing (their src is -1 and loads zeros).
 //
 // Work split: a workgroup owns an output tile (BM rows x 64 boxes of one class)
-// and a group of taps.  When the tap list is split over G groups (to put enough
-// workgroups on the 256 CUs at coarse levels) each group writes an FP32 partial
-// sum to scratch and reduce_partials adds the groups in a fixed order in FP64,
-// so results do not depend on scheduling.
+// and a group of taps.  Tiles are numbered with the row tile fastest, and each
+// XCD takes a contiguous range of tile numbers, so the workgroups resident on one
+// XCD share the source boxes of a compact region in its L2.  When the tap list is
+// split over G groups (to put enough workgroups on the 256 CUs at coarse levels)
+// each group writes an FP32 partial sum to scratch and reduce_partials adds the
+// groups in a fixed order in FP64, so results do not depend on scheduling.
 //
 // Kernels:
-//   tapgemm_f32<BM>   FP32 on MFMA (v_mfma_f32_16x16x4f32)
-//   tapgemm_lp<TL,X3> BF16 or FP16 operands on v_mfma_f32_16x16x32_{bf16,f16}
-//                     with FP32 accumulation; inputs scaled by 1/max|in| and
-//                     rounded to nearest-even when staged.  X3: split BF16 --
-//                     A = A_hi + A_lo and B = B_hi + B_lo, three products
-//                     A_hi B_hi + A_hi B_lo + A_lo B_hi (about 16 mantissa bits)
-//   tapgemm_valu<T>   LDS-tiled VALU version for FP64 (and any T)
+//   tapgemm_f32_staged      FP32 on v_mfma_f32_32x32x2f32, operators of more than
+//                           64 rows (128-row tiles)
+//   tapgemm_lp_staged<TL,NP> BF16 or FP16 operands on v_mfma_f32_32x32x16_{bf16,f16}
+//                           with FP32 accumulation.  The input is split beforehand
+//                           by split_lp_kernel: v = in / max|in|, B_hi = round(v),
+//                           B_lo = round(v - B_hi); operators are stored split the
+//                           same way.  NP = 1: A_hi B_hi; NP = 3: A_hi B_hi +
+//                           A_hi B_lo + A_lo B_hi (about 16 mantissa bits)
+//   tapgemm_f32_small       FP32 on v_mfma_f32_16x16x4f32, 64-row tiles
+//   tapgemm_lp<TL,X3>       low precision for small operators and for inputs that
+//                           are not split beforehand: the input is scaled and
+//                           rounded while it is staged through registers
+//   tapgemm_valu<T>         LDS-tiled VALU version for FP64 (and any T)
 //
-// Inside a 32-wide K chunk the reduction index is permuted so that lane group
-// q = lane / 16 owns k = 8q .. 8q+7: one 16-byte LDS read then feeds several
-// MFMA steps (the products are summed in any order, so A and B only have to use
-// the same permutation).  MFMA partial sums are folded into FP64 totals after
-// every chunk (8 chained FP32 steps), so long near-field and M2L sums keep the
-// rounding of one short chain.  The next chunk's global loads are issued before
-// the current chunk's MFMAs (register prefetch).
+// The staged kernels copy operand tiles from global memory straight into LDS
+// (global_load_lds_dwordx4), three chunks deep: while chunk c is multiplied, the
+// copies of chunks c+1 and c+2 are in flight, and one barrier per chunk hands a
+// stage from the copies to the readers.  Each thread's copies land at fixed
+// 16-byte positions; the global address a position is filled from is chosen so
+// that the tile ends up in an XOR-swizzled layout that the MFMA fragment reads
+// see without bank conflicts.
+//
+// Inside a 32-wide K chunk the reduction index is permuted so that one 16-byte
+// LDS read feeds several MFMA steps (products are summed in any order, so A and B
+// only have to use the same permutation).  MFMA partial sums are folded into FP64
+// totals every few chunks (at most 96 products per FP32 chain), so long near-field
+// and M2L sums keep the rounding of one short chain.
 #include "common.h"
 #include "tapgemm.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace kifmm {
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
@@ -71,6 +87,15 @@ __device__ inline int64_t source_box(int mode, int64_t b, int off, int nl) {
 __device__ inline int tap_op_of(const int *tab, const int *inl, int i) { return tab ? tab[i] : inl[i]; }
 
 constexpr int BN = 64;     // boxes per tile
+
+// Workgroups are dispatched round-robin over the 8 XCDs (linear id % 8), and each XCD
+// has its own L2.  Tile index of this workgroup: XCD x gets the contiguous range
+// [x * nt / 8, (x + 1) * nt / 8) of the Morton-ordered box tiles, a spatially compact
+// region, so the neighbour halos and operator tiles it reads are shared in one L2.
+__device__ inline int64_t xcd_tile(int64_t bx, int64_t nt) {
+    if (nt % 8 != 0) return bx;
+    return (bx % 8) * (nt / 8) + bx / 8;
+}
 constexpr int BK = 32;     // reduction chunk
 constexpr int APAD = 4;    // LDS row padding (floats)
 
@@ -78,8 +103,55 @@ __device__ inline float comp(const float4 &v, int e) {
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
 }
 
-template <int BM, int PASS>
-__global__ __launch_bounds__(256) void tapgemm_f32(TapArgs<float, float, float> p) {
+// s_waitcnt immediate: at most `vm` vector-memory operations outstanding, no LDS/scalar
+// operation outstanding (expcnt left free)
+constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | 0x70; }
+
+// Workgroup barrier.  The memory clobber keeps the compiler from moving loads or stores
+// across it; each wave has already waited for its own LDS reads and for its own
+// asynchronous global-to-LDS copies with s_waitcnt.
+__device__ inline void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+__device__ __align__(16) float kZeroChunk[BK];   // zero source for boxes outside the grid
+
+// asynchronous copy of 16 bytes per lane from global memory to LDS: lane l writes
+// lds + 16 l (lds is the same for the whole wave)
+__device__ inline void copy16_to_lds(const float *g, float *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
+
+// Swizzled position of the 16-byte group kq (0..7) of row r in a BK = 32 float tile:
+// 16 consecutive rows read at one kq hit 16 distinct 16-byte bank groups.
+__device__ inline int swz_slot(int r, int kq) { return r * 8 + (kq ^ ((r ^ (r >> 3)) & 7)); }
+
+// Twelve 16-byte LDS reads (byte addresses a[i]) completed before returning.  Written
+// as one asm block so that the compiler, which cannot tell these reads from the
+// asynchronous copies still in flight into other stages, adds no wait for them.
+__device__ inline void lds_read12(const int (&a)[12], float4 (&v)[12]) {
+    asm volatile(
+        "ds_read_b128 %0, %12\n"
+        "ds_read_b128 %1, %13\n"
+        "ds_read_b128 %2, %14\n"
+        "ds_read_b128 %3, %15\n"
+        "ds_read_b128 %4, %16\n"
+        "ds_read_b128 %5, %17\n"
+        "ds_read_b128 %6, %18\n"
+        "ds_read_b128 %7, %19\n"
+        "ds_read_b128 %8, %20\n"
+        "ds_read_b128 %9, %21\n"
+        "ds_read_b128 %10, %22\n"
+        "ds_read_b128 %11, %23\n"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]),
+          "=&v"(v[6]), "=&v"(v[7]), "=&v"(v[8]), "=&v"(v[9]), "=&v"(v[10]), "=&v"(v[11])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
+          "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11])
+        : "memory");
+}
+
+// FP32 tap GEMM for operators of at most 64 rows: 64 x 64 tiles on v_mfma_f32_16x16x4f32,
+// operands staged through registers into padded LDS tiles.
+template <int PASS>
+__global__ __launch_bounds__(256) void tapgemm_f32_small(TapArgs<float, float, float> p) {
+    constexpr int BM = 64;
     constexpr int IM = BM / 32;          // 16-row blocks per wave (waves: 2 x 2)
     constexpr int JN = 2;                // 16-box blocks per wave
     constexpr int AR = BM / 32;          // float4 loads of A per thread per chunk
@@ -90,8 +162,10 @@ __global__ __launch_bounds__(256) void tapgemm_f32(TapArgs<float, float, float> 
     const int cls = blockIdx.z / G, grp = blockIdx.z % G;
     const int tpg = (p.ntaps + G - 1) / G;
     const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
-    const int64_t j0 = (int64_t)blockIdx.x * BN;
-    const int m0 = blockIdx.y * BM;
+    const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
+    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j0 = lin / RT * BN;
+    const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
     const int KC = p.K / BK;
     const int total = t1 > t0 ? (t1 - t0) * KC : 0;
@@ -195,6 +269,193 @@ __global__ __launch_bounds__(256) void tapgemm_f32(TapArgs<float, float, float> 
         }
 }
 
+// Calls f(integral_constant<int, U>) for U = 0, 1, ... in order while it returns true.
+template <class F, int... U>
+__device__ inline void unrolled_steps(F &f, std::integer_sequence<int, U...>) {
+    (f(std::integral_constant<int, U>()) && ...);
+}
+
+// Waits until at most n * per vector-memory operations are outstanding (0 <= n <= 4),
+// with no LDS or scalar operation outstanding, then joins the workgroup barrier.
+template <int PER>
+__device__ inline void wait_outstanding_then_barrier(int n) {
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0)); break;
+        case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(PER)); break;
+        case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(2 * PER)); break;
+        case 3: __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(3 * PER)); break;
+        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(4 * PER)); break;
+    }
+    lds_barrier();
+}
+
+// FP32 tap GEMM on v_mfma_f32_32x32x2f32, BM = 128 rows x 64 boxes per workgroup, each
+// wave a 64 x 32 tile.  Operand tiles are copied from global memory straight into LDS
+// (global_load_lds_dwordx4) three stages deep: two chunks of copies are in flight while
+// the third chunk is multiplied.
+template <int PASS>
+__global__ __launch_bounds__(256) void tapgemm_f32_staged(TapArgs<float, float, float> p) {
+    constexpr int BM = 128;
+    constexpr int IM = 2;                    // 32-row blocks per wave (waves: 2 x 2)
+    constexpr int AR = BM * 8 / 256;         // 16-byte copies of A per thread per chunk
+    constexpr int BR = BN * 8 / 256;         // 16-byte copies of B per thread per chunk
+    constexpr int LPC = AR + BR;
+    constexpr int STG = (BM + BN) * BK;      // floats per stage: A tile then B tile
+    __shared__ __align__(16) float St[3 * STG];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = p.groups;
+    const int cls = blockIdx.z / G, grp = blockIdx.z % G;
+    const int tpg = (p.ntaps + G - 1) / G;
+    const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
+    const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
+    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j0 = lin / RT * BN;
+    const int m0 = (int)(lin % RT) * BM;
+    const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
+    const int KC = p.K / BK;
+    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
+
+    floatx16 acc[IM];
+    double tot[IM][16];
+#pragma unroll
+    for (int i = 0; i < IM; ++i) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { acc[i][v] = 0.f; tot[i][v] = 0.0; }
+    }
+
+    // this group's taps: lane i of register r holds tap t0 + 64 r + i (read with readlane)
+    int my_op[4], my_off[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = t0 + 64 * r + lane;
+        my_op[r] = t < t1 ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
+        my_off[r] = t < t1 ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
+    }
+
+    // copy r of this thread fills 16-byte position (r * 4 + wave) * 64 + lane of a tile
+    int a_off[AR], b_kq[BR];
+#pragma unroll
+    for (int r = 0; r < AR; ++r) {
+        const int pos = (r * 4 + wave) * 64 + lane, row = pos >> 3;
+        const int kq = (pos & 7) ^ ((row ^ (row >> 3)) & 7);
+        a_off[r] = min(m0 + row, p.M - 1) * p.K + kq * 4;   // rows past M are never stored
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const int pos = (r * 4 + wave) * 64 + lane, box = pos >> 3;
+        b_kq[r] = (pos & 7) ^ ((box ^ (box >> 3)) & 7);
+    }
+    const float *bsrc[BR];
+    const float *Aop = p.A;
+    auto issue = [&](int it, int stage) {
+        const int tt = it / KC, kc = it % KC;
+        if (kc == 0) {
+            int op = 0, off = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if ((tt >> 6) == r) {
+                    op = __builtin_amdgcn_readlane(my_op[r], tt & 63);
+                    off = __builtin_amdgcn_readlane(my_off[r], tt & 63);
+                }
+            Aop = p.A + (int64_t)op * p.a_stride;
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const int64_t j = j0 + (r * 4 + wave) * 8 + (lane >> 3);
+                const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+                bsrc[r] = src >= 0 ? p.in + src * p.in_ld : nullptr;
+            }
+        }
+        const int k = kc * BK;
+        float *As = St + stage * STG, *Bs = As + BM * BK;
+#pragma unroll
+        for (int r = 0; r < AR; ++r) copy16_to_lds(Aop + a_off[r] + k, As + (r * 4 + wave) * 256);
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+            copy16_to_lds(bsrc[r] ? bsrc[r] + k + b_kq[r] * 4 : kZeroChunk + b_kq[r] * 4, Bs + (r * 4 + wave) * 256);
+    };
+
+    // LDS byte addresses (stage 0) of this lane's fragments: for h = 0..3, the A rows of
+    // blocks 0 and 1 and the B column, at k = 16q + 4h .. 16q + 4h + 3
+    const int q = lane >> 5, r32 = lane & 31;
+    int fa[12];
+    {
+        const int base = (int)(uintptr_t)(__attribute__((address_space(3))) float *)St;   // LDS byte address
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int kq = 4 * q + h;
+            fa[3 * h] = base + swz_slot(wr + r32, kq) * 16;
+            fa[3 * h + 1] = base + swz_slot(wr + 32 + r32, kq) * 16;
+            fa[3 * h + 2] = base + BM * BK * 4 + swz_slot(wc + r32, kq) * 16;
+        }
+    }
+    auto compute = [&](const float4 (&fr)[12]) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < IM; ++i)
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(fr[3 * h + i], e), comp(fr[3 * h + 2], e), acc[i],
+                                                                0, 0, 0);
+    };
+    auto fold = [&]() {   // FP64 totals take the FP32 partial sums of the last NS chunks
+#pragma unroll
+        for (int i = 0; i < IM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { tot[i][v] += (double)acc[i][v]; acc[i][v] = 0.f; }
+        }
+    };
+    constexpr int NS = 3;
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+        if (u < total) issue(u, u);
+    float4 fr[12];
+    int it = 0;
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        const int c = it + u;
+        if (c >= total) return false;
+        wait_outstanding_then_barrier<LPC>(min(total - 1 - c, NS - 2));
+        int a[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a[i] = fa[i] + u * STG * 4;
+        lds_read12(a, fr);
+        if (c + NS - 1 < total) issue(c + NS - 1, (u + NS - 1) % NS);
+        compute(fr);
+        return true;
+    };
+    for (; it < total; it += NS) {
+        unrolled_steps(step, std::make_integer_sequence<int, NS>());
+        fold();
+    }
+    // D layout of 32x32x2: lane holds column lane%32 and, in registers 4g .. 4g+3,
+    // rows 8g + 4*(lane/32) + 0..3
+    const int64_t j = j0 + wc + r32;
+    if (j < p.n_per_class) {
+        const int64_t b = (int64_t)p.cls_stride * j + cls;
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int row = m0 + wr + 32 * i + 8 * g + 4 * q;
+                if (row < p.M) {
+                    double v0 = tot[i][4 * g], v1 = tot[i][4 * g + 1], v2 = tot[i][4 * g + 2], v3 = tot[i][4 * g + 3];
+                    float *o;
+                    if (G > 1) {
+                        o = p.part + ((int64_t)grp * p.n_boxes + b) * p.out_ld + row;
+                    } else {
+                        o = p.out + b * p.out_ld + row;
+                        if (p.accumulate) {
+                            const float4 old = *(const float4 *)o;
+                            v0 += old.x; v1 += old.y; v2 += old.z; v3 += old.w;
+                        }
+                    }
+                    *(float4 *)o = make_float4((float)v0, (float)v1, (float)v2, (float)v3);
+                }
+            }
+    }
+}
+
 // out[e] = (accumulate ? out[e] : 0) + sum_g part[g][e], FP64 sum in g order
 __global__ void reduce_partials(const float *__restrict__ part, int G, int64_t n, int accumulate,
                                 float *__restrict__ out) {
@@ -232,8 +493,10 @@ __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
     const int cls = blockIdx.z / G, grp = blockIdx.z % G;
     const int tpg = (p.ntaps + G - 1) / G;
     const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
-    const int64_t j0 = (int64_t)blockIdx.x * BN;
-    const int m0 = blockIdx.y * BM;
+    const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
+    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j0 = lin / RT * BN;
+    const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
     const int KC = p.K / LBK;
     const int total = t1 > t0 ? (t1 - t0) * KC : 0;
@@ -563,6 +826,233 @@ __global__ void amax_partial(const float *__restrict__ x, int64_t n, float *__re
     if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
 
+// ------------------------------------------------- staged low precision ----
+// Input split for the staged kernel: v = x / max|x|, hi = round(v), lo = round(v - hi).
+template <typename TL>
+__global__ void split_lp_kernel(const float *__restrict__ x, int64_t n, const float *__restrict__ amax, int n_amax,
+                                TL *__restrict__ hi, TL *__restrict__ lo) {
+    __shared__ float s_sh;
+    if (threadIdx.x == 0) {
+        float mx = 0.f;
+        for (int i = 0; i < n_amax; ++i) mx = fmaxf(mx, amax[i]);
+        s_sh = mx > 0.f ? 1.0f / mx : 1.0f;
+    }
+    __syncthreads();
+    const float sc = s_sh;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = x[i] * sc;
+        const TL h = (TL)v;
+        hi[i] = h;
+        if (lo) lo[i] = (TL)(v - (float)h);
+    }
+}
+
+template <typename TL>
+__device__ inline floatx16 mfma32_lp(const typename LPVec<TL>::type &a, const typename LPVec<TL>::type &b, floatx16 c) {
+    if constexpr (std::is_same<TL, __bf16>::value) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// LDS position (16-byte units) of the 8-element group kq (0..3) of row r in a 32-element
+// chunk row: 8 (and 16) consecutive rows read at one kq hit distinct bank groups.
+__device__ inline int swz4(int r, int kq) { return r * 4 + (kq ^ (((r >> 1) ^ (r >> 3)) & 3)); }
+
+__device__ inline void copy16_to_lds_b(const void *g, void *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
+
+// Six 16-byte LDS reads (byte addresses a[i]) completed before returning.
+__device__ inline void lds_read6(const int *a, float4 *v) {
+    asm volatile(
+        "ds_read_b128 %0, %6\n"
+        "ds_read_b128 %1, %7\n"
+        "ds_read_b128 %2, %8\n"
+        "ds_read_b128 %3, %9\n"
+        "ds_read_b128 %4, %10\n"
+        "ds_read_b128 %5, %11\n"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5])
+        : "memory");
+}
+
+// Low-precision tap GEMM with both operands already split (A = A_hi + A_lo stored as
+// operators, B = (B_hi + B_lo) * max|in| by split_lp_kernel): products on
+// v_mfma_f32_32x32x16_{bf16,f16} with FP32 accumulation, NP = 1 (hi only) or 3
+// (hi.hi + hi.lo + lo.hi).  BM = 128 rows x 64 boxes per workgroup, each wave 64 x 32;
+// tiles are copied global -> LDS asynchronously three stages deep, as in tapgemm_f32.
+template <typename TL, int NP, int NS, int PASS>
+__global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> p) {
+    static_assert(NS >= 3 && NS <= 6, "three to six stages");
+    typedef typename LPVec<TL>::type vec8;
+    constexpr int BM = 128, IM = 2, NPART = NP == 3 ? 2 : 1;
+    constexpr int A_BYTES = BM * 64, B_BYTES = BN * 64;                 // one part of one tile
+    constexpr int STG = NPART * (A_BYTES + B_BYTES);                      // bytes per stage
+    constexpr int LPC = NPART * 3;                                        // copies per thread per chunk
+    constexpr int NR = NPART * 6;                                         // fragment reads per chunk
+    __shared__ __align__(16) char St[NS * STG];
+    __shared__ float in_scale_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = p.groups;
+    const int cls = blockIdx.z / G, grp = blockIdx.z % G;
+    const int tpg = (p.ntaps + G - 1) / G;
+    const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
+    const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
+    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j0 = lin / RT * BN;
+    const int m0 = (int)(lin % RT) * BM;
+    const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
+    const int KC = p.K / 32;
+    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
+    if (tid == 0) {
+        float mx = 0.f;
+        for (int i = 0; i < p.n_amax; ++i) mx = fmaxf(mx, p.amax[i]);
+        in_scale_sh = mx > 0.f ? mx : 1.0f;
+    }
+
+    floatx16 acc[IM];
+    double tot[IM][16];
+#pragma unroll
+    for (int i = 0; i < IM; ++i) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { acc[i][v] = 0.f; tot[i][v] = 0.0; }
+    }
+    int my_op[4], my_off[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = t0 + 64 * r + lane;
+        my_op[r] = t < t1 ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
+        my_off[r] = t < t1 ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
+    }
+    // copy r (0, 1) of this thread fills A position (r * 4 + wave) * 64 + lane; the B
+    // position is wave * 64 + lane.  Positions are 16-byte groups.
+    int a_off[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int pos = (r * 4 + wave) * 64 + lane, row = pos >> 2;
+        const int kq = (pos & 3) ^ (((row >> 1) ^ (row >> 3)) & 3);
+        a_off[r] = min(m0 + row, p.M - 1) * p.K + kq * 8;
+    }
+    const int bpos = wave * 64 + lane, bbox = bpos >> 2;
+    const int b_kq = (bpos & 3) ^ (((bbox >> 1) ^ (bbox >> 3)) & 3);
+    int64_t bsrc = -1;
+    const TL *Ahi = p.A, *Alo = p.A2;
+    auto issue = [&](int it, int stage) {
+        const int tt = it / KC, kc = it % KC;
+        if (kc == 0) {
+            int op = 0, off = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if ((tt >> 6) == r) {
+                    op = __builtin_amdgcn_readlane(my_op[r], tt & 63);
+                    off = __builtin_amdgcn_readlane(my_off[r], tt & 63);
+                }
+            Ahi = p.A + (int64_t)op * p.a_stride;
+            if (NP == 3) Alo = p.A2 + (int64_t)op * p.a_stride;
+            const int64_t j = j0 + bbox;
+            const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+            bsrc = src >= 0 ? src * p.in_ld + b_kq * 8 : -1;
+        }
+        const int k = kc * 32;
+        char *S = St + stage * STG;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            copy16_to_lds_b(Ahi + a_off[r] + k, S + (r * 4 + wave) * 1024);
+            if (NP == 3) copy16_to_lds_b(Alo + a_off[r] + k, S + A_BYTES + (r * 4 + wave) * 1024);
+        }
+        const TL *zero = (const TL *)kZeroChunk + b_kq * 8;
+        copy16_to_lds_b(bsrc >= 0 ? p.in + bsrc + k : zero, S + NPART * A_BYTES + wave * 1024);
+        if (NP == 3) copy16_to_lds_b(bsrc >= 0 ? p.in2 + bsrc + k : zero, S + NPART * A_BYTES + B_BYTES + wave * 1024);
+    };
+
+    // fragment addresses (stage 0): [A_hi (i, s)] [A_lo (i, s)] [B_hi s] [B_lo s], k group 2q + s
+    const int q = lane >> 5, r32 = lane & 31;
+    int fa[NR];
+    {
+        const int base = (int)(uintptr_t)(__attribute__((address_space(3))) char *)St;   // LDS byte address
+        int n = 0;
+        for (int part = 0; part < NPART; ++part)
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) fa[n++] = base + part * A_BYTES + swz4(wr + 32 * i + r32, 2 * q + s) * 16;
+        for (int part = 0; part < NPART; ++part)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                fa[n++] = base + NPART * A_BYTES + part * B_BYTES + swz4(wc + r32, 2 * q + s) * 16;
+    }
+    auto as8 = [](const float4 &v) { vec8 r; __builtin_memcpy(&r, &v, 16); return r; };
+    auto compute = [&](const float4 *fr, int it) {
+        const float4 *Ah = fr, *Al = fr + 4, *Bh = fr + 4 * NPART, *Bl = fr + 4 * NPART + 2;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < IM; ++i) {
+                acc[i] = mfma32_lp<TL>(as8(Ah[2 * i + s]), as8(Bh[s]), acc[i]);
+                if (NP == 3) {
+                    acc[i] = mfma32_lp<TL>(as8(Ah[2 * i + s]), as8(Bl[s]), acc[i]);
+                    acc[i] = mfma32_lp<TL>(as8(Al[2 * i + s]), as8(Bh[s]), acc[i]);
+                }
+            }
+    };
+    auto fold = [&]() {   // FP64 totals take the FP32 partial sums of the last NS chunks
+#pragma unroll
+        for (int i = 0; i < IM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { tot[i][v] += (double)acc[i][v]; acc[i][v] = 0.f; }
+        }
+    };
+    __syncthreads();   // in_scale_sh
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+        if (u < total) issue(u, u);
+    float4 fr[NR];
+    int it = 0;
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        const int c = it + u;
+        if (c >= total) return false;
+        // chunk c has landed for every wave; chunks c+1 .. c+NS-2 may still be in flight
+        wait_outstanding_then_barrier<LPC>(min(total - 1 - c, NS - 2));
+        int a[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) a[i] = fa[i] + u * STG;
+        if constexpr (NR == 12) lds_read12(*(const int (*)[12])a, *(float4 (*)[12])fr);
+        else lds_read6(a, fr);
+        if (c + NS - 1 < total) issue(c + NS - 1, (u + NS - 1) % NS);
+        compute(fr, c);
+        return true;
+    };
+    for (; it < total; it += NS) {
+        unrolled_steps(step, std::make_integer_sequence<int, NS>());
+        fold();
+    }
+    const double oscale = (double)p.op_scale * (double)in_scale_sh;
+    const int64_t j = j0 + wc + r32;
+    if (j < p.n_per_class) {
+        const int64_t b = (int64_t)p.cls_stride * j + cls;
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int row = m0 + wr + 32 * i + 8 * g + 4 * q;
+                if (row < p.M) {
+                    double v0 = tot[i][4 * g] * oscale, v1 = tot[i][4 * g + 1] * oscale;
+                    double v2 = tot[i][4 * g + 2] * oscale, v3 = tot[i][4 * g + 3] * oscale;
+                    float *o;
+                    if (G > 1) {
+                        o = p.part + ((int64_t)grp * p.n_boxes + b) * p.out_ld + row;
+                    } else {
+                        o = p.out + b * p.out_ld + row;
+                        if (p.accumulate) {
+                            const float4 old = *(const float4 *)o;
+                            v0 += old.x; v1 += old.y; v2 += old.z; v3 += old.w;
+                        }
+                    }
+                    *(float4 *)o = make_float4((float)v0, (float)v1, (float)v2, (float)v3);
+                }
+            }
+    }
+}
+
 constexpr int64_t kTargetWGs = 2048;   // about 8 workgroups per CU
 
 template <typename TA, typename TI, typename TO>
@@ -582,7 +1072,7 @@ int choose_groups(const TapArgs<TA, TI, TO> &p, int bm) {
 template <typename TA, typename TI, typename TO, typename F>
 int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st) {
     p.groups = choose_groups(p, bm);
-    dim3 grid((unsigned)((p.n_per_class + BN - 1) / BN), (unsigned)((p.M + bm - 1) / bm),
+    dim3 grid((unsigned)(((p.n_per_class + BN - 1) / BN) * ((p.M + bm - 1) / bm)), 1u,
               (unsigned)(p.nclass * p.groups));
     hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p);
     KIFMM_HIP(hipGetLastError());
@@ -601,12 +1091,14 @@ int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st) {
 
 template <int PASS>
 int run_f32_pass(const TapArgs<float, float, float> &p, hipStream_t st) {
-    if (p.M >= 128) return launch_split(p, 128, tapgemm_f32<128, PASS>, st);
-    return launch_split(p, 64, tapgemm_f32<64, PASS>, st);
+    if (p.M > 64) return launch_split(p, 128, tapgemm_f32_staged<PASS>, st);
+    return launch_split(p, 64, tapgemm_f32_small<PASS>, st);
 }
 
 int run_tap_f32(const TapArgs<float, float, float> &p, hipStream_t st) {
     if (p.K % BK != 0) return fail(KIFMM_EINVAL, "tap GEMM: K not a multiple of 32");
+    if (p.in_ld % 4 != 0) return fail(KIFMM_EINVAL, "tap GEMM: input stride not a multiple of 4");
+    if (p.ntaps > 256) return fail(KIFMM_EINVAL, "tap GEMM: more than 256 taps");
     if (p.pass == PASS_P2P) return run_f32_pass<PASS_P2P>(p, st);
     if (p.pass == PASS_M2L) return run_f32_pass<PASS_M2L>(p, st);
     return run_f32_pass<PASS_GENERIC>(p, st);
@@ -683,5 +1175,34 @@ int run_amax(const float *x, int64_t n, float *part, int nparts, hipStream_t st)
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
+
+template <typename TL>
+int run_split_lp(const float *x, int64_t n, const float *amax, int n_amax, TL *hi, TL *lo, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(split_lp_kernel<TL>, dim3((unsigned)blocks), dim3(256), 0, st, x, n, amax, n_amax, hi, lo);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+template int run_split_lp<__bf16>(const float *, int64_t, const float *, int, __bf16 *, __bf16 *, hipStream_t);
+template int run_split_lp<_Float16>(const float *, int64_t, const float *, int, _Float16 *, _Float16 *, hipStream_t);
+
+template <typename TL, int NP, int NS>
+int run_staged_pass(const TapArgs<TL, TL, float> &p, hipStream_t st) {
+    if (p.pass == PASS_P2P) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_P2P>, st);
+    if (p.pass == PASS_M2L) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_M2L>, st);
+    return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_GENERIC>, st);
+}
+
+template <typename TL>
+int run_tap_lp_staged(const TapArgs<TL, TL, float> &p, bool x3, hipStream_t st) {
+    if (p.K % 32 != 0) return fail(KIFMM_EINVAL, "tap GEMM (staged): K not a multiple of 32");
+    if (p.in_ld % 8 != 0) return fail(KIFMM_EINVAL, "tap GEMM (staged): input stride not a multiple of 8");
+    if (p.ntaps > 256) return fail(KIFMM_EINVAL, "tap GEMM (staged): more than 256 taps");
+    if (x3) return run_staged_pass<TL, 3, 3>(p, st);
+    return run_staged_pass<TL, 1, 3>(p, st);
+}
+template int run_tap_lp_staged<__bf16>(const TapArgs<__bf16, __bf16, float> &, bool, hipStream_t);
+template int run_tap_lp_staged<_Float16>(const TapArgs<_Float16, _Float16, float> &, bool, hipStream_t);
 
 }  // namespace kifmm
