@@ -908,12 +908,17 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
         in_scale_sh = mx > 0.f ? mx : 1.0f;
     }
 
+    // NP = 3 folds the FP32 partial sums into FP64 totals every NS chunks; with NP = 1
+    // the operand rounding (2^-9 or 2^-12) dwarfs FP32 accumulation and acc is the sum
+    constexpr int NT = NP == 3 ? 16 : 1;
     floatx16 acc[IM];
-    double tot[IM][16];
+    double tot[IM][NT];
 #pragma unroll
     for (int i = 0; i < IM; ++i) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) { acc[i][v] = 0.f; tot[i][v] = 0.0; }
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+#pragma unroll
+        for (int v = 0; v < NT; ++v) tot[i][v] = 0.0;
     }
     int my_op[4], my_off[4];
 #pragma unroll
@@ -994,11 +999,17 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
             }
     };
     auto fold = [&]() {   // FP64 totals take the FP32 partial sums of the last NS chunks
+        if constexpr (NP == 3) {
 #pragma unroll
-        for (int i = 0; i < IM; ++i) {
+            for (int i = 0; i < IM; ++i) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) { tot[i][v] += (double)acc[i][v]; acc[i][v] = 0.f; }
+                for (int v = 0; v < 16; ++v) { tot[i][v] += (double)acc[i][v]; acc[i][v] = 0.f; }
+            }
         }
+    };
+    auto total_of = [&](int i, int v) -> double {
+        if constexpr (NP == 3) return tot[i][v];
+        else return (double)acc[i][v];
     };
     __syncthreads();   // in_scale_sh
 #pragma unroll
@@ -1035,8 +1046,8 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
             for (int g = 0; g < 4; ++g) {
                 const int row = m0 + wr + 32 * i + 8 * g + 4 * q;
                 if (row < p.M) {
-                    double v0 = tot[i][4 * g] * oscale, v1 = tot[i][4 * g + 1] * oscale;
-                    double v2 = tot[i][4 * g + 2] * oscale, v3 = tot[i][4 * g + 3] * oscale;
+                    double v0 = total_of(i, 4 * g) * oscale, v1 = total_of(i, 4 * g + 1) * oscale;
+                    double v2 = total_of(i, 4 * g + 2) * oscale, v3 = total_of(i, 4 * g + 3) * oscale;
                     float *o;
                     if (G > 1) {
                         o = p.part + ((int64_t)grp * p.n_boxes + b) * p.out_ld + row;
