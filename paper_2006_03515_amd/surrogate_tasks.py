@@ -206,8 +206,15 @@ def serve(args):
         K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
     torch.cuda.synchronize()
     t_fmm = time.perf_counter() - t0
-    # error of the served field (surrogate or fallback) and of the FMM on the same samples
-    served, fmm_err = [], []
+    # error of the served field (surrogate or fallback) and of the FMM on the same samples;
+    # the coarse floor is the FMM itself run on the 64^3 coarsening and upsampled the same
+    # way, i.e. the best any 64^3 predictor can do at these samples, and net_vs_coarse is
+    # the network's full-field rel-L2 against that 64^3 FMM answer
+    grid64 = K.Grid.cube(64, L_CM)
+    tree64 = K.build_tree(grid64, 512)
+    ops64 = K.precompute_operators(tree64, kern, K.Opts(**OPTS))
+    c64 = torch.empty_like(coarse)
+    served, fmm_err, floor, net_vs_coarse = [], [], [], []
     for k in range(0, args.steps, max(1, args.steps // 20)):
         e, fb = step_surrogate(k)
         K.direct_eval(grid, kern, Id[k], 1.0, tg[k], out=ref, fp64=False)
@@ -216,6 +223,14 @@ def serve(args):
         K.eval(tree, ops, Id[k], 1.0, out=S, precision=K.FP32)
         K.nn_call("kifmm_nn_sampled_rel_err", args.check_targets, S, tg[k], ref, 1.0, err)
         fmm_err.append(float(err.item()))
+        K.nn_call("kifmm_nn_coarsen2", 1, 64, Id[k], coarse)
+        K.eval(tree64, ops64, coarse, 1.0, out=c64, precision=K.FP32)
+        net.predict(coarse, 64, 1, s64)
+        net_vs_coarse.append(float(torch.linalg.vector_norm((s64 - c64).double())
+                                   / torch.linalg.vector_norm(c64.double())))
+        K.nn_call("kifmm_nn_upsample2", 1, 64, c64, S)
+        K.nn_call("kifmm_nn_sampled_rel_err", args.check_targets, S, tg[k], ref, 1.0, err)
+        floor.append(float(err.item()))
     errs = np.array(errs)
     rep = {"task": "surrogate_serve", "grid": "128^3 / 4 mm, surrogate on 64^3", "steps": args.steps,
            "tol": args.tol, "check_targets": args.check_targets,
@@ -224,6 +239,8 @@ def serve(args):
            "surrogate_rel_err": {"mean": float(errs.mean()), "median": float(np.median(errs)),
                                  "min": float(errs.min()), "max": float(errs.max())},
            "served_rel_err_max": float(np.max(served)), "fmm_rel_err_max": float(np.max(fmm_err)),
+           "coarse_floor_rel_err": {"mean": float(np.mean(floor)), "max": float(np.max(floor))},
+           "net_vs_coarse_fmm_rel_l2": {"mean": float(np.mean(net_vs_coarse)), "max": float(np.max(net_vs_coarse))},
            "checkpoint": args.checkpoint}
     print(json.dumps(rep), flush=True)
     return rep
