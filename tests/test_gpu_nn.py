@@ -54,7 +54,10 @@ def _layer_case(kind, ci, co, n_in, B, seed):
 
 @pytest.mark.parametrize("bf16,tol", [(0, 2e-6), (1, 2e-2)])
 @pytest.mark.parametrize("kind,ci,co,n_in", [("conv3", 32, 32, 8), ("conv3", 64, 32, 16), ("down2", 32, 64, 8),
-                                             ("up2", 64, 32, 4), ("up2", 128, 128, 4), ("point", 32, 64, 8)])
+                                             ("up2", 64, 32, 4), ("up2", 128, 128, 4), ("point", 32, 64, 8),
+                                             # operators of 96/160/192 rows: the 128-row staged tiles with
+                                             # rows past M clamped; 16 output boxes: a ragged box tile
+                                             ("conv3", 96, 96, 4), ("point", 96, 160, 2), ("down2", 96, 192, 4)])
 def test_layer_forward_and_gradients(K, kind, ci, co, n_in, bf16, tol):
     B = 2
     xs, w, gys, n_out = _layer_case(kind, ci, co, n_in, B, seed=ci + co + n_in)
