@@ -36,14 +36,25 @@ def test_direct_fp64_sampled_targets(K, p_o2):
     np.testing.assert_allclose(got, ref, rtol=1e-12)
 
 
-def test_direct_fp32_kernel_within_1e6(K):
+@pytest.mark.parametrize("p_o2", [150.0, 19.74, 1.974])
+def test_direct_fp32_kernel_within_1e6(K, p_o2):
+    # 1.974 Torr puts (b-a)R below 1/2 for most near pairs: the series branch of 1 - e^{-x}
     n, L = 32, 0.1
     I = gauss(n, L).astype(np.float32).astype(np.float64)
     h = (L / n,) * 3
     tg = workloads.sample_targets(n ** 3, 256, seed=12)
-    ref = odirect.direct_targets(I, h, 150.0, tg)
-    got = _run(K, I, h, 150.0, tg, fp64=False)
+    ref = odirect.direct_targets(I, h, p_o2, tg)
+    got = _run(K, I, h, p_o2, tg, fp64=False)
     assert np.max(np.abs(got / ref - 1)) < 1e-6
+
+
+def test_direct_fp32_kernel_anisotropic_all_targets(K):
+    rng = np.random.default_rng(9)
+    I = rng.random((7, 5, 300)).astype(np.float32).astype(np.float64)
+    h = (2e-3, 1e-3, 1.5e-3)
+    ref = odirect.direct_numpy(I, h, 19.74)
+    got = _run(K, I, h, 19.74, None, fp64=False)
+    assert np.max(np.abs(got / ref.ravel() - 1)) < 1e-6
 
 
 def test_direct_all_targets_ragged_anisotropic(K):
