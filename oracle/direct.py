@@ -98,23 +98,23 @@ def direct_targets(I, h, p_o2, targets, prefactor=1.0):
 def fft_full(I, h, p_o2, prefactor=1.0, workers=None):
     """The full field of the same sum by zero-padded FFT convolution.
 
-    S[i] = sum_j T[i - j + n - 1] q[j] with T the offset table of G.  Placing T
-    (length 2n-1 per axis) and q in arrays of length 2n per axis, the circular
-    convolution at positions n-1 .. 2n-2 never wraps, so it equals the linear one.
+    Per axis a of length n: S[i] = sum_j T[i - j + n - 1] q[j] with T the offset
+    table of G (length 2n-1).  Placing T and q in arrays of length 2n per axis, the
+    circular convolution at positions n-1 .. 2n-2 never wraps, so it equals the
+    linear one.  Any box shape (nx, ny, nz).
     """
     I = np.asarray(I, dtype=np.float64)
     n = I.shape
-    if not (n[0] == n[1] == n[2]):
-        raise ValueError("fft_full supports cubic grids")
-    nn = n[0]
-    T = _k.offset_table(nn, h, p_o2)
-    M = 2 * nn
+    T = _k.offset_table(n, h, p_o2)
+    M = tuple(2 * m for m in n)
     q = weights(I, h, prefactor)
     axes = (0, 1, 2)
-    Fq = scipy.fft.rfftn(q, s=(M, M, M), axes=axes, workers=workers)
-    FT = scipy.fft.rfftn(T, s=(M, M, M), axes=axes, workers=workers)
+    Fq = scipy.fft.rfftn(q, s=M, axes=axes, workers=workers)
+    del q
+    FT = scipy.fft.rfftn(T, s=M, axes=axes, workers=workers)
     del T
     Fq *= FT
     del FT
-    full = scipy.fft.irfftn(Fq, s=(M, M, M), axes=axes, workers=workers)
-    return np.ascontiguousarray(full[nn - 1:2 * nn - 1, nn - 1:2 * nn - 1, nn - 1:2 * nn - 1])
+    full = scipy.fft.irfftn(Fq, s=M, axes=axes, workers=workers)
+    del Fq
+    return np.ascontiguousarray(full[n[0] - 1:2 * n[0] - 1, n[1] - 1:2 * n[1] - 1, n[2] - 1:2 * n[2] - 1])

@@ -46,17 +46,19 @@ def self_value(hx, hy, hz, p_o2, chi_min=CHI_MIN, chi_max=CHI_MAX):
 
 
 def offset_table(n, h, p_o2, chi_min=CHI_MIN, chi_max=CHI_MAX):
-    """G over all integer cell offsets of an n^3 grid with spacing h = (hx, hy, hz).
+    """G over all integer cell offsets of an n[0] x n[1] x n[2] grid (n an int for a
+    cube) with spacing h = (hx, hy, hz).
 
-    Returns an array T of shape (2n-1,)*3 with T[d + n-1] = G(offset d), where the
-    offset d = (di, dj, dk) is in cells; the centre entry is the self value.
+    Returns an array T of shape (2n[a]-1 per axis) with T[d + n-1] = G(offset d),
+    where the offset d = (di, dj, dk) is in cells; the centre entry is the self value.
     """
+    ns = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
     hx, hy, hz = h
-    o = np.arange(-(n - 1), n, dtype=np.float64)
-    X, Y, Z = np.meshgrid(o * hx, o * hy, o * hz, indexing="ij")
+    ox, oy, oz = (np.arange(-(m - 1), m, dtype=np.float64) for m in ns)
+    X, Y, Z = np.meshgrid(ox * hx, oy * hy, oz * hz, indexing="ij", sparse=True)
     R = np.sqrt(X * X + Y * Y + Z * Z)
-    c = n - 1
-    R[c, c, c] = 1.0  # placeholder, overwritten below
+    c = tuple(m - 1 for m in ns)
+    R[c] = 1.0  # placeholder, overwritten below
     T = K(R, p_o2, chi_min, chi_max)
-    T[c, c, c] = self_value(hx, hy, hz, p_o2, chi_min, chi_max)
+    T[c] = self_value(hx, hy, hz, p_o2, chi_min, chi_max)
     return T

@@ -43,6 +43,17 @@ def test_anisotropic_cells_direct_forms_agree():
                                direct.direct_numpy(I, h, 19.74, tg), rtol=1e-13)
 
 
+def test_fft_form_on_box_shaped_grids():
+    # box-shaped grids (nx != ny != nz), isotropic and anisotropic cells: the FFT
+    # convolution equals the direct loop at every cell
+    rng = np.random.default_rng(5)
+    for shape, h in (((6, 5, 7), (2e-3, 1e-3, 1.5e-3)), ((8, 8, 4), (1.25e-3,) * 3)):
+        I = rng.random(shape)
+        full = direct.fft_full(I, h, 19.74, prefactor=0.3)
+        ref = direct.direct_numpy(I, h, 19.74, None, prefactor=0.3).reshape(shape)
+        np.testing.assert_allclose(full, ref, rtol=1e-12)
+
+
 def test_linearity_symmetry_positivity():
     rng = np.random.default_rng(5)
     n = 10
