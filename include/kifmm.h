@@ -118,7 +118,9 @@ typedef struct kifmm_ops_s *kifmm_ops;
  * leaves are cubes of ell^3 cells, ell^3 <= max_leaf (the paper's m) with ell
  * the largest power of two that fits; computes the Morton leaf order on the
  * device.  Requires nx == ny == nz, hx == hy == hz (else KIFMM_EUNSUPPORTED),
- * max_leaf >= 1.  Allocates device memory owned by the tree; *out is set only
+ * max_leaf >= 1.  A box-shaped grid of cubic cells is evaluated exactly inside
+ * the smallest such cube with zero sources outside the box (caller-side:
+ * paper_2006_03515_amd/embedding.py).  Allocates device memory owned by the tree; *out is set only
  * on success.  Synchronises `stream` before returning. */
 int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kifmm_tree *out);
 
@@ -155,7 +157,10 @@ int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefact
  * indices tgt_idx_dev[t] (device int64, each in [0, N)), or for every cell
  * t = 0..N-1 when tgt_idx_dev is NULL (then n_tgt must equal N).  I_dev is float
  * [N]; out_dev is double [n_tgt].  fp64_accumulate = 1 evaluates the kernel in
- * FP64; 0 evaluates it in FP32 (distances from integer cell offsets).  Sums are
+ * FP64; 0 evaluates it in FP32 (distances from integer cell offsets, 1/R from the
+ * hardware reciprocal square root, exponentials from the hardware base-2
+ * exponential, 1 - e^{-x} from a series below x = 1/2; per-value relative error
+ * about 1e-7).  Sums are
  * always FP64, in a fixed order (bitwise repeatable).  Any grid is accepted.
  * n_tgt = 0 is a no-op (out_dev may then be NULL).  Out-of-range indices are
  * not checked on the device: the caller guarantees them. */

@@ -147,3 +147,59 @@ def sample_targets(n_cells, count, seed):
     """`count` distinct flat cell indices drawn without replacement."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n_cells, size=min(count, n_cells), replace=False)).astype(np.int64)
+
+
+# ------------------------------------------------- the paper's Section 4 sources ----
+XI = 0.1                  # xi of eq. (Ifun), Section 4.1
+OMEGA_OVER_ALPHA = 0.6    # omega / alpha of eq. (Ifun), Section 4.1
+
+
+@dataclass
+class BoxWorkload:
+    """A source on a box-shaped grid of isotropic cells (cell centres (i + 1/2) h)."""
+    name: str
+    shape: tuple
+    h: float
+    p: float
+    p_o2: float
+    prefactor: float      # I of eq. (Ifun) = prefactor * S_i
+    S_i: np.ndarray       # ionization source on the grid
+    x0: tuple             # centre of the local error ball [cm]
+    delta: float          # its radius [cm]
+
+
+def _box_centres(shape, h):
+    return [(np.arange(m) + 0.5) * h for m in shape]
+
+
+def paper_gaussian(case=1, dtype=np.float32):
+    """Section 4.1: S_i = 1.53e25 exp(-|x - x0|^2 / sigma^2) on 320 x 320 x 160 cells,
+    case 1: 0.4 x 0.4 x 0.2 cm, sigma = 0.01 cm; case 2: 0.04 x 0.04 x 0.02 cm,
+    sigma = 0.001 cm; x0 the domain centre; 760 Torr, pO2 = 150 Torr, p_q = 30 Torr,
+    xi = 0.1, omega/alpha = 0.6; error ball radius 5 sigma."""
+    xd, zd, sigma = (0.4, 0.2, 0.01) if case == 1 else (0.04, 0.02, 0.001)
+    shape = (320, 320, 160)
+    h = xd / 320
+    cx, cy, cz = _box_centres(shape, h)
+    x0 = (xd / 2, xd / 2, zd / 2)
+    ex, ey, ez = (np.exp(-((c - x0[a]) / sigma) ** 2) for a, c in enumerate((cx, cy, cz)))
+    S = (1.53e25 * ex[:, None, None] * ey[None, :, None] * ez[None, None, :]).astype(dtype)
+    return BoxWorkload("paper_gaussian_%d" % case, shape, h, 760.0, 150.0,
+                       XI * OMEGA_OVER_ALPHA * quench(760.0), S, x0, 5 * sigma)
+
+
+def paper_multipeak(dtype=np.float32):
+    """Section 4.3: S_i = 1.53e25 sin^2(50 pi x) sin^2(50 pi y) sin^2(50 pi z) inside
+    [x_d/4, 3x_d/4] x [y_d/4, 3y_d/4] x [z_d/4, 3z_d/4], zero outside, on the grid of
+    Section 4.1 case 1; error ball radius 0.05 cm around the domain centre."""
+    xd, zd = 0.4, 0.2
+    shape = (320, 320, 160)
+    h = xd / 320
+    f = []
+    for c, d in zip(_box_centres(shape, h), (xd, xd, zd)):
+        v = np.sin(50 * np.pi * c) ** 2
+        v[(c < d / 4) | (c > 3 * d / 4)] = 0.0
+        f.append(v)
+    S = (1.53e25 * f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]).astype(dtype)
+    return BoxWorkload("paper_multipeak", shape, h, 760.0, 150.0, XI * OMEGA_OVER_ALPHA * quench(760.0), S,
+                       (xd / 2, xd / 2, zd / 2), 0.05)

@@ -1,0 +1,67 @@
+"""The paper's Section 4.1 workload at full size (320 x 320 x 160 cells, 16.4 M points),
+evaluated inside a 512^3 cube, against the oracle's exact sum in FFT form: the global and
+local relative errors E_V and E_delta of eq. (relativefun)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as odirect
+from paper_2006_03515_amd import embedding, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2006_03515_amd import kifmm
+    return kifmm
+
+
+def paper_errors(num, ref, w):
+    """E_V (over all cells) and E_delta(x0) (mean relative error over the cells within
+    delta of x0), both as fractions."""
+    ev = float(np.linalg.norm(num - ref) / np.linalg.norm(ref))
+    cx, cy, cz = [(np.arange(m) + 0.5) * w.h for m in w.shape]
+    d2 = ((cx[:, None, None] - w.x0[0]) ** 2 + (cy[None, :, None] - w.x0[1]) ** 2
+          + (cz[None, None, :] - w.x0[2]) ** 2)
+    ball = d2 <= w.delta ** 2
+    ed = float(np.mean(np.abs(num[ball] - ref[ball]) / ref[ball]))
+    return ev, ed
+
+
+def test_embedding_in_a_cube_is_exact(K):
+    # a 12 x 10 x 6 box inside a 16^3 cube with leaves of 8^3: depth 1, where the FMM is
+    # the exact sum, so the embedded evaluation must equal direct_eval on the box itself
+    rng = np.random.default_rng(21)
+    shape, h, p_o2 = (12, 10, 6), 1.25e-3, 150.0
+    I = torch.tensor(rng.random(shape).astype(np.float32), dtype=torch.float64, device="cuda")
+    n = embedding.cube_side(shape)
+    assert n == 16
+    tree = K.build_tree(K.Grid.cube(n, n * h), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5))
+    S = K.eval(tree, ops, embedding.embed(I, shape), 0.7, precision=K.FP64)
+    got = embedding.extract(S, shape).cpu().numpy()
+    ref = K.direct_eval(K.Grid(shape, (h,) * 3), K.Kernel(p_o2), I.float().reshape(-1), 0.7, None,
+                        fp64=True).cpu().numpy().reshape(shape)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+def test_section41_gaussian_full_size(K, record_property):
+    w = workloads.paper_gaussian(1)
+    ref = odirect.fft_full(w.S_i.astype(np.float64), (w.h,) * 3, w.p_o2, prefactor=w.prefactor, workers=16)
+    n = embedding.cube_side(w.shape)
+    tree = K.build_tree(K.Grid.cube(n, n * w.h), 512)
+    I = embedding.embed(torch.from_numpy(w.S_i).cuda(), w.shape)
+    kern = K.Kernel(w.p_o2)
+    # the paper's own layout (one surface each, m0 = 6) and this build's nested layout
+    cases = (("paper_m0_6", K.Opts(K.LAYOUT_PAPER, 6, 10, 1e-7), 1e-2),
+             ("nested_m0_5", K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), 1e-4))
+    for name, opts, bar in cases:
+        ops = K.precompute_operators(tree, kern, opts)
+        S = K.eval(tree, ops, I, w.prefactor, precision=K.FP32)
+        num = embedding.extract(S, w.shape).double().cpu().numpy()
+        ev, ed = paper_errors(num, ref, w)
+        record_property(name, {"E_V": ev, "E_delta": ed})
+        print("%s: E_V %.3e  E_delta %.3e" % (name, ev, ed), flush=True)
+        assert ev < bar
+        del ops
