@@ -1065,12 +1065,14 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
 }
 
 constexpr int64_t kTargetWGs = 2048;   // about 8 workgroups per CU
-
+// The staged kernels hold two workgroups per CU; launches that split their taps do
+// best with about one such wave of workgroups (measured on the 256^3 M2L levels).
+constexpr int64_t kTargetWGsStaged = 512;
 template <typename TA, typename TI, typename TO>
-int choose_groups(const TapArgs<TA, TI, TO> &p, int bm) {
+int choose_groups(const TapArgs<TA, TI, TO> &p, int bm, int64_t target) {
     if (!p.part || p.ntaps <= 1) return 1;
     const int64_t base = ((p.n_per_class + BN - 1) / BN) * ((p.M + bm - 1) / bm) * p.nclass;
-    int64_t g = (kTargetWGs + base - 1) / base;
+    int64_t g = (target + base - 1) / base;
     if (g > p.ntaps) g = p.ntaps;
     // the scratch must hold g partial outputs
     while (g > 1 && g * p.n_boxes * p.out_ld > p.part_capacity) --g;
@@ -1081,8 +1083,8 @@ int choose_groups(const TapArgs<TA, TI, TO> &p, int bm) {
 }
 
 template <typename TA, typename TI, typename TO, typename F>
-int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st) {
-    p.groups = choose_groups(p, bm);
+int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st, int64_t target = kTargetWGs) {
+    p.groups = choose_groups(p, bm, target);
     dim3 grid((unsigned)(((p.n_per_class + BN - 1) / BN) * ((p.M + bm - 1) / bm)), 1u,
               (unsigned)(p.nclass * p.groups));
     hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p);
@@ -1102,7 +1104,7 @@ int launch_split(TapArgs<TA, TI, TO> p, int bm, F kernel, hipStream_t st) {
 
 template <int PASS>
 int run_f32_pass(const TapArgs<float, float, float> &p, hipStream_t st) {
-    if (p.M > 64) return launch_split(p, 128, tapgemm_f32_staged<PASS>, st);
+    if (p.M > 64) return launch_split(p, 128, tapgemm_f32_staged<PASS>, st, kTargetWGsStaged);
     return launch_split(p, 64, tapgemm_f32_small<PASS>, st);
 }
 
@@ -1200,9 +1202,11 @@ template int run_split_lp<_Float16>(const float *, int64_t, const float *, int, 
 
 template <typename TL, int NP, int NS>
 int run_staged_pass(const TapArgs<TL, TL, float> &p, hipStream_t st) {
-    if (p.pass == PASS_P2P) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_P2P>, st);
-    if (p.pass == PASS_M2L) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_M2L>, st);
-    return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_GENERIC>, st);
+    // single-part products are cheap enough that more, smaller tap groups pay
+    const int64_t target = NP == 3 ? kTargetWGsStaged : kTargetWGs;
+    if (p.pass == PASS_P2P) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_P2P>, st, target);
+    if (p.pass == PASS_M2L) return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_M2L>, st, target);
+    return launch_split(p, 128, tapgemm_lp_staged<TL, NP, NS, PASS_GENERIC>, st, target);
 }
 
 template <typename TL>
