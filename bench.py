@@ -251,6 +251,15 @@ def main():
                     "flops_per_launch": m2l_launch, "avg_launch_ms": round(pass_ms["m2l"], 4),
                     "launches_per_step": calls_step["m2l"]}
 
+    # tree passes (permute into leaf order, and far + near field back to grid order):
+    # HBM-bound, algorithmic bytes = values read + written once
+    esz = 8 if args.precision == "fp64" else 4
+    tree_bytes = {"permute_in": 2 * N * esz, "permute_out": 3 * N * esz}
+    tree_passes = {k: {"avg_launch_ms": round(pass_ms[k], 4), "bytes": b,
+                       "GB_per_s": round(b / (pass_ms[k] * 1e-3) / 1e9, 1),
+                       "frac_of_8TBps": round(b / (pass_ms[k] * 1e-3) / PEAK_HBM, 4)}
+                   for k, b in tree_bytes.items() if k in pass_ms}
+
     variants = {}
     for v in [x for x in args.variants.split(",") if x]:
         log("timing variant %s" % v)
@@ -307,6 +316,7 @@ def main():
         "p2p_flops_per_step": p2p_flops,
         "roofline": roofline,
         "roofline_m2l": roofline_m2l,
+        "tree_passes": tree_passes,
         "variants": variants,
         "cpu_baseline": cpu,
     }

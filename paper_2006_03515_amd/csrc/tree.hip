@@ -5,8 +5,8 @@
 //     key = morton(leaf coordinates) * ell^3 + (C-order index inside the leaf)
 // Keys are distinct and cover [0, N) exactly, so sorting the cells by key is a
 // single scatter perm[key] = cell (a counting sort whose buckets hold one cell
-// each).  The layouts used by the evaluation (q and S in leaf order) index
-// through perm.
+// each).  perm is kept for callers; the evaluation's permutes recompute
+// cell = perm[p] from p by decoding the key instead of reading perm.
 #include "common.h"
 
 namespace kifmm {
@@ -27,38 +27,56 @@ __global__ void morton_scatter_kernel(int n, int ell, int lg_ell, int64_t N, int
     }
 }
 
-// q[p] = I[perm[p]] (FP32 or FP64 in, same type out)
-template <typename T>
-__global__ void permute_in_kernel(const T *__restrict__ I, const int32_t *__restrict__ perm,
-                                  int64_t N, T *__restrict__ q) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x)
-        q[p] = I[perm[p]];
+// Grid index of leaf-ordered slot p (the inverse of the key above): p = leaf * ell^3 +
+// local, leaf a Morton code of leaf coordinates, local the C-order index inside it.
+__device__ inline int64_t cell_of_slot(int64_t p, int n, int lg_ell) {
+    const int lg_s = 3 * lg_ell, mask = (1 << lg_ell) - 1;
+    const uint32_t leaf = (uint32_t)(p >> lg_s);
+    const int local = (int)(p & ((1 << lg_s) - 1));
+    int lx, ly, lz;
+    morton_decode(leaf, lx, ly, lz);
+    const int i = (lx << lg_ell) | (local >> (2 * lg_ell));
+    const int j = (ly << lg_ell) | ((local >> lg_ell) & mask);
+    const int k = (lz << lg_ell) | (local & mask);
+    return ((int64_t)i * n + j) * n + k;
 }
 
-// S[perm[p]] = scale * Sp[p]
+// q[p] = I[cell(p)] (FP32 or FP64 in, same type out)
 template <typename T>
-__global__ void permute_out_kernel(const T *__restrict__ Sp, const int32_t *__restrict__ perm,
-                                   int64_t N, T scale, T *__restrict__ S) {
+__global__ void permute_in_kernel(const T *__restrict__ I, int n, int lg_ell, int64_t N, T *__restrict__ q) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
-        S[perm[p]] = Sp[p] * scale;
+        q[p] = I[cell_of_slot(p, n, lg_ell)];
 }
 
-// S[perm[p]] = scale * (Sa[p] + Sb[p])  (far field + near field)
+// S[cell(p)] = scale * Sp[p]
 template <typename T>
-__global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb,
-                                    const int32_t *__restrict__ perm, int64_t N, T scale,
-                                    T *__restrict__ S) {
+__global__ void permute_out_kernel(const T *__restrict__ Sp, int n, int lg_ell, int64_t N, T scale,
+                                   T *__restrict__ S) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
-        S[perm[p]] = (Sa[p] + Sb[p]) * scale;
+        S[cell_of_slot(p, n, lg_ell)] = Sp[p] * scale;
+}
+
+// S[cell(p)] = scale * (Sa[p] + Sb[p])  (far field + near field)
+template <typename T>
+__global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb, int n, int lg_ell,
+                                    int64_t N, T scale, T *__restrict__ S) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x)
+        S[cell_of_slot(p, n, lg_ell)] = (Sa[p] + Sb[p]) * scale;
 }
 
 __global__ void perm_to_i64_kernel(const int32_t *perm, int64_t N, int64_t *out) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
         out[p] = perm[p];
+}
+
+int lg_of(int ell) {
+    int lg = 0;
+    while ((1 << lg) < ell) ++lg;
+    return lg;
 }
 
 unsigned grid_for(int64_t N) {
@@ -69,17 +87,15 @@ unsigned grid_for(int64_t N) {
 }  // namespace
 
 int launch_morton_scatter(const Tree &t, hipStream_t st) {
-    int lg = 0;
-    while ((1 << lg) < t.ell) ++lg;
     hipLaunchKernelGGL(morton_scatter_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.n, t.ell,
-                       lg, t.N, t.perm);
+                       lg_of(t.ell), t.N, t.perm);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
 template <typename T>
 int launch_permute_in(const Tree &t, const T *I, T *q, hipStream_t st) {
-    hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.perm,
+    hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.n, lg_of(t.ell),
                        t.N, q);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
@@ -87,7 +103,7 @@ int launch_permute_in(const Tree &t, const T *I, T *q, hipStream_t st) {
 
 template <typename T>
 int launch_permute_out(const Tree &t, const T *Sp, T scale, T *S, hipStream_t st) {
-    hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, t.perm,
+    hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, t.n, lg_of(t.ell),
                        t.N, scale, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
@@ -95,8 +111,8 @@ int launch_permute_out(const Tree &t, const T *Sp, T scale, T *S, hipStream_t st
 
 template <typename T>
 int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, T *S, hipStream_t st) {
-    hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.perm,
-                       t.N, scale, S);
+    hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.n,
+                       lg_of(t.ell), t.N, scale, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
