@@ -152,6 +152,20 @@ int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
 int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor,
                void *S_dev, int32_t precision, void *stream);
 
+/* Zero-source skipping (an addition to the method: it changes which terms are
+ * added, not their values).  With enable != 0, every later kifmm_eval with these
+ * ops marks the leaves whose sources are all exactly zero and the boxes all of whose
+ * leaves are marked (one pass over the leaf-ordered sources, before the near field
+ * starts), and the near field, P2M, M2M and M2L skip, per output tile of 64 boxes,
+ * the taps whose source boxes are all marked.  The skipped terms are exact zeros, so
+ * the result is the same sum; the FP32 partial sums are grouped differently, which
+ * changes results at rounding level.  It pays for sources that vanish on large
+ * regions (localized sources, a box-shaped grid embedded in a cube) and costs the
+ * marking pass otherwise.  The first enable allocates one byte per box of levels
+ * 2..D, owned by ops; enable = 0 turns skipping off.  FP64 evaluations and trees of
+ * depth < 2 are unaffected.  Returns 0, KIFMM_EINVAL (ops NULL) or KIFMM_ENOMEM. */
+int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable);
+
 /* Direct evaluation of the exact sum (Section 3, eq. (summation)):
  * out_dev[t] = prefactor * sum_j G(x_t, y_j) I_dev[j] hx hy hz for the flat cell
  * indices tgt_idx_dev[t] (device int64, each in [0, N)), or for every cell

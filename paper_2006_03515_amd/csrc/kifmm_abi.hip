@@ -163,6 +163,10 @@ struct kifmm_ops_s {
     // coefficients (M2L, main stream)
     uint16_t *split_q = nullptr, *split_c = nullptr;
     int64_t split_q_n = 0, split_c_n = 0;   // elements per part
+    // zero-source skipping (kifmm_ops_skip_zero_sources): per level l = 2..D, one byte per
+    // box, 1 if some leaf below it has a nonzero source (level D: the leaves themselves)
+    bool skip_zero = false;
+    std::vector<uint8_t *> nz;
     _Float16 *m2lh = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
@@ -185,6 +189,11 @@ struct kifmm_ops_s {
     double prof_ms[KIFMM_NPASS] = {};
     int64_t prof_calls[KIFMM_NPASS] = {};
 };
+
+// flags of the boxes at level l, or null when zero-source skipping is off
+static const uint8_t *nz_of(kifmm_ops o, int l) {
+    return o->skip_zero && l >= 2 && l < (int)o->nz.size() ? o->nz[l] : nullptr;
+}
 
 static void drain_profile(kifmm_ops o) {
     for (int i = 0; i < o->ev_used; ++i) {
@@ -235,6 +244,8 @@ static void free_ops(kifmm_ops o) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
+        if (p) (void)hipFree(p);
+    for (uint8_t *p : o->nz)
         if (p) (void)hipFree(p);
     for (double *p : o->cd)
         if (p) (void)hipFree(p);
@@ -844,6 +855,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                                                      1 << l, o->t_m2l, 8, nper, acc);
                     p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                     p.part = o->part; p.part_capacity = o->part_capacity;
+                    p.in_nz = nz_of(o, l);
                     p.pass = PASS_M2L;
                     return run_tap_lp_staged<_Float16>(p, false, st);
                 }
@@ -855,7 +867,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 p.in2 = lo;
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                 p.part = o->part; p.part_capacity = o->part_capacity;
-                p.pass = PASS_M2L;
+                p.in_nz = nz_of(o, l);
+                    p.pass = PASS_M2L;
                 return run_tap_lp_staged<__bf16>(p, x3, st);
             }
             if (precision == KIFMM_M2L_FP16) {
@@ -863,7 +876,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                                               (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                 p.part = o->part; p.part_capacity = o->part_capacity;
-                p.pass = PASS_M2L;
+                p.in_nz = nz_of(o, l);
+                    p.pass = PASS_M2L;
                 return run_tap_lp<_Float16>(p, false, st);
             }
             auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
@@ -871,7 +885,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             p.A2 = o->m2lbf_lo + so;
             p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
             p.part = o->part; p.part_capacity = o->part_capacity;
-            p.pass = PASS_M2L;
+            p.in_nz = nz_of(o, l);
+                    p.pass = PASS_M2L;
             return run_tap_lp<__bf16>(p, x3, st);
         }
     }
@@ -881,7 +896,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
         p.part = o->part;
         p.part_capacity = o->part_capacity;
     }
-    p.pass = PASS_M2L;
+    p.in_nz = nz_of(o, l);
+                    p.pass = PASS_M2L;
     return run(p, st);
 }
 
@@ -901,6 +917,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
                 p.A2 = o->p2pbf_lo;
                 p.in2 = lo;
                 p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
+                p.in_nz = nz_of(o, o->D);
                 p.pass = PASS_P2P;
                 return run_tap_lp_staged<__bf16>(p, true, st);
             }
@@ -908,12 +925,14 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
                                         SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
             p.A2 = o->p2pbf_lo;
             p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
-            p.pass = PASS_P2P;
+            p.in_nz = nz_of(o, o->D);
+                p.pass = PASS_P2P;
             return run_tap_lp<__bf16>(p, true, st);
         }
     }
     auto p = tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, out, s, SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
-    p.pass = PASS_P2P;
+    p.in_nz = nz_of(o, o->D);
+                p.pass = PASS_P2P;
     return run(p, st);
 }
 
@@ -921,6 +940,44 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
 //   stream st : permute in -> [fork] -> P2M -> M2M (l = D-1..2) -> for l = 2..D:
 //               L2L (l > 2) then M2L -> L2P -> [wait join] -> permute out (far + near)
 //   side      : [wait fork] -> P2P with the self cell -> [join]
+// nz[leaf] = 1 if any of the leaf's s sources is nonzero (one wave per leaf)
+template <typename T>
+__global__ void leaf_nonzero_kernel(const T *__restrict__ q, int64_t nleaf, int s, uint8_t *__restrict__ nz) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t L = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; L < nleaf;
+         L += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        bool any = false;
+        for (int i = lane; i < s; i += 64) any |= q[L * s + i] != (T)0;
+        const uint64_t m = __ballot(any);
+        if (lane == 0) nz[L] = m != 0;
+    }
+}
+
+// parent[b] = OR of the 8 children 8b .. 8b+7 (Morton order)
+__global__ void parent_nonzero_kernel(const uint8_t *__restrict__ child, int64_t nparent, uint8_t *__restrict__ parent) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nparent; b += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t v = 0;
+        for (int c = 0; c < 8; ++c) v |= child[8 * b + c];
+        parent[b] = v != 0;
+    }
+}
+
+template <typename T>
+int mark_nonzero_sources(kifmm_ops o, const T *q, hipStream_t st) {
+    const int64_t nleaf = (int64_t)o->nb * o->nb * o->nb;
+    int64_t blocks = (nleaf * 64 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(leaf_nonzero_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, q, nleaf, o->s, o->nz[o->D]);
+    KIFMM_HIP(hipGetLastError());
+    for (int l = o->D - 1; l >= 2; --l) {
+        const int64_t n = (int64_t)1 << (3 * l);
+        hipLaunchKernelGGL(parent_nonzero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, o->nz[l + 1], n,
+                           o->nz[l]);
+        KIFMM_HIP(hipGetLastError());
+    }
+    return KIFMM_OK;
+}
+
 template <typename T>
 int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, int precision,
                hipStream_t st) {
@@ -935,6 +992,7 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, q, st));
     }
+    if (o->skip_zero && D >= 2) KIFMM_TRY(mark_nonzero_sources<T>(o, q, st));
     if (D < 2) {   // every leaf is in every other leaf's near range
         {
             PassTimer pt(o, KIFMM_PASS_P2P, st);
@@ -954,14 +1012,16 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // far field: upward pass, downward pass, local expansion at the cells
     {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        KIFMM_TRY(run(tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1,
-                                nleaf, 0), st));
+        auto p = tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
+        p.in_nz = nz_of(o, D);
+        KIFMM_TRY(run(p, st));
     }
     for (int l = D - 1; l >= 2; --l) {
         const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
         PassTimer pt(o, KIFMM_PASS_M2M, st);
         auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
                            o->t_m2m, 1, (int64_t)1 << (3 * l), 0);
+        p.in_nz = nz_of(o, l + 1);
         if constexpr (sizeof(T) == 4) {
             p.part = o->part;
             p.part_capacity = o->part_capacity;
@@ -1050,6 +1110,28 @@ int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n) {
         if (ms) ms[p] = ops->prof_ms[p];
         if (calls) calls[p] = ops->prof_calls[p];
     }
+    return KIFMM_OK;
+}
+
+int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    if (!enable) {
+        ops->skip_zero = false;
+        return KIFMM_OK;
+    }
+    if (ops->D >= 2 && ops->nz.empty()) {
+        ops->nz.assign(ops->D + 1, nullptr);
+        for (int l = 2; l <= ops->D; ++l) {
+            const int rc = dmalloc(&ops->nz[l], (size_t)1 << (3 * l));
+            if (rc != KIFMM_OK) {
+                for (uint8_t *p : ops->nz)
+                    if (p) (void)hipFree(p);
+                ops->nz.clear();
+                return rc;
+            }
+        }
+    }
+    ops->skip_zero = true;
     return KIFMM_OK;
 }
 

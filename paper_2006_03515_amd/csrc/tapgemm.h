@@ -12,6 +12,8 @@ struct TapArgs {
     int M, K;             // padded rows / columns
     const TI *in;         // in[src * in_ld + k]
     const TI *in2;        // staged low-precision kernel: low parts of the split input
+    const uint8_t *in_nz; // per input box: 0 if all its values are zero (null: unknown);
+                          // the staged kernels skip taps whose sources are all zero
     int64_t in_ld;
     TO *out;              // out[b * out_ld + row]
     int64_t out_ld;

@@ -269,6 +269,62 @@ __global__ __launch_bounds__(256) void tapgemm_f32_small(TapArgs<float, float, f
         }
 }
 
+// Taps of this workgroup's group [t0, t1) whose source boxes are not all zero for the 64
+// output boxes j0 .. j0+63 of class cls (every tap when p.in_nz is null).  Returns the
+// count and leaves, in increasing order, the offsets t - t0 of those taps in lane i of
+// act[r] for the (64 r + i)-th of them.  A skipped tap adds exact zeros, so the sum over
+// the remaining taps is the same sum.  Called by all 256 threads; uses flags[256].
+template <typename TA, typename TI, typename TO>
+__device__ inline int active_taps(const TapArgs<TA, TI, TO> &p, int cls, int t0, int t1, int64_t j0,
+                                  uint8_t *flags, int (&act)[4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nt = t1 - t0;
+    if (!p.in_nz) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) act[r] = 64 * r + lane;
+        return nt > 0 ? nt : 0;
+    }
+    for (int t = t0 + wave; t < t1; t += 4) {   // one wave per tap, one lane per box
+        const int off = tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t);
+        const int64_t j = j0 + lane;
+        const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+        const bool live = src >= 0 && p.in_nz[src] != 0;
+        const uint64_t any = __ballot(live);
+        if (lane == 0) flags[t - t0] = any != 0;
+    }
+    __syncthreads();
+    // compaction, computed the same way in every wave: four 64-tap ballots, then lane L of
+    // act[r] looks up the set flag of rank 64 r + L
+    uint64_t m[4];
+    int cum[5];
+    cum[0] = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int t = 64 * c + lane;
+        m[c] = __ballot(t < nt && flags[t] != 0);
+        cum[c + 1] = cum[c] + __popcll(m[c]);
+    }
+    const int count = cum[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 64 * r + lane;
+        act[r] = 0;
+        if (k < count) {
+            const int c = (k >= cum[1]) + (k >= cum[2]) + (k >= cum[3]);
+            const int want = k - (c == 0 ? 0 : c == 1 ? cum[1] : c == 2 ? cum[2] : cum[3]);
+            const uint64_t mm = c == 0 ? m[0] : c == 1 ? m[1] : c == 2 ? m[2] : m[3];
+            int lo = 0, hi = 63;   // position of the set bit of rank `want` in mm
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (__popcll(mm & ((2ull << mid) - 1ull)) > want) hi = mid;
+                else lo = mid + 1;
+            }
+            act[r] = 64 * c + lo;
+        }
+    }
+    __syncthreads();   // flags may be reused
+    return count;
+}
+
 // Calls f(integral_constant<int, U>) for U = 0, 1, ... in order while it returns true.
 template <class F, int... U>
 __device__ inline void unrolled_steps(F &f, std::integer_sequence<int, U...>) {
@@ -313,7 +369,10 @@ __global__ __launch_bounds__(256) void tapgemm_f32_staged(TapArgs<float, float, 
     const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
     const int KC = p.K / BK;
-    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
+    __shared__ uint8_t tap_flags[256];
+    int act[4];
+    const int nact = active_taps(p, cls, t0, t1, j0, tap_flags, act);   // taps with nonzero sources
+    const int total = nact * KC;
 
     floatx16 acc[IM];
     double tot[IM][16];
@@ -323,13 +382,14 @@ __global__ __launch_bounds__(256) void tapgemm_f32_staged(TapArgs<float, float, 
         for (int v = 0; v < 16; ++v) { acc[i][v] = 0.f; tot[i][v] = 0.0; }
     }
 
-    // this group's taps: lane i of register r holds tap t0 + 64 r + i (read with readlane)
+    // this group's live taps: lane i of register r holds the (64 r + i)-th (read with readlane)
     int my_op[4], my_off[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int t = t0 + 64 * r + lane;
-        my_op[r] = t < t1 ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
-        my_off[r] = t < t1 ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
+        const int t = t0 + act[r];
+        const bool live = 64 * r + lane < nact;
+        my_op[r] = live ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
+        my_off[r] = live ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
     }
 
     // copy r of this thread fills 16-byte position (r * 4 + wave) * 64 + lane of a tile
@@ -901,7 +961,10 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
     const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
     const int KC = p.K / 32;
-    const int total = t1 > t0 ? (t1 - t0) * KC : 0;
+    __shared__ uint8_t tap_flags[256];
+    int act[4];
+    const int nact = active_taps(p, cls, t0, t1, j0, tap_flags, act);   // taps with nonzero sources
+    const int total = nact * KC;
     if (tid == 0) {
         float mx = 0.f;
         for (int i = 0; i < p.n_amax; ++i) mx = fmaxf(mx, p.amax[i]);
@@ -923,9 +986,10 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
     int my_op[4], my_off[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int t = t0 + 64 * r + lane;
-        my_op[r] = t < t1 ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
-        my_off[r] = t < t1 ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
+        const int t = t0 + act[r];
+        const bool live = 64 * r + lane < nact;
+        my_op[r] = live ? tap_op_of(p.tap_op, p.inl_op, cls * p.ntaps + t) : 0;
+        my_off[r] = live ? tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t) : 0;
     }
     // copy r (0, 1) of this thread fills A position (r * 4 + wave) * 64 + lane; the B
     // position is wave * 64 + lane.  Positions are 16-byte groups.

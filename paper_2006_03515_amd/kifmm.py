@@ -75,6 +75,7 @@ def load_library(path=LIB_PATH):
     lib.kifmm_last_error.restype = ctypes.c_char_p
     lib.kifmm_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.kifmm_profile_read.argtypes = [P, P, P, ctypes.c_int32]
+    lib.kifmm_ops_skip_zero_sources.argtypes = [P, ctypes.c_int32]
     I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     nn = {
         "kifmm_nn_layer_forward": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
@@ -186,6 +187,10 @@ class Ops:
         ku, kd = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.kifmm_ops_rank(self.handle, level, ctypes.byref(ku), ctypes.byref(kd)))
         return ku.value, kd.value
+
+    def skip_zero_sources(self, enable=True):
+        """Skip taps whose source boxes hold only zeros in later eval() calls (same sum)."""
+        _check(_lib.kifmm_ops_skip_zero_sources(self.handle, 1 if enable else 0))
 
     def profile(self, on=True):
         """Start (clearing old sums) or stop per-pass event timing of eval()."""

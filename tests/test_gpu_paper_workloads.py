@@ -65,3 +65,31 @@ def test_section41_gaussian_full_size(K, record_property):
         print("%s: E_V %.3e  E_delta %.3e" % (name, ev, ed), flush=True)
         assert ev < bar
         del ops
+
+
+def test_zero_source_skipping_is_the_same_sum(K):
+    # a box of sources in the low corner of a 64^3 cube (the rest exactly zero), plus a
+    # localized Gaussian that underflows to zero far away: skipping the all-zero source
+    # boxes changes only the grouping of FP32 partial sums
+    n, h, p_o2 = 64, 1.25e-3, 150.0
+    rng = np.random.default_rng(33)
+    I = np.zeros((n, n, n), dtype=np.float32)
+    I[:40, :24, :36] = rng.random((40, 24, 36)).astype(np.float32)
+    c = (np.arange(n) + 0.5) * h
+    g = np.exp(-((c - 0.06) / 0.002) ** 2)
+    I += (1e3 * g[:, None, None] * g[None, :, None] * g[None, None, :]).astype(np.float32)
+    It = torch.from_numpy(I.ravel()).cuda()
+    tree = K.build_tree(K.Grid.cube(n, n * h), 64)        # leaves of 4^3, depth 4
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5))
+    for prec in (K.FP32, K.BF16X3, K.M2L_FP16):
+        ops.skip_zero_sources(False)
+        a = K.eval(tree, ops, It, 1.0, precision=prec).double()
+        ops.skip_zero_sources(True)
+        b = K.eval(tree, ops, It, 1.0, precision=prec).double()
+        d = float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a))
+        assert d < 2e-6, (prec, d)
+    # against the exact sum
+    ref = odirect.fft_full(I.astype(np.float64), (h,) * 3, p_o2)
+    b = K.eval(tree, ops, It, 1.0, precision=K.FP32).double().cpu().numpy().reshape(n, n, n)
+    assert np.linalg.norm(b - ref) / np.linalg.norm(ref) < 1e-4
+    ops.skip_zero_sources(False)
