@@ -166,6 +166,20 @@ int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefact
  * depth < 2 are unaffected.  Returns 0, KIFMM_EINVAL (ops NULL) or KIFMM_ENOMEM. */
 int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable);
 
+/* Target restriction: evaluation on a part of the domain only (Section 5.1, closing
+ * remark: S_ph is often needed on a sub-region).  leaf_mask is a host array of nb^3
+ * bytes, nb = n / ell leaves per axis (ell from kifmm_tree_info), in C order
+ * [nb][nb][nb] over leaf coordinates (leaf (a, b, c) holds the cells a*ell .. a*ell+ell-1
+ * along x, and so on); nonzero marks a wanted leaf.  It is copied (the caller keeps
+ * ownership).  Every later kifmm_eval with these ops returns, at each cell of a wanted
+ * leaf, exactly what it returns without the restriction (bit for bit: the sum and its
+ * order are unchanged), and 0 at every other cell.  M2L, L2L, L2P and the near field
+ * skip, per output tile of 64 boxes, the tiles that hold no box with a wanted leaf
+ * below it; the upward pass is unchanged.  leaf_mask = NULL removes the restriction.
+ * The call synchronizes the device (flags in use by an evaluation are not
+ * overwritten).  Returns 0, KIFMM_EINVAL (ops NULL), KIFMM_ENOMEM or KIFMM_EHIP. */
+int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask);
+
 /* Direct evaluation of the exact sum (Section 3, eq. (summation)):
  * out_dev[t] = prefactor * sum_j G(x_t, y_j) I_dev[j] hx hy hz for the flat cell
  * indices tgt_idx_dev[t] (device int64, each in [0, N)), or for every cell

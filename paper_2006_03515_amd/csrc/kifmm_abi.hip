@@ -29,7 +29,7 @@ int launch_direct(const kifmm_grid *, const kifmm_kernel *, const float *, doubl
                   int64_t, double *, int, hipStream_t);
 int launch_morton_scatter(const Tree &, hipStream_t);
 template <typename T> int launch_permute_in(const Tree &, const T *, T *, hipStream_t);
-template <typename T> int launch_permute_out(const Tree &, const T *, T, T *, hipStream_t);
+template <typename T> int launch_permute_out(const Tree &, const T *, T, const uint8_t *, T *, hipStream_t);
 int launch_perm_i64(const Tree &, int64_t *, hipStream_t);
 int launch_kmat(const double *, int, const double *, int, const double *, const double *, int, int,
                 const kifmm_kernel &, double, double *, hipStream_t);
@@ -47,7 +47,8 @@ int launch_cast_pad(const double *, int, int, int64_t, T *, int, int, int64_t, i
                     hipStream_t);
 int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, int64_t, int, double,
                        hipStream_t);
-template <typename T> int launch_permute_out2(const Tree &, const T *, const T *, T, T *, hipStream_t);
+template <typename T>
+int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
 
 static std::atomic<uint64_t> g_magic{0x6b69666d6d000001ull};
 
@@ -167,6 +168,9 @@ struct kifmm_ops_s {
     // box, 1 if some leaf below it has a nonzero source (level D: the leaves themselves)
     bool skip_zero = false;
     std::vector<uint8_t *> nz;
+    // target restriction (kifmm_ops_restrict_targets): per level l = 0..D, one byte per box,
+    // 1 if some leaf below it is wanted (level D: the leaves); empty: every target is wanted
+    std::vector<uint8_t *> want;
     _Float16 *m2lh = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
@@ -193,6 +197,11 @@ struct kifmm_ops_s {
 // flags of the boxes at level l, or null when zero-source skipping is off
 static const uint8_t *nz_of(kifmm_ops o, int l) {
     return o->skip_zero && l >= 2 && l < (int)o->nz.size() ? o->nz[l] : nullptr;
+}
+
+// wanted-target flags of the boxes at level l, or null when every target is wanted
+static const uint8_t *want_of(kifmm_ops o, int l) {
+    return l >= 0 && l < (int)o->want.size() ? o->want[l] : nullptr;
 }
 
 static void drain_profile(kifmm_ops o) {
@@ -246,6 +255,8 @@ static void free_ops(kifmm_ops o) {
     for (double *p : o->cu)
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->nz)
+        if (p) (void)hipFree(p);
+    for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
     for (double *p : o->cd)
         if (p) (void)hipFree(p);
@@ -856,6 +867,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                     p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                     p.part = o->part; p.part_capacity = o->part_capacity;
                     p.in_nz = nz_of(o, l);
+                    p.out_need = want_of(o, l);
                     p.pass = PASS_M2L;
                     return run_tap_lp_staged<_Float16>(p, false, st);
                 }
@@ -868,7 +880,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                 p.part = o->part; p.part_capacity = o->part_capacity;
                 p.in_nz = nz_of(o, l);
-                    p.pass = PASS_M2L;
+                p.out_need = want_of(o, l);
+                p.pass = PASS_M2L;
                 return run_tap_lp_staged<__bf16>(p, x3, st);
             }
             if (precision == KIFMM_M2L_FP16) {
@@ -877,7 +890,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                 p.part = o->part; p.part_capacity = o->part_capacity;
                 p.in_nz = nz_of(o, l);
-                    p.pass = PASS_M2L;
+                p.out_need = want_of(o, l);
+                p.pass = PASS_M2L;
                 return run_tap_lp<_Float16>(p, false, st);
             }
             auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
@@ -886,7 +900,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
             p.part = o->part; p.part_capacity = o->part_capacity;
             p.in_nz = nz_of(o, l);
-                    p.pass = PASS_M2L;
+            p.out_need = want_of(o, l);
+            p.pass = PASS_M2L;
             return run_tap_lp<__bf16>(p, x3, st);
         }
     }
@@ -897,7 +912,8 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
         p.part_capacity = o->part_capacity;
     }
     p.in_nz = nz_of(o, l);
-                    p.pass = PASS_M2L;
+    p.out_need = want_of(o, l);
+    p.pass = PASS_M2L;
     return run(p, st);
 }
 
@@ -918,6 +934,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
                 p.in2 = lo;
                 p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
                 p.in_nz = nz_of(o, o->D);
+                p.out_need = want_of(o, o->D);
                 p.pass = PASS_P2P;
                 return run_tap_lp_staged<__bf16>(p, true, st);
             }
@@ -926,13 +943,15 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
             p.A2 = o->p2pbf_lo;
             p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
             p.in_nz = nz_of(o, o->D);
-                p.pass = PASS_P2P;
+            p.out_need = want_of(o, o->D);
+            p.pass = PASS_P2P;
             return run_tap_lp<__bf16>(p, true, st);
         }
     }
     auto p = tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, out, s, SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
     p.in_nz = nz_of(o, o->D);
-                p.pass = PASS_P2P;
+    p.out_need = want_of(o, o->D);
+    p.pass = PASS_P2P;
     return run(p, st);
 }
 
@@ -999,7 +1018,7 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
             KIFMM_TRY(p2p_pass<T>(o, ops, q, Sp, precision, st));
         }
         PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
-        return launch_permute_out<T>(*t, Sp, scale, S, st);
+        return launch_permute_out<T>(*t, Sp, scale, want_of(o, D), S, st);
     }
     // near field on the side stream
     KIFMM_HIP(hipEventRecord(o->fork, st));
@@ -1032,20 +1051,23 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         if (l > 2) {
             const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
             PassTimer pt(o, KIFMM_PASS_L2L, st);
-            KIFMM_TRY(run(tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD,
-                                    SRC_PARENT, 0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), 0), st));
+            auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
+                               0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), 0);
+        p.out_need = want_of(o, l);
+            KIFMM_TRY(run(p, st));
         }
         PassTimer pt(o, KIFMM_PASS_M2L, st);
         KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > 2 ? 1 : 0, st));
     }
     {
         PassTimer pt(o, KIFMM_PASS_L2P, st);
-        KIFMM_TRY(run(tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1,
-                                nleaf, 0), st));
+        auto p = tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
+        p.out_need = want_of(o, D);
+        KIFMM_TRY(run(p, st));
     }
     KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
     PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
-    return launch_permute_out2<T>(*t, Sp, SpN, scale, S, st);
+    return launch_permute_out2<T>(*t, Sp, SpN, scale, want_of(o, D), S, st);
 }
 
 }  // namespace
@@ -1132,6 +1154,45 @@ int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable) {
         }
     }
     ops->skip_zero = true;
+    return KIFMM_OK;
+}
+
+int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    KIFMM_HIP(hipDeviceSynchronize());   // no evaluation may still read the old flags
+    if (!leaf_mask) {
+        for (uint8_t *p : ops->want)
+            if (p) (void)hipFree(p);
+        ops->want.clear();
+        return KIFMM_OK;
+    }
+    const int D = ops->D, nb = ops->nb;
+    // host flags per level: leaves by Morton code, then each parent the OR of its 8 children
+    std::vector<std::vector<uint8_t>> h(D + 1);
+    h[D].assign((size_t)nb * nb * nb, 0);
+    for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nb; ++c)
+                h[D][morton_encode(a, b, c)] = leaf_mask[((size_t)a * nb + b) * nb + c] != 0;
+    for (int l = D - 1; l >= 0; --l) {
+        h[l].assign((size_t)1 << (3 * l), 0);
+        for (size_t i = 0; i < h[l].size(); ++i)
+            for (int k = 0; k < 8; ++k) h[l][i] |= h[l + 1][8 * i + k];
+    }
+    if (ops->want.empty()) {
+        ops->want.assign(D + 1, nullptr);
+        for (int l = 0; l <= D; ++l) {
+            const int rc = dmalloc(&ops->want[l], h[l].size());
+            if (rc != KIFMM_OK) {
+                for (uint8_t *p : ops->want)
+                    if (p) (void)hipFree(p);
+                ops->want.clear();
+                return rc;
+            }
+        }
+    }
+    for (int l = 0; l <= D; ++l)
+        KIFMM_HIP(hipMemcpy(ops->want[l], h[l].data(), h[l].size(), hipMemcpyHostToDevice));
     return KIFMM_OK;
 }
 

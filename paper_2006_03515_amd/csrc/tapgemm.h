@@ -14,6 +14,9 @@ struct TapArgs {
     const TI *in2;        // staged low-precision kernel: low parts of the split input
     const uint8_t *in_nz; // per input box: 0 if all its values are zero (null: unknown);
                           // the staged kernels skip taps whose sources are all zero
+    const uint8_t *out_need;// per output box: 0 if its values are not wanted (null: all are);
+                            // the staged kernels give a tile with no wanted box no taps
+                            // (it is written as zeros, or left as is when accumulating)
     int64_t in_ld;
     TO *out;              // out[b * out_ld + row]
     int64_t out_ld;

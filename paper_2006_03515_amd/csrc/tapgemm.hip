@@ -96,6 +96,17 @@ __device__ inline int64_t xcd_tile(int64_t bx, int64_t nt) {
     if (nt % 8 != 0) return bx;
     return (bx % 8) * (nt / 8) + bx / 8;
 }
+
+// Tile of block bx for launches that skip work by box flags (zero sources, unwanted
+// targets): the skipped tiles cluster in Morton ranges, so one contiguous eighth per XCD
+// could leave most XCDs idle.  Each XCD takes every 8th run of 8 box tiles (rt row tiles
+// each) instead, which keeps neighbouring boxes in one L2 and spreads the work.
+__device__ inline int64_t sparse_tile(int64_t bx, int64_t nt, int rt) {
+    const int64_t run = 8 * (int64_t)rt;
+    if (nt % (8 * run) != 0) return bx;
+    const int64_t k = bx % 8, i = bx / 8;
+    return ((i / run) * 8 + k) * run + i % run;
+}
 constexpr int BK = 32;     // reduction chunk
 constexpr int APAD = 4;    // LDS row padding (floats)
 
@@ -273,11 +284,21 @@ __global__ __launch_bounds__(256) void tapgemm_f32_small(TapArgs<float, float, f
 // output boxes j0 .. j0+63 of class cls (every tap when p.in_nz is null).  Returns the
 // count and leaves, in increasing order, the offsets t - t0 of those taps in lane i of
 // act[r] for the (64 r + i)-th of them.  A skipped tap adds exact zeros, so the sum over
-// the remaining taps is the same sum.  Called by all 256 threads; uses flags[256].
+// the remaining taps is the same sum.  None of the taps is kept when p.out_need marks
+// none of the 64 output boxes as wanted.  Called by all 256 threads; uses flags[256].
 template <typename TA, typename TI, typename TO>
 __device__ inline int active_taps(const TapArgs<TA, TI, TO> &p, int cls, int t0, int t1, int64_t j0,
                                   uint8_t *flags, int (&act)[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nt = t1 - t0;
+    if (p.out_need) {   // every wave takes the same ballot, so all return together or none
+        const int64_t j = j0 + lane;
+        const bool want = j < p.n_per_class && p.out_need[(int64_t)p.cls_stride * j + cls] != 0;
+        if (__ballot(want) == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) act[r] = 0;
+            return 0;
+        }
+    }
     if (!p.in_nz) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) act[r] = 64 * r + lane;
@@ -364,7 +385,8 @@ __global__ __launch_bounds__(256) void tapgemm_f32_staged(TapArgs<float, float, 
     const int tpg = (p.ntaps + G - 1) / G;
     const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
     const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
-    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t lin = p.in_nz || p.out_need ? sparse_tile(blockIdx.x, gridDim.x, RT)
+                                              : xcd_tile(blockIdx.x, gridDim.x);
     const int64_t j0 = lin / RT * BN;
     const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
@@ -956,7 +978,8 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
     const int tpg = (p.ntaps + G - 1) / G;
     const int t0 = grp * tpg, t1 = min(p.ntaps, t0 + tpg);
     const int RT = (p.M + BM - 1) / BM;                 // row tiles: the fastest tile index
-    const int64_t lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t lin = p.in_nz || p.out_need ? sparse_tile(blockIdx.x, gridDim.x, RT)
+                                              : xcd_tile(blockIdx.x, gridDim.x);
     const int64_t j0 = lin / RT * BN;
     const int m0 = (int)(lin % RT) * BM;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;

@@ -49,22 +49,29 @@ __global__ void permute_in_kernel(const T *__restrict__ I, int n, int lg_ell, in
         q[p] = I[cell_of_slot(p, n, lg_ell)];
 }
 
-// S[cell(p)] = scale * Sp[p]
+// S[cell(p)] = scale * Sp[p], or 0 where want (one byte per leaf, Morton order; null: every
+// leaf is wanted) marks the leaf of slot p as not wanted
 template <typename T>
 __global__ void permute_out_kernel(const T *__restrict__ Sp, int n, int lg_ell, int64_t N, T scale,
-                                   T *__restrict__ S) {
+                                   const uint8_t *__restrict__ want, T *__restrict__ S) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x)
-        S[cell_of_slot(p, n, lg_ell)] = Sp[p] * scale;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        T v = 0;
+        if (!want || want[p >> (3 * lg_ell)]) v = Sp[p] * scale;
+        S[cell_of_slot(p, n, lg_ell)] = v;
+    }
 }
 
-// S[cell(p)] = scale * (Sa[p] + Sb[p])  (far field + near field)
+// S[cell(p)] = scale * (Sa[p] + Sb[p])  (far field + near field), 0 where not wanted
 template <typename T>
 __global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb, int n, int lg_ell,
-                                    int64_t N, T scale, T *__restrict__ S) {
+                                    int64_t N, T scale, const uint8_t *__restrict__ want, T *__restrict__ S) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x)
-        S[cell_of_slot(p, n, lg_ell)] = (Sa[p] + Sb[p]) * scale;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        T v = 0;
+        if (!want || want[p >> (3 * lg_ell)]) v = (Sa[p] + Sb[p]) * scale;
+        S[cell_of_slot(p, n, lg_ell)] = v;
+    }
 }
 
 __global__ void perm_to_i64_kernel(const int32_t *perm, int64_t N, int64_t *out) {
@@ -102,24 +109,25 @@ int launch_permute_in(const Tree &t, const T *I, T *q, hipStream_t st) {
 }
 
 template <typename T>
-int launch_permute_out(const Tree &t, const T *Sp, T scale, T *S, hipStream_t st) {
+int launch_permute_out(const Tree &t, const T *Sp, T scale, const uint8_t *want, T *S, hipStream_t st) {
     hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, t.n, lg_of(t.ell),
-                       t.N, scale, S);
+                       t.N, scale, want, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
 template <typename T>
-int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, T *S, hipStream_t st) {
+int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, const uint8_t *want, T *S,
+                        hipStream_t st) {
     hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.n,
-                       lg_of(t.ell), t.N, scale, S);
+                       lg_of(t.ell), t.N, scale, want, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
-template int launch_permute_out2<float>(const Tree &, const float *, const float *, float, float *,
-                                        hipStream_t);
+template int launch_permute_out2<float>(const Tree &, const float *, const float *, float, const uint8_t *,
+                                        float *, hipStream_t);
 template int launch_permute_out2<double>(const Tree &, const double *, const double *, double,
-                                         double *, hipStream_t);
+                                         const uint8_t *, double *, hipStream_t);
 
 int launch_perm_i64(const Tree &t, int64_t *out, hipStream_t st) {
     hipLaunchKernelGGL(perm_to_i64_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.perm, t.N,
@@ -130,8 +138,9 @@ int launch_perm_i64(const Tree &t, int64_t *out, hipStream_t st) {
 
 template int launch_permute_in<float>(const Tree &, const float *, float *, hipStream_t);
 template int launch_permute_in<double>(const Tree &, const double *, double *, hipStream_t);
-template int launch_permute_out<float>(const Tree &, const float *, float, float *, hipStream_t);
-template int launch_permute_out<double>(const Tree &, const double *, double, double *,
+template int launch_permute_out<float>(const Tree &, const float *, float, const uint8_t *, float *,
+                                       hipStream_t);
+template int launch_permute_out<double>(const Tree &, const double *, double, const uint8_t *, double *,
                                         hipStream_t);
 
 }  // namespace kifmm

@@ -9,6 +9,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,6 +25,7 @@ CHI_MIN, CHI_MAX = 0.035, 2.0
 EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "kifmm_tree_info",
            "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_tree_destroy",
            "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read",
+           "kifmm_ops_skip_zero_sources", "kifmm_ops_restrict_targets",
            "kifmm_nn_layer_forward", "kifmm_nn_layer_backward_data", "kifmm_nn_layer_backward_weight",
            "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
            "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
@@ -76,6 +78,7 @@ def load_library(path=LIB_PATH):
     lib.kifmm_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.kifmm_profile_read.argtypes = [P, P, P, ctypes.c_int32]
     lib.kifmm_ops_skip_zero_sources.argtypes = [P, ctypes.c_int32]
+    lib.kifmm_ops_restrict_targets.argtypes = [P, P]
     I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     nn = {
         "kifmm_nn_layer_forward": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
@@ -191,6 +194,19 @@ class Ops:
     def skip_zero_sources(self, enable=True):
         """Skip taps whose source boxes hold only zeros in later eval() calls (same sum)."""
         _check(_lib.kifmm_ops_skip_zero_sources(self.handle, 1 if enable else 0))
+
+    def restrict_targets(self, leaf_mask=None):
+        """Evaluate only at the leaves marked in leaf_mask (array of nb^3 values, C order
+        over leaf coordinates, nonzero = wanted); later eval() calls return 0 elsewhere.
+        None evaluates every target again."""
+        if leaf_mask is None:
+            _check(_lib.kifmm_ops_restrict_targets(self.handle, None))
+            return
+        nb = self.tree.grid.n[0] // self.tree.leaf_side
+        m = np.ascontiguousarray(np.asarray(leaf_mask).reshape(-1) != 0, dtype=np.uint8)
+        if m.size != nb ** 3:
+            raise ValueError("leaf_mask has %d values, the tree has %d leaves" % (m.size, nb ** 3))
+        _check(_lib.kifmm_ops_restrict_targets(self.handle, ctypes.c_void_p(m.ctypes.data)))
 
     def profile(self, on=True):
         """Start (clearing old sums) or stop per-pass event timing of eval()."""

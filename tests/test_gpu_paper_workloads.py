@@ -93,3 +93,35 @@ def test_zero_source_skipping_is_the_same_sum(K):
     b = K.eval(tree, ops, It, 1.0, precision=K.FP32).double().cpu().numpy().reshape(n, n, n)
     assert np.linalg.norm(b - ref) / np.linalg.norm(ref) < 1e-4
     ops.skip_zero_sources(False)
+
+
+@pytest.mark.parametrize("max_leaf", [64, 512])
+def test_target_restriction_is_exact_inside_and_zero_outside(K, max_leaf):
+    # sources in a box at the low corner of a 64^3 cube; targets restricted to the leaves
+    # that meet the box, then to a random set of leaves: at wanted leaves the values are
+    # the unrestricted evaluation's, bit for bit, and 0 elsewhere
+    n, h, p_o2 = 64, 1.25e-3, 150.0
+    shape = (40, 24, 36)
+    rng = np.random.default_rng(34)
+    I = np.zeros((n, n, n), dtype=np.float32)
+    I[:shape[0], :shape[1], :shape[2]] = rng.random(shape).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, n * h), max_leaf)
+    ell, nb = tree.leaf_side, n // tree.leaf_side
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5))
+    masks = [embedding.leaf_mask(shape, n, ell),
+             (rng.random((nb, nb, nb)) < 0.15).astype(np.uint8)]
+    for skip in (False, True):
+        ops.skip_zero_sources(skip)
+        for prec in (K.FP64, K.FP32, K.BF16X3, K.M2L_FP16):
+            dt = torch.float64 if prec == K.FP64 else torch.float32
+            It = torch.from_numpy(I.ravel()).to(dt).cuda()
+            ops.restrict_targets(None)
+            a = K.eval(tree, ops, It, 1.0, precision=prec).reshape(n, n, n)
+            for m in masks:
+                ops.restrict_targets(m)
+                b = K.eval(tree, ops, It, 1.0, precision=prec).reshape(n, n, n)
+                cells = torch.from_numpy(np.kron(m, np.ones((ell,) * 3, dtype=np.uint8)) != 0).cuda()
+                assert torch.equal(b[cells], a[cells]), (skip, prec)
+                assert int(torch.count_nonzero(b[~cells])) == 0, (skip, prec)
+    ops.restrict_targets(None)
+    ops.skip_zero_sources(False)
