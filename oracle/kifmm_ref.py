@@ -32,6 +32,11 @@ three layouts are provided, all in units of the box half-width r:
             check_edge^3 lattice filling [-1.05 r, 1.05 r]^3
   'nested'  as 'single' but y^u adds an m0 surface at 0.55 r and y^d adds an
             m0 surface at 4 r
+  'lattice' y^u and x^d: the full m0^3 lattice filling [-1.4 r, 1.4 r]^3; x^u as in
+            'single'; y^d as in 'nested'.  Equivalent points and M2L check points
+            then lie on lattices of one spacing, so each M2L matrix G(x^d, y^u + 2 r o)
+            is a block of a 3-D convolution (the FFT form of M2L, Section 3 remark);
+            here it is still applied as the plain matrix
 """
 import itertools
 
@@ -39,7 +44,7 @@ import numpy as np
 
 from . import kernel as _k
 
-LAYOUTS = ("paper", "single", "nested")
+LAYOUTS = ("paper", "single", "nested", "lattice")
 
 
 def cube_surface(m, rad):
@@ -69,6 +74,9 @@ def point_sets(layout, m0, check_edge, r):
         yu = np.vstack([cube_surface(m0, 1.05 * r), cube_surface(m0, 0.55 * r)])
         yd = np.vstack([cube_surface(m0, 2.95 * r), cube_surface(m0, 4.0 * r)])
         return yu, xu, yd, xd
+    if layout == "lattice":
+        yd = np.vstack([cube_surface(m0, 2.95 * r), cube_surface(m0, 4.0 * r)])
+        return cube_lattice(m0, 1.4 * r), xu, yd, cube_lattice(m0, 1.4 * r)
     raise ValueError(layout)
 
 
