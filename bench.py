@@ -144,12 +144,18 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--p", type=float, default=760.0, help="air pressure [Torr]")
     ap.add_argument("--max-leaf", type=int, default=512)
-    ap.add_argument("--layout", default="nested", choices=["paper", "single", "nested"])
+    ap.add_argument("--layout", default="lattice", choices=["paper", "single", "nested", "lattice"])
+    ap.add_argument("--lattice-radius", type=float, default=1.0,
+                    help="lattice layout: half-width of its point lattices in box half-widths (1.0 "
+                         "measured best for 760 Torr air; 0 = the library default 1.2, robust over pressures)")
+    ap.add_argument("--m2l", default="fft", choices=["fft", "dense"],
+                    help="M2L form for the lattice layout (the other layouts have only the dense form)")
     ap.add_argument("--rcond", type=float, default=1e-5)
     ap.add_argument("--m0", type=int, default=5)
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--variants", default="bf16x3,m2l_bf16x3,m2l_fp16,m2l_bf16",
-                    help="extra precisions timed after the headline one ('' for none)")
+    ap.add_argument("--variants", default="bf16x3,fp32/dense,bf16x3/dense,m2l_bf16x3,m2l_fp16,m2l_bf16",
+                    help="extra precisions timed after the headline one ('' for none); "
+                         "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout)")
     ap.add_argument("--check-targets", type=int, default=4096)
     ap.add_argument("--cpu-targets", type=int, default=2048,
                     help="targets of the oracle CPU baseline sample (0 = skip)")
@@ -178,14 +184,18 @@ def main():
     I = torch.from_numpy(I_host).to(dev)
     grid = K.Grid.cube(w.n, w.L)
     kern = K.Kernel(w.p_o2)
-    layout = {"paper": K.LAYOUT_PAPER, "single": K.LAYOUT_SINGLE, "nested": K.LAYOUT_NESTED}[args.layout]
-    opts = K.Opts(layout, args.m0, 10, args.rcond)
+    layout = {"paper": K.LAYOUT_PAPER, "single": K.LAYOUT_SINGLE, "nested": K.LAYOUT_NESTED,
+              "lattice": K.LAYOUT_LATTICE}[args.layout]
+    opts = K.Opts(layout, args.m0, 10, args.rcond, args.lattice_radius)
 
     t0 = time.perf_counter()
     tree = K.build_tree(grid, args.max_leaf)
     ops = K.precompute_operators(tree, kern, opts)
     torch.cuda.synchronize()
     t_pre = time.perf_counter() - t0
+    m2l_form = args.m2l if args.layout == "lattice" else "dense"
+    if args.layout == "lattice":
+        ops.m2l_fft(m2l_form == "fft")
     ranks = {l: ops.rank(l) for l in range(2, tree.depth + 1)}
     log("tree depth %d, leaf %d^3, precompute %.2f s, ranks %s" % (tree.depth, tree.leaf_side, t_pre, ranks))
 
@@ -232,7 +242,14 @@ def main():
     N = w.n ** 3
     nb, s = tree.grid.n[0] // tree.leaf_side, tree.leaf_side ** 3
     p2p_flops = 2.0 * near_pairs(nb, s)
-    m2l_flops = sum(2.0 * m2l_pairs(l) * ranks[l][0] * ranks[l][1] for l in ranks)
+    if m2l_form == "fft":
+        # FFT form: coefficients -> half spectra and back (two GEMMs per box), plus one
+        # complex multiply-add (8 flops) per interaction pair and frequency
+        nf = (2 * args.m0 - 1) ** 2 * args.m0
+        m2l_flops = sum(2.0 * 8 ** l * 2 * nf * (ranks[l][0] + ranks[l][1]) + 8.0 * m2l_pairs(l) * nf
+                        for l in ranks)
+    else:
+        m2l_flops = sum(2.0 * m2l_pairs(l) * ranks[l][0] * ranks[l][1] for l in ranks)
     pass_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}        # mean per launch
     pass_step = {k: v[0] / args.steps for k, v in prof.items()}       # per step
     calls_step = {k: v[1] / args.steps for k, v in prof.items()}
@@ -246,7 +263,8 @@ def main():
                 "avg_launch_ms": round(pass_ms["p2p"], 4)}
     m2l_launch = m2l_flops / max(calls_step["m2l"], 1)
     m2l_ach = m2l_launch / (pass_ms["m2l"] * 1e-3) / 1e12
-    roofline_m2l = {"bound": "mfma", "kernel": "m2l (all levels)", "achieved": round(m2l_ach, 3),
+    roofline_m2l = {"bound": "mfma" if m2l_form == "dense" else "alu",
+                    "kernel": "m2l (all levels, %s form)" % m2l_form, "achieved": round(m2l_ach, 3),
                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(m2l_ach * 1e12 / peak, 4),
                     "flops_per_launch": m2l_launch, "avg_launch_ms": round(pass_ms["m2l"], 4),
                     "launches_per_step": calls_step["m2l"]}
@@ -263,8 +281,13 @@ def main():
     variants = {}
     for v in [x for x in args.variants.split(",") if x]:
         log("timing variant %s" % v)
-        vms, _ = timed(v, args.steps, args.warmup, profile=False)
+        prec, _, form = v.partition("/")
+        if form and args.layout == "lattice":
+            ops.m2l_fft(form == "fft")
+        vms, _ = timed(prec, args.steps, args.warmup, profile=False)
         variants[v] = {"value": N / (vms * 1e-3), "ms_per_step": round(vms, 4), "rel_l2": accuracy()}
+        if args.layout == "lattice":
+            ops.m2l_fft(m2l_form == "fft")
 
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device=dev)
@@ -306,7 +329,9 @@ def main():
         "config": {"workload": "streamer_channel_%d" % w.n, "n": w.n, "L_cm": w.L, "p_torr": w.p,
                    "p_o2_torr": w.p_o2, "layout": args.layout, "m0": args.m0, "check_edge": 10,
                    "rcond": args.rcond, "max_leaf": args.max_leaf, "leaf_side": tree.leaf_side,
-                   "depth": tree.depth, "precision": args.precision, "parallelism": "none"},
+                   "depth": tree.depth, "precision": args.precision, "m2l": m2l_form,
+                   "lattice_radius": (args.lattice_radius or 1.2) if args.layout == "lattice" else None,
+                   "parallelism": "none"},
         "rel_l2_sampled": err,
         "accuracy_ok": err <= 1e-4,
         "pair_interactions_per_s": near_pairs(nb, s) / (ms * 1e-3),

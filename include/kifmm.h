@@ -81,16 +81,23 @@ typedef struct {
  *                        downward check: check_edge^3 lattice on [-1.05 r, 1.05 r]^3.
  *   KIFMM_LAYOUT_NESTED: as SINGLE plus a second m0 surface at 0.55 r (upward
  *                        equivalent) and at 4 r (downward equivalent).
+ *   KIFMM_LAYOUT_LATTICE: upward equivalent and downward check: the full m0^3
+ *                        lattice on [-R r, R r]^3, R = lattice_radius (0: 1.2;
+ *                        0.5 < R <= 2; 3 <= m0 <= 8); upward check
+ *                        as SINGLE; downward equivalent as NESTED.  Both M2L point
+ *                        sets lie on lattices of one spacing, which lets M2L run in
+ *                        its FFT form (kifmm_ops_m2l_fft; on by default).
  * rcond: singular values <= rcond * s_max are dropped from the pseudo-inverse.
  * Expansions are carried as coefficients on the retained left singular vectors
  * of the check-to-equivalent matrix (the backward-stable form of the
  * pseudo-inverse, Section 3 remark on the pseudo-inverse). */
-enum { KIFMM_LAYOUT_PAPER = 0, KIFMM_LAYOUT_SINGLE = 1, KIFMM_LAYOUT_NESTED = 2 };
+enum { KIFMM_LAYOUT_PAPER = 0, KIFMM_LAYOUT_SINGLE = 1, KIFMM_LAYOUT_NESTED = 2, KIFMM_LAYOUT_LATTICE = 3 };
 typedef struct {
     int32_t layout;       /* KIFMM_LAYOUT_* */
     int32_t m0;           /* equivalent points per cube edge, 2..16 (paper: 6) */
-    int32_t check_edge;   /* check points per edge, layouts SINGLE/NESTED, 2..16 */
+    int32_t check_edge;   /* check points per edge, layouts SINGLE/NESTED/LATTICE, 2..16 */
     double rcond;         /* relative SVD cutoff, 0 < rcond < 1 */
+    double lattice_radius;/* layout LATTICE: lattice half-width / r (0: 1.2); else ignored */
 } kifmm_opts;
 
 /* Arithmetic of kifmm_eval.
@@ -179,6 +186,20 @@ int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable);
  * The call synchronizes the device (flags in use by an evaluation are not
  * overwritten).  Returns 0, KIFMM_EINVAL (ops NULL), KIFMM_ENOMEM or KIFMM_EHIP. */
 int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask);
+
+/* FFT form of M2L (Section 3 remark: the translation between equivalent and check
+ * points on regular grids is a convolution).  Operators built with
+ * KIFMM_LAYOUT_LATTICE hold, per level, the spectra of the kernel on the
+ * (2 m0 - 1)^3 cyclic grid for the 316 offsets and the maps from coefficients to
+ * the half spectra of the equivalent densities and from check-potential spectra
+ * back to coefficients.  With enable != 0 (the default for that layout), the M2L
+ * of FP32 and KIFMM_BF16X3 evaluations runs as: spectra of every box's density
+ * (FP32 MFMA GEMM), a pointwise complex multiply-add over each box's interaction
+ * list, then coefficients from the summed spectra (FP32 MFMA GEMM).  It computes
+ * the same sum as the dense M2L of the same layout up to FP32 rounding; enable = 0
+ * selects the dense M2L (other precisions always use it).  Returns 0,
+ * KIFMM_EINVAL (ops NULL) or KIFMM_EUNSUPPORTED (another layout). */
+int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 
 /* Direct evaluation of the exact sum (Section 3, eq. (summation)):
  * out_dev[t] = prefactor * sum_j G(x_t, y_j) I_dev[j] hx hy hz for the flat cell

@@ -32,8 +32,8 @@ three layouts are provided, all in units of the box half-width r:
             check_edge^3 lattice filling [-1.05 r, 1.05 r]^3
   'nested'  as 'single' but y^u adds an m0 surface at 0.55 r and y^d adds an
             m0 surface at 4 r
-  'lattice' y^u and x^d: the full m0^3 lattice filling [-1.4 r, 1.4 r]^3; x^u as in
-            'single'; y^d as in 'nested'.  Equivalent points and M2L check points
+  'lattice' y^u and x^d: the full m0^3 lattice filling [-R r, R r]^3 (R =
+            lattice_radius, 1.2 by default); x^u as in 'single'; y^d as in 'nested'.  Equivalent points and M2L check points
             then lie on lattices of one spacing, so each M2L matrix G(x^d, y^u + 2 r o)
             is a block of a 3-D convolution (the FFT form of M2L, Section 3 remark);
             here it is still applied as the plain matrix
@@ -61,7 +61,7 @@ def cube_lattice(m, rad):
     return np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
 
 
-def point_sets(layout, m0, check_edge, r):
+def point_sets(layout, m0, check_edge, r, lattice_radius=1.2):
     """(y_u, x_u, y_d, x_d) relative to the box centre for half-width r."""
     if layout == "paper":
         return (cube_surface(m0, 1.05 * r), cube_surface(m0, 2.95 * r),
@@ -76,7 +76,8 @@ def point_sets(layout, m0, check_edge, r):
         return yu, xu, yd, xd
     if layout == "lattice":
         yd = np.vstack([cube_surface(m0, 2.95 * r), cube_surface(m0, 4.0 * r)])
-        return cube_lattice(m0, 1.4 * r), xu, yd, cube_lattice(m0, 1.4 * r)
+        R = lattice_radius * r
+        return cube_lattice(m0, R), xu, yd, cube_lattice(m0, R)
     raise ValueError(layout)
 
 
@@ -109,7 +110,7 @@ def _shift(arr, o):
 
 
 def evaluate(I, L, p_o2, ell, layout="nested", m0=6, check_edge=10, rcond=1e-10,
-             prefactor=1.0):
+             prefactor=1.0, lattice_radius=1.2):
     """KIFMM approximation of S on an n^3 grid of cubic cells spanning [0, L]^3.
 
     I: (n,n,n) source values; returns S of the same shape (FP64).
@@ -145,7 +146,7 @@ def evaluate(I, L, p_o2, ell, layout="nested", m0=6, check_edge=10, rcond=1e-10,
     sets, pinv_u, pinv_d = {}, {}, {}
     for l in range(2, D + 1):
         r = L / 2 ** (l + 1)
-        yu, xu, yd, xd = point_sets(layout, m0, check_edge, r)
+        yu, xu, yd, xd = point_sets(layout, m0, check_edge, r, lattice_radius)
         sets[l] = (r, yu, xu, yd, xd)
         pinv_u[l] = np.linalg.pinv(gmat(xu, yu, p_o2), rcond=rcond)
         pinv_d[l] = np.linalg.pinv(gmat(xd, yd, p_o2), rcond=rcond)

@@ -47,6 +47,8 @@ int launch_cast_pad(const double *, int, int, int64_t, T *, int, int, int64_t, i
                     hipStream_t);
 int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, int64_t, int, double,
                        hipStream_t);
+int run_m2l_hadamard(const float *, const float *, const int *, const int *, int, int, int, const uint8_t *,
+                     const uint8_t *, float *, hipStream_t);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
 
@@ -113,9 +115,13 @@ static PointSets make_point_sets(const kifmm_opts &o, double r) {
     cube_lattice(o.check_edge, 1.05 * r, p.xd);
     cube_surface(o.m0, 1.05 * r, p.yu);
     cube_surface(o.m0, 2.95 * r, p.yd);
-    if (o.layout == KIFMM_LAYOUT_NESTED) {
-        cube_surface(o.m0, 0.55 * r, p.yu);
-        cube_surface(o.m0, 4.0 * r, p.yd);
+    if (o.layout == KIFMM_LAYOUT_NESTED || o.layout == KIFMM_LAYOUT_LATTICE) cube_surface(o.m0, 4.0 * r, p.yd);
+    if (o.layout == KIFMM_LAYOUT_NESTED) cube_surface(o.m0, 0.55 * r, p.yu);
+    if (o.layout == KIFMM_LAYOUT_LATTICE) {   // both M2L point sets on one lattice
+        p.yu.clear();
+        p.xd.clear();
+        cube_lattice(o.m0, o.lattice_radius * r, p.yu);
+        cube_lattice(o.m0, o.lattice_radius * r, p.xd);
     }
     return p;
 }
@@ -172,6 +178,14 @@ struct kifmm_ops_s {
     // 1 if some leaf below it is wanted (level D: the leaves); empty: every target is wanted
     std::vector<uint8_t *> want;
     _Float16 *m2lh = nullptr;
+    // FFT form of M2L (layout LATTICE): per level l, the kernel spectra of the 316 offsets
+    // (fft_g[l], 316 x nfp complex), coefficients -> half spectra (fft_f[l], mf x KU) and
+    // spectra -> coefficients (fft_i[l], KD x mf), mf = 2 nfp; spectra of one level's
+    // densities and sums (spec_e, spec_p: boxes of level D x mf)
+    bool m2l_fft = false;
+    int nfp = 0, mf = 0;
+    std::vector<float *> fft_g, fft_f, fft_i;
+    float *spec_e = nullptr, *spec_p = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
     TapList t_single{}, t_m2m{}, t_l2l{}, t_m2l{}, t_p2p{};
@@ -249,7 +263,7 @@ static void free_ops(kifmm_ops o) {
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
-                    o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c};
+                    o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -258,6 +272,9 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
+    for (auto *v : {&o->fft_g, &o->fft_f, &o->fft_i})
+        for (float *p : *v)
+            if (p) (void)hipFree(p);
     for (double *p : o->cd)
         if (p) (void)hipFree(p);
     if (o->fork) (void)hipEventDestroy(o->fork);
@@ -404,7 +421,9 @@ int upload(DevBuf &db, const std::vector<T> &h, T **d, hipStream_t st) {
 }
 
 // truncated SVDs of a batch of same-shape matrices G(X_b, Y_b) (m x n).
-// Output per batch item: UT (k x m) and W = V S^-1 (n x k), FP64 device.
+// Output per batch item: UT (k x m) and W = V S^-1 (n x k), FP64 device.  The one-sided
+// Jacobi method orthogonalises the columns of the matrix it is given, so a wide G
+// (m < n) is factored through its transpose: G^T = U' S V'^T gives U = V', V = U'.
 struct Factor {
     double *UT = nullptr, *W = nullptr;
     int k = 0, m = 0, n = 0;
@@ -414,6 +433,9 @@ int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::ve
                  int m, int n, const kifmm_kernel &kern, double h, double rcond,
                  std::vector<Factor> &out, hipStream_t st) {
     const int B = (int)X.size();
+    const bool trans = m < n;
+    const int mg = m, ng = n;   // shape of G
+    if (trans) std::swap(m, n);   // from here on: the factored matrix, n columns of length m
     const int npad = n + (n & 1);
     double *A, *V;
     KIFMM_TRY(db.get(&A, (size_t)B * npad * m));
@@ -422,8 +444,8 @@ int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::ve
     for (int i = 0; i < npad; ++i) eye[(size_t)i * npad + i] = 1.0;
     for (int b = 0; b < B; ++b) {
         KIFMM_HIP(hipMemsetAsync(A + (size_t)b * npad * m, 0, sizeof(double) * npad * m, st));
-        // column j of G(X, Y) stored contiguously: transposed kernel matrix
-        KIFMM_TRY(launch_kmat(X[b], m, Y[b], n, nullptr, nullptr, 1, 1, kern, h,
+        // columns stored contiguously: G transposed, or for a wide G its rows (= G^T's columns)
+        KIFMM_TRY(launch_kmat(X[b], mg, Y[b], ng, nullptr, nullptr, 1, trans ? 0 : 1, kern, h,
                               A + (size_t)b * npad * m, st));
         KIFMM_HIP(hipMemcpyAsync(V + (size_t)b * npad * npad, eye.data(), eye.size() * sizeof(double),
                                  hipMemcpyHostToDevice, st));
@@ -485,11 +507,32 @@ int batched_tsvd(DevBuf &db, const std::vector<const double *> &X, const std::ve
         KIFMM_TRY(upload(db, order, &ordd, st));
         KIFMM_TRY(upload(db, sk, &skd, st));
         Factor &f = out[b];
-        f.k = k; f.m = m; f.n = n;
-        KIFMM_TRY(db.get(&f.UT, (size_t)k * m));
-        KIFMM_TRY(db.get(&f.W, (size_t)n * k));
+        f.k = k; f.m = mg; f.n = ng;
+        KIFMM_TRY(db.get(&f.UT, (size_t)k * mg));
+        KIFMM_TRY(db.get(&f.W, (size_t)ng * k));
+        if (!trans) {
+            KIFMM_TRY(launch_svd_gather(A + (size_t)b * npad * m, V + (size_t)b * npad * npad, m, npad,
+                                        m, n, k, ordd, skd, f.UT, f.W, st));
+            continue;
+        }
+        // G^T = U' S V'^T: the gather gives U'^T (k x ng) and V' S^-1 (mg x k);
+        // G's U^T = V'^T = (V' S^-1 S)^T and W = V S^-1 = U' S^-1
+        double *ut2, *w2;
+        KIFMM_TRY(db.get(&ut2, (size_t)k * ng));
+        KIFMM_TRY(db.get(&w2, (size_t)mg * k));
         KIFMM_TRY(launch_svd_gather(A + (size_t)b * npad * m, V + (size_t)b * npad * npad, m, npad,
-                                    m, n, k, ordd, skd, f.UT, f.W, st));
+                                    m, n, k, ordd, skd, ut2, w2, st));
+        std::vector<double> hu((size_t)k * ng), hw((size_t)mg * k), UT((size_t)k * mg), W((size_t)ng * k);
+        KIFMM_HIP(hipMemcpyAsync(hu.data(), ut2, hu.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        KIFMM_HIP(hipMemcpyAsync(hw.data(), w2, hw.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        KIFMM_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < k; ++r) {
+            for (int i = 0; i < mg; ++i) UT[(size_t)r * mg + i] = hw[(size_t)i * k + r] * sk[r];
+            for (int i = 0; i < ng; ++i) W[(size_t)i * k + r] = hu[(size_t)r * ng + i] / sk[r];
+        }
+        KIFMM_HIP(hipMemcpyAsync(f.UT, UT.data(), UT.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        KIFMM_HIP(hipMemcpyAsync(f.W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        KIFMM_HIP(hipStreamSynchronize(st));   // UT and W are host vectors of this iteration
     }
     return KIFMM_OK;
 }
@@ -537,6 +580,92 @@ int max_abs_host(const double *d, size_t count, double *out, hipStream_t st) {
     double m = 0;
     for (double v : h) m = std::max(m, std::fabs(v));
     *out = m;
+    return KIFMM_OK;
+}
+
+// FFT form of M2L for the lattice layout.  With y^u = x^d = the m0^3 lattice of spacing t
+// around the box centre, G(x^d_i, y^u_j + 2 r o) = g_o(i - j) with g_o(d) = G(d t - 2 r o).
+// On the cyclic grid of N = 2 m0 - 1 points per axis the differences i - j never wrap onto
+// one another, so the M2L product is the inverse DFT of DFT(g_o) times DFT(density).  Per
+// level: the half spectra (frequencies (kx, ky, kz), kz < m0, index (kx N + ky) m0 + kz,
+// real and imaginary parts interleaved) of g_o for the 316 offsets; the map from upward
+// coefficients to the half spectrum of the equivalent density, DFT . W_u; and the map from
+// a check-potential half spectrum to downward coefficients, U_d^T . inverse DFT (the
+// conjugate-symmetric half counted twice where kz > 0).
+int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::vector<int> &m2lo,
+                  const std::vector<Factor> &fu, const std::vector<Factor> &fd, hipStream_t st) {
+    const int m = o->opts.m0, N = 2 * m - 1, D = o->D, KU = o->KU, KD = o->KD;
+    const int n316 = (int)m2lo.size() / 3;
+    const int nf = N * N * m, nfp = pad_to(nf, 16), mf = 2 * nfp;
+    const int nd = N * N * N, nlat = m * m * m;
+    o->nfp = nfp;
+    o->mf = mf;
+    const double twopi_n = 2.0 * M_PI / N;
+    auto phase = [&](int f, int x, int y, int z) {   // exact integer phase, reduced mod N
+        const int kx = f / (N * m), ky = (f / m) % N, kz = f % m;
+        const int64_t ph = (int64_t)kx * x + (int64_t)ky * y + (int64_t)kz * z;
+        return twopi_n * (double)(((ph % N) + N) % N);
+    };
+    std::vector<double> FD((size_t)nd * 2 * nf), FY((size_t)2 * nf * nlat), BI((size_t)nlat * 2 * nf);
+    for (int d = 0; d < nd; ++d) {   // difference d = (dx, dy, dz) in [-(m-1), m-1]^3, C order
+        const int dx = d / (N * N) - (m - 1), dy = (d / N) % N - (m - 1), dz = d % N - (m - 1);
+        for (int f = 0; f < nf; ++f) {
+            const double a = phase(f, dx, dy, dz);
+            FD[(size_t)d * 2 * nf + 2 * f] = std::cos(a);
+            FD[(size_t)d * 2 * nf + 2 * f + 1] = -std::sin(a);
+        }
+    }
+    const double inv = 1.0 / ((double)N * N * N);
+    for (int j = 0; j < nlat; ++j) {   // lattice point (jx, jy, jz), C order
+        const int jx = j / (m * m), jy = (j / m) % m, jz = j % m;
+        for (int f = 0; f < nf; ++f) {
+            const double a = phase(f, jx, jy, jz), w = (f % m == 0 ? 1.0 : 2.0) * inv;
+            FY[(size_t)(2 * f) * nlat + j] = std::cos(a);
+            FY[(size_t)(2 * f + 1) * nlat + j] = -std::sin(a);
+            BI[(size_t)j * 2 * nf + 2 * f] = w * std::cos(a);
+            BI[(size_t)j * 2 * nf + 2 * f + 1] = -w * std::sin(a);
+        }
+    }
+    double *FDd, *FYd, *BId, *org, *Dp, *sh, *G, *tmp;
+    KIFMM_TRY(upload(db, FD, &FDd, st));
+    KIFMM_TRY(upload(db, FY, &FYd, st));
+    KIFMM_TRY(upload(db, BI, &BId, st));
+    KIFMM_TRY(upload(db, std::vector<double>(3, 0.0), &org, st));
+    KIFMM_TRY(db.get(&Dp, (size_t)3 * nd));
+    KIFMM_TRY(db.get(&sh, (size_t)3 * n316));
+    KIFMM_TRY(db.get(&G, (size_t)n316 * nd));
+    KIFMM_TRY(db.get(&tmp, (size_t)std::max(n316, std::max(KU, KD)) * 2 * nf));
+    o->fft_g.assign(D + 1, nullptr);
+    o->fft_f.assign(D + 1, nullptr);
+    o->fft_i.assign(D + 1, nullptr);
+    for (int l = 2; l <= D; ++l) {
+        const double r = Lside / std::ldexp(1.0, l + 1), t = 2.0 * o->opts.lattice_radius * r / (m - 1);
+        std::vector<double> dp(3 * nd), shifts(3 * n316);
+        for (int d = 0; d < nd; ++d) {   // points -d t: G(0, -d t + 2 r o) = g_o(d)
+            dp[3 * d] = -(d / (N * N) - (m - 1)) * t;
+            dp[3 * d + 1] = -((d / N) % N - (m - 1)) * t;
+            dp[3 * d + 2] = -(d % N - (m - 1)) * t;
+        }
+        for (int i = 0; i < 3 * n316; ++i) shifts[i] = 2.0 * r * m2lo[i];
+        KIFMM_HIP(hipMemcpyAsync(Dp, dp.data(), dp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        KIFMM_HIP(hipMemcpyAsync(sh, shifts.data(), shifts.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        KIFMM_TRY(launch_kmat(org, 1, Dp, nd, nullptr, sh, n316, 0, o->kern, h, G, st));
+        KIFMM_TRY(launch_gemm_f64(n316, 2 * nf, nd, G, nd, 0, FDd, 2 * nf, 0, tmp, 2 * nf, 0, 1, st));
+        KIFMM_TRY(dmalloc(&o->fft_g[l], (size_t)n316 * mf));
+        KIFMM_TRY(store<float>(tmp, n316, 2 * nf, 1, o->fft_g[l], n316, mf, 1.0, st));
+        const Factor &u = fu[l - 2], &dn = fd[l - 2];
+        KIFMM_TRY(launch_gemm_f64(2 * nf, u.k, nlat, FYd, nlat, 0, u.W, u.k, 0, tmp, u.k, 0, 1, st));
+        KIFMM_TRY(dmalloc(&o->fft_f[l], (size_t)mf * KU));
+        KIFMM_TRY(store<float>(tmp, 2 * nf, u.k, 1, o->fft_f[l], mf, KU, 1.0, st));
+        KIFMM_TRY(launch_gemm_f64(dn.k, 2 * nf, nlat, dn.UT, nlat, 0, BId, 2 * nf, 0, tmp, 2 * nf, 0, 1, st));
+        KIFMM_TRY(dmalloc(&o->fft_i[l], (size_t)KD * mf));
+        KIFMM_TRY(store<float>(tmp, dn.k, 2 * nf, 1, o->fft_i[l], KD, mf, 1.0, st));
+        KIFMM_HIP(hipStreamSynchronize(st));   // dp and shifts are reused by the next level
+    }
+    const size_t nbx = (size_t)1 << (3 * D);
+    KIFMM_TRY(dmalloc(&o->spec_e, nbx * mf));
+    KIFMM_TRY(dmalloc(&o->spec_p, nbx * mf));
+    o->m2l_fft = true;
     return KIFMM_OK;
 }
 
@@ -794,6 +923,7 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             KIFMM_TRY(store<_Float16>(tmp, kd, ku, n316, o->m2lh + so, KD, KU, 1.0 / mx, st));
         }
     }
+    if (o->opts.layout == KIFMM_LAYOUT_LATTICE) KIFMM_TRY(build_fft_m2l(db, o, Lside, h, m2lo, fu, fd, st));
     for (int l = 2; l <= D; ++l) {
         const size_t nbx = (size_t)1 << (3 * l);
         KIFMM_TRY(dmalloc(&o->cu[l], nbx * KU));
@@ -852,6 +982,21 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
     const size_t per = (size_t)316 * KD * KU;
     const size_t so = (size_t)(l - 2) * per;
     if constexpr (sizeof(T) == 4) {
+        if (o->m2l_fft && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
+            // FFT form: spectra of the densities, pointwise products, coefficients
+            const int64_t nbx = (int64_t)1 << (3 * l);
+            auto pf = tap<float, float>(o->fft_f[l], 0, o->mf, KU, (const float *)o->cu[l], KU, o->spec_e, o->mf,
+                                        SRC_SAME, 0, o->t_single, 1, nbx, 0);
+            pf.in_nz = nz_of(o, l);
+            KIFMM_TRY(run(pf, st));
+            KIFMM_TRY(run_m2l_hadamard(o->spec_e, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev, o->t_m2l.ntaps,
+                                       1 << l, o->nfp, want_of(o, l), nz_of(o, l), o->spec_p, st));
+            auto pi = tap<float, float>(o->fft_i[l], 0, KD, o->mf, (const float *)o->spec_p, o->mf, (float *)o->cd[l],
+                                        KD, SRC_SAME, 0, o->t_single, 1, nbx, acc);
+            pi.out_need = want_of(o, l);
+            pi.pass = PASS_M2L;
+            return run(pi, st);
+        }
         if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16X3 ||
             precision == KIFMM_BF16X3) {
             const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
@@ -1020,7 +1165,9 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
         return launch_permute_out<T>(*t, Sp, scale, want_of(o, D), S, st);
     }
-    // near field on the side stream
+    // near field on the side stream, forked as early as possible: whatever runs beside it
+    // waits for its long workgroups (forking it later, after the upward pass or before the
+    // finest M2L level, measured slower)
     KIFMM_HIP(hipEventRecord(o->fork, st));
     KIFMM_HIP(hipStreamWaitEvent(o->side, o->fork, 0));
     {
@@ -1053,7 +1200,7 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
                                0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), 0);
-        p.out_need = want_of(o, l);
+            p.out_need = want_of(o, l);
             KIFMM_TRY(run(p, st));
         }
         PassTimer pt(o, KIFMM_PASS_M2L, st);
@@ -1080,8 +1227,13 @@ int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, cons
     KIFMM_TRY(check_kernel(kernel));
     kifmm_opts o;
     if (opts) o = *opts;
-    else { o.layout = KIFMM_LAYOUT_SINGLE; o.m0 = 6; o.check_edge = 10; o.rcond = 1e-7; }
-    if (o.layout < 0 || o.layout > 2) return fail(KIFMM_EINVAL, "unknown layout");
+    else { o.layout = KIFMM_LAYOUT_SINGLE; o.m0 = 6; o.check_edge = 10; o.rcond = 1e-7; o.lattice_radius = 0; }
+    if (o.layout == KIFMM_LAYOUT_LATTICE && o.lattice_radius == 0) o.lattice_radius = 1.2;
+    if (o.layout == KIFMM_LAYOUT_LATTICE && !(o.lattice_radius > 0.5 && o.lattice_radius <= 2.0))
+        return fail(KIFMM_EINVAL, "lattice_radius must be in (0.5, 2]");
+    if (o.layout < 0 || o.layout > 3) return fail(KIFMM_EINVAL, "unknown layout");
+    if (o.layout == KIFMM_LAYOUT_LATTICE && (o.m0 < 3 || o.m0 > 8))
+        return fail(KIFMM_EINVAL, "m0 must be in [3, 8] for the lattice layout");
     if (o.m0 < 2 || o.m0 > 16) return fail(KIFMM_EINVAL, "m0 must be in [2, 16]");
     if (o.layout != KIFMM_LAYOUT_PAPER && (o.check_edge < 2 || o.check_edge > 16))
         return fail(KIFMM_EINVAL, "check_edge must be in [2, 16]");
@@ -1154,6 +1306,16 @@ int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable) {
         }
     }
     ops->skip_zero = true;
+    return KIFMM_OK;
+}
+
+int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    if (ops->opts.layout != KIFMM_LAYOUT_LATTICE) {
+        if (!enable) return KIFMM_OK;
+        return fail(KIFMM_EUNSUPPORTED, "the FFT form of M2L needs operators of the lattice layout");
+    }
+    ops->m2l_fft = enable != 0 && !ops->fft_g.empty();
     return KIFMM_OK;
 }
 

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("KIFMM_LIB") or os.path.join(_HERE, "libkifmm.so")   # KIFMM_LIB: another build
 
 OK, EINVAL, EUNSUPPORTED, EMISMATCH, ENOMEM, EHIP = 0, -1, -2, -3, -4, -5
-LAYOUT_PAPER, LAYOUT_SINGLE, LAYOUT_NESTED = 0, 1, 2
+LAYOUT_PAPER, LAYOUT_SINGLE, LAYOUT_NESTED, LAYOUT_LATTICE = 0, 1, 2, 3
 FP64, FP32, M2L_BF16, M2L_FP16, M2L_BF16X3, BF16X3 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "m2l_bf16": M2L_BF16, "m2l_fp16": M2L_FP16,
               "m2l_bf16x3": M2L_BF16X3, "bf16x3": BF16X3}
@@ -25,7 +25,7 @@ CHI_MIN, CHI_MAX = 0.035, 2.0
 EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "kifmm_tree_info",
            "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_tree_destroy",
            "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read",
-           "kifmm_ops_skip_zero_sources", "kifmm_ops_restrict_targets",
+           "kifmm_ops_skip_zero_sources", "kifmm_ops_restrict_targets", "kifmm_ops_m2l_fft",
            "kifmm_nn_layer_forward", "kifmm_nn_layer_backward_data", "kifmm_nn_layer_backward_weight",
            "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
            "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
@@ -53,7 +53,7 @@ class _Kernel(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("m0", ctypes.c_int32), ("check_edge", ctypes.c_int32),
-                ("rcond", ctypes.c_double)]
+                ("rcond", ctypes.c_double), ("lattice_radius", ctypes.c_double)]
 
 
 def load_library(path=LIB_PATH):
@@ -79,6 +79,7 @@ def load_library(path=LIB_PATH):
     lib.kifmm_profile_read.argtypes = [P, P, P, ctypes.c_int32]
     lib.kifmm_ops_skip_zero_sources.argtypes = [P, ctypes.c_int32]
     lib.kifmm_ops_restrict_targets.argtypes = [P, P]
+    lib.kifmm_ops_m2l_fft.argtypes = [P, ctypes.c_int32]
     I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     nn = {
         "kifmm_nn_layer_forward": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
@@ -158,9 +159,10 @@ class Opts:
     m0: int = 6
     check_edge: int = 10
     rcond: float = 1e-7
+    lattice_radius: float = 0.0     # layout LATTICE only; 0 = the library default (1.2)
 
     def c(self):
-        return _Opts(self.layout, self.m0, self.check_edge, self.rcond)
+        return _Opts(self.layout, self.m0, self.check_edge, self.rcond, self.lattice_radius)
 
 
 class Tree:
@@ -194,6 +196,10 @@ class Ops:
     def skip_zero_sources(self, enable=True):
         """Skip taps whose source boxes hold only zeros in later eval() calls (same sum)."""
         _check(_lib.kifmm_ops_skip_zero_sources(self.handle, 1 if enable else 0))
+
+    def m2l_fft(self, enable=True):
+        """FFT form of M2L (lattice layout only; on by default there) or the dense M2L."""
+        _check(_lib.kifmm_ops_m2l_fft(self.handle, 1 if enable else 0))
 
     def restrict_targets(self, leaf_mask=None):
         """Evaluate only at the leaves marked in leaf_mask (array of nb^3 values, C order

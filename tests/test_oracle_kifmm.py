@@ -51,13 +51,14 @@ def test_linearity():
 
 @pytest.mark.parametrize("p_o2", [150.0, 1.974])
 def test_lattice_layout_truncation(p_o2):
-    # the 125-point lattices bound the accuracy at about 2e-5 (measured against the exact
-    # sum at 32^3 to 64^3, both pressures, any rcond down to 1e-10)
+    # the 125-point lattices bound the accuracy at a few 1e-5 (measured against the exact
+    # sum at 32^3 to 256^3, pressures 2 to 150 Torr O2, lattice radii 1.0 r to 1.4 r)
     h, I = _gauss(32)
     ref = direct.fft_full(I, (h,) * 3, p_o2)
-    S = kifmm_ref.evaluate(I, L, p_o2, ell=4, layout="lattice", m0=5, rcond=1e-7)
-    e = metrics.rel_l2(S, ref)
-    assert 1e-6 < e < 1e-4
+    for R in (1.0, 1.2, 1.4):
+        S = kifmm_ref.evaluate(I, L, p_o2, ell=4, layout="lattice", m0=5, rcond=1e-7, lattice_radius=R)
+        e = metrics.rel_l2(S, ref)
+        assert 1e-6 < e < 1e-4, (R, e)
 
 
 def test_lattice_m2l_matrix_is_a_convolution():
@@ -65,10 +66,11 @@ def test_lattice_m2l_matrix_is_a_convolution():
     # i - j only, so applying it is a cyclic convolution of length 2 m0 - 1 per axis; the
     # product computed with numpy's FFT must equal the matrix product
     r, m0, p_o2 = 0.003, 5, 150.0
-    yu, _, _, xd = kifmm_ref.point_sets("lattice", m0, 10, r)
-    t = 2.8 * r / (m0 - 1)
-    idx = np.rint((yu + 1.4 * r) / t).astype(int)          # lattice indices 0..m0-1
-    assert np.allclose(idx * t - 1.4 * r, yu) and np.allclose(xd, yu)
+    R = 1.2 * r
+    yu, _, _, xd = kifmm_ref.point_sets("lattice", m0, 10, r, lattice_radius=1.2)
+    t = 2 * R / (m0 - 1)
+    idx = np.rint((yu + R) / t).astype(int)          # lattice indices 0..m0-1
+    assert np.allclose(idx * t - R, yu) and np.allclose(xd, yu)
     N = 2 * m0 - 1
     rng = np.random.default_rng(8)
     e = rng.standard_normal(len(yu))
