@@ -244,7 +244,9 @@ def main():
     p2p_flops = 2.0 * near_pairs(nb, s)
     if m2l_form == "fft":
         # FFT form: coefficients -> half spectra and back (two GEMMs per box), plus one
-        # complex multiply-add (8 flops) per interaction pair and frequency
+        # complex multiply-add (8 flops) per interaction pair and frequency (all three on
+        # MFMA at levels >= 3; the parent-pair products also multiply the zero entries of
+        # adjacent children, which are not counted)
         nf = (2 * args.m0 - 1) ** 2 * args.m0
         m2l_flops = sum(2.0 * 8 ** l * 2 * nf * (ranks[l][0] + ranks[l][1]) + 8.0 * m2l_pairs(l) * nf
                         for l in ranks)
@@ -263,7 +265,7 @@ def main():
                 "avg_launch_ms": round(pass_ms["p2p"], 4)}
     m2l_launch = m2l_flops / max(calls_step["m2l"], 1)
     m2l_ach = m2l_launch / (pass_ms["m2l"] * 1e-3) / 1e12
-    roofline_m2l = {"bound": "mfma" if m2l_form == "dense" else "alu",
+    roofline_m2l = {"bound": "mfma",
                     "kernel": "m2l (all levels, %s form)" % m2l_form, "achieved": round(m2l_ach, 3),
                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(m2l_ach * 1e12 / peak, 4),
                     "flops_per_launch": m2l_launch, "avg_launch_ms": round(pass_ms["m2l"], 4),

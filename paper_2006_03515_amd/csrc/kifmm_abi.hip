@@ -49,6 +49,7 @@ int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, in
                        hipStream_t);
 int run_m2l_hadamard(const float *, const float *, const int *, const int *, int, int, int, const uint8_t *,
                      const uint8_t *, float *, hipStream_t);
+int run_m2l_pair_mfma(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
 
@@ -185,6 +186,7 @@ struct kifmm_ops_s {
     bool m2l_fft = false;
     int nfp = 0, mf = 0;
     std::vector<float *> fft_g, fft_f, fft_i;
+    std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
     float *spec_e = nullptr, *spec_p = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
@@ -272,7 +274,7 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
-    for (auto *v : {&o->fft_g, &o->fft_f, &o->fft_i})
+    for (auto *v : {&o->fft_g, &o->fft_f, &o->fft_i, &o->fft_pair})
         for (float *p : *v)
             if (p) (void)hipFree(p);
     for (double *p : o->cd)
@@ -638,6 +640,11 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
     o->fft_g.assign(D + 1, nullptr);
     o->fft_f.assign(D + 1, nullptr);
     o->fft_i.assign(D + 1, nullptr);
+    o->fft_pair.assign(D + 1, nullptr);
+    // offset -> index into the 316 offsets, for the parent-pair matrices
+    std::vector<int> oidx(343, -1);
+    for (int t = 0; t < n316; ++t)
+        oidx[((m2lo[3 * t] + 3) * 7 + (m2lo[3 * t + 1] + 3)) * 7 + (m2lo[3 * t + 2] + 3)] = t;
     for (int l = 2; l <= D; ++l) {
         const double r = Lside / std::ldexp(1.0, l + 1), t = 2.0 * o->opts.lattice_radius * r / (m - 1);
         std::vector<double> dp(3 * nd), shifts(3 * n316);
@@ -653,6 +660,33 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
         KIFMM_TRY(launch_gemm_f64(n316, 2 * nf, nd, G, nd, 0, FDd, 2 * nf, 0, tmp, 2 * nf, 0, 1, st));
         KIFMM_TRY(dmalloc(&o->fft_g[l], (size_t)n316 * mf));
         KIFMM_TRY(store<float>(tmp, n316, 2 * nf, 1, o->fft_g[l], n316, mf, 1.0, st));
+        if (l >= 3) {
+            // Parent-pair form: per frequency the 16 x 432 real matrix taking the spectra of
+            // the 8 children of each of the 27 neighbour parents (k = 16 d + 2 c_s + re/im) to
+            // the 8 children of the target parent (row = 2 c_t + re/im), laid out as MFMA
+            // fragments [f][k-step][lane]: lane l holds (row l % 16, k = 4 k-step + l / 16).
+            std::vector<double> gh((size_t)n316 * 2 * nf);
+            KIFMM_HIP(hipMemcpyAsync(gh.data(), tmp, gh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            KIFMM_HIP(hipStreamSynchronize(st));
+            std::vector<float> am((size_t)nfp * 108 * 64, 0.f);
+            for (int ks = 0; ks < 108; ++ks)
+                for (int ln = 0; ln < 64; ++ln) {
+                    const int row = ln & 15, ct = row >> 1, rt = row & 1;
+                    const int k = 4 * ks + (ln >> 4), d = k / 16, cs = (k / 2) % 8, rs = k & 1;
+                    const int ov[3] = {2 * (d / 9 - 1) + ((cs >> 2) & 1) - ((ct >> 2) & 1),
+                                       2 * ((d / 3) % 3 - 1) + ((cs >> 1) & 1) - ((ct >> 1) & 1),
+                                       2 * (d % 3 - 1) + (cs & 1) - (ct & 1)};
+                    const int t = oidx[((ov[0] + 3) * 7 + (ov[1] + 3)) * 7 + (ov[2] + 3)];
+                    if (t < 0) continue;   // adjacent children: no M2L term
+                    for (int f = 0; f < nf; ++f) {
+                        const double gr = gh[(size_t)t * 2 * nf + 2 * f], gi = gh[(size_t)t * 2 * nf + 2 * f + 1];
+                        am[((size_t)f * 108 + ks) * 64 + ln] = (float)(rt == 0 ? (rs == 0 ? gr : -gi) : (rs == 0 ? gi : gr));
+                    }
+                }
+            KIFMM_TRY(dmalloc(&o->fft_pair[l], am.size()));
+            KIFMM_HIP(hipMemcpyAsync(o->fft_pair[l], am.data(), am.size() * sizeof(float), hipMemcpyHostToDevice, st));
+            KIFMM_HIP(hipStreamSynchronize(st));   // am is a host vector of this iteration
+        }
         const Factor &u = fu[l - 2], &dn = fd[l - 2];
         KIFMM_TRY(launch_gemm_f64(2 * nf, u.k, nlat, FYd, nlat, 0, u.W, u.k, 0, tmp, u.k, 0, 1, st));
         KIFMM_TRY(dmalloc(&o->fft_f[l], (size_t)mf * KU));
@@ -989,8 +1023,12 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                                         SRC_SAME, 0, o->t_single, 1, nbx, 0);
             pf.in_nz = nz_of(o, l);
             KIFMM_TRY(run(pf, st));
-            KIFMM_TRY(run_m2l_hadamard(o->spec_e, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev, o->t_m2l.ntaps,
-                                       1 << l, o->nfp, want_of(o, l), nz_of(o, l), o->spec_p, st));
+            if (o->fft_pair[l])
+                KIFMM_TRY(run_m2l_pair_mfma(o->spec_e, o->fft_pair[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l),
+                                            o->spec_p, st));
+            else
+                KIFMM_TRY(run_m2l_hadamard(o->spec_e, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev,
+                                           o->t_m2l.ntaps, 1 << l, o->nfp, want_of(o, l), nz_of(o, l), o->spec_p, st));
             auto pi = tap<float, float>(o->fft_i[l], 0, KD, o->mf, (const float *)o->spec_p, o->mf, (float *)o->cd[l],
                                         KD, SRC_SAME, 0, o->t_single, 1, nbx, acc);
             pi.out_need = want_of(o, l);
