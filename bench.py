@@ -54,20 +54,27 @@ def m2l_pairs(level):
     return total
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tapgemm_p2p_traffic_streamer256.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2006_03515_amd", "csrc", "tapgemm.hip")
+TRAFFIC_FILES = {   # (summary with the counters, source file of the kernel they were taken on)
+    "dense": (os.path.join(ROOT, "profiles", "tapgemm_p2p_traffic_streamer256.md"),
+              os.path.join(ROOT, "paper_2006_03515_amd", "csrc", "tapgemm.hip")),
+    "fft": (os.path.join(ROOT, "profiles", "near_products_traffic_streamer256.md"),
+            os.path.join(ROOT, "paper_2006_03515_amd", "csrc", "near_fft.hip")),
+}
+# FP32 FMA on the vector ALUs without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP32_VALU = 78.6e12
 
 
 def p2p_traffic(args):
-    """HBM-side bytes of one near-field launch from the committed --pmc summary, or
-    None when that summary is missing, was taken on another configuration, or the
-    kernel source has changed since."""
+    """HBM-side bytes of one launch of the near field's dominant kernel from the committed
+    --pmc summary, or None when that summary is missing, was taken on another
+    configuration, or the kernel source has changed since."""
     import hashlib
-    if args.precision != "fp32" or args.n != 256 or not os.path.exists(TRAFFIC_FILE):
+    traffic_file, kernel_src = TRAFFIC_FILES[args.p2p]
+    if args.precision != "fp32" or args.n != 256 or not os.path.exists(traffic_file):
         return None
-    h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(traffic_file):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
@@ -148,14 +155,17 @@ def main():
     ap.add_argument("--lattice-radius", type=float, default=1.0,
                     help="lattice layout: half-width of its point lattices in box half-widths (1.0 "
                          "measured best for 760 Torr air; 0 = the library default 1.2, robust over pressures)")
+    ap.add_argument("--p2p", default="fft", choices=["fft", "dense"],
+                    help="near field: dense 512 x 512 blocks on MFMA, or in Fourier space (leaves of 8^3)")
     ap.add_argument("--m2l", default="fft", choices=["fft", "dense"],
                     help="M2L form for the lattice layout (the other layouts have only the dense form)")
     ap.add_argument("--rcond", type=float, default=1e-5)
     ap.add_argument("--m0", type=int, default=5)
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--variants", default="bf16x3,fp32/dense,bf16x3/dense,m2l_bf16x3,m2l_fp16,m2l_bf16",
+    ap.add_argument("--variants", default="bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense,bf16x3/dense/near_dense,m2l_bf16x3/near_dense,m2l_fp16/near_dense,m2l_bf16/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "
-                         "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout)")
+                         "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout), "
+                         "'/near_fft' or '/near_dense' the near-field form")
     ap.add_argument("--check-targets", type=int, default=4096)
     ap.add_argument("--cpu-targets", type=int, default=2048,
                     help="targets of the oracle CPU baseline sample (0 = skip)")
@@ -196,6 +206,7 @@ def main():
     m2l_form = args.m2l if args.layout == "lattice" else "dense"
     if args.layout == "lattice":
         ops.m2l_fft(m2l_form == "fft")
+    ops.p2p_fft(args.p2p == "fft")
     ranks = {l: ops.rank(l) for l in range(2, tree.depth + 1)}
     log("tree depth %d, leaf %d^3, precompute %.2f s, ranks %s" % (tree.depth, tree.leaf_side, t_pre, ranks))
 
@@ -258,11 +269,24 @@ def main():
     # Roofline of the near field (P2P): the largest kernel when each pass runs alone,
     # one launch per step.  The M2L launches (one per level) are reported beside it.
     peak = PEAK_FP32_MFMA if args.precision in ("fp32", "fp64") else PEAK_BF16_MFMA
-    achieved = p2p_flops / (pass_ms["p2p"] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "p2p (tapgemm near field)", "achieved": round(achieved, 3),
-                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
-                "traffic": p2p_traffic(args), "flops_per_launch": p2p_flops,
-                "avg_launch_ms": round(pass_ms["p2p"], 4)}
+    if args.p2p == "fft" and pass_ms.get("near_products", 0) > 0:
+        # near field in Fourier space: the dominant kernel is the products kernel, one
+        # complex multiply-add (8 flops) per frequency (16 x 16 x 9) and existing leaf pair
+        leaf_pairs = float(3 * nb - 2) ** 3
+        prod_flops = 8.0 * 2304 * leaf_pairs
+        t = pass_ms["near_products"]
+        achieved = prod_flops / (t * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "near_products (near field in Fourier space)",
+                    "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                    "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": p2p_traffic(args),
+                    "flops_per_launch": prod_flops, "avg_launch_ms": round(t, 4),
+                    "near_field_pass_ms": round(pass_ms["p2p"], 4)}
+    else:
+        achieved = p2p_flops / (pass_ms["p2p"] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "p2p (tapgemm near field)", "achieved": round(achieved, 3),
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
+                    "traffic": p2p_traffic(args), "flops_per_launch": p2p_flops,
+                    "avg_launch_ms": round(pass_ms["p2p"], 4)}
     m2l_launch = m2l_flops / max(calls_step["m2l"], 1)
     m2l_ach = m2l_launch / (pass_ms["m2l"] * 1e-3) / 1e12
     roofline_m2l = {"bound": "mfma",
@@ -283,13 +307,17 @@ def main():
     variants = {}
     for v in [x for x in args.variants.split(",") if x]:
         log("timing variant %s" % v)
-        prec, _, form = v.partition("/")
-        if form and args.layout == "lattice":
-            ops.m2l_fft(form == "fft")
+        prec, *forms = v.split("/")
+        for form in forms:
+            if form in ("fft", "dense") and args.layout == "lattice":
+                ops.m2l_fft(form == "fft")
+            if form in ("near_fft", "near_dense"):
+                ops.p2p_fft(form == "near_fft")
         vms, _ = timed(prec, args.steps, args.warmup, profile=False)
         variants[v] = {"value": N / (vms * 1e-3), "ms_per_step": round(vms, 4), "rel_l2": accuracy()}
         if args.layout == "lattice":
             ops.m2l_fft(m2l_form == "fft")
+        ops.p2p_fft(args.p2p == "fft")
 
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device=dev)
@@ -331,7 +359,7 @@ def main():
         "config": {"workload": "streamer_channel_%d" % w.n, "n": w.n, "L_cm": w.L, "p_torr": w.p,
                    "p_o2_torr": w.p_o2, "layout": args.layout, "m0": args.m0, "check_edge": 10,
                    "rcond": args.rcond, "max_leaf": args.max_leaf, "leaf_side": tree.leaf_side,
-                   "depth": tree.depth, "precision": args.precision, "m2l": m2l_form,
+                   "depth": tree.depth, "precision": args.precision, "m2l": m2l_form, "p2p": args.p2p,
                    "lattice_radius": (args.lattice_radius or 1.2) if args.layout == "lattice" else None,
                    "parallelism": "none"},
         "rel_l2_sampled": err,

@@ -201,6 +201,18 @@ int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask);
  * KIFMM_EINVAL (ops NULL) or KIFMM_EUNSUPPORTED (another layout). */
 int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 
+/* Near field in Fourier space (eq. (nearfar), direct part, with the self cell).  On the
+ * uniform grid the matrix between a leaf of 8^3 cells and a neighbour leaf is a block of a
+ * convolution, so with enable != 0 the near field of FP32 and KIFMM_BF16X3 evaluations
+ * runs as: half spectra (16 x 16 x 9) of every leaf's sources zero-padded to 16^3,
+ * 27 complex products per frequency against the kernel spectra of the 27 neighbour
+ * offsets (built in FP64 with the operators), and the inverse transform at the 8^3 cells.
+ * Same sum as the dense near field up to FP32 rounding (about 1e-7 of the result).  The
+ * first enable allocates two spectra buffers of 18 KiB per leaf (owned by ops).  Returns
+ * 0, KIFMM_EINVAL (ops NULL), KIFMM_EUNSUPPORTED (leaves other than 8^3, or fewer than 4
+ * per axis) or KIFMM_ENOMEM. */
+int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable);
+
 /* Direct evaluation of the exact sum (Section 3, eq. (summation)):
  * out_dev[t] = prefactor * sum_j G(x_t, y_j) I_dev[j] hx hy hz for the flat cell
  * indices tgt_idx_dev[t] (device int64, each in [0, N)), or for every cell
@@ -232,7 +244,8 @@ int kifmm_tree_permutation(kifmm_tree tree, int64_t *perm_dev, void *stream);
  * (4096 pairs) is nearly full; with profiling off it never waits. */
 enum { KIFMM_PASS_PERMUTE_IN = 0, KIFMM_PASS_P2M = 1, KIFMM_PASS_M2M = 2, KIFMM_PASS_M2L = 3,
        KIFMM_PASS_L2L = 4, KIFMM_PASS_L2P = 5, KIFMM_PASS_P2P = 6, KIFMM_PASS_PERMUTE_OUT = 7,
-       KIFMM_NPASS = 8 };
+       KIFMM_PASS_NEAR_PRODUCTS = 8, /* inside P2P: the products of the Fourier-space near field */
+       KIFMM_NPASS = 9 };
 int kifmm_profile_enable(kifmm_ops ops, int32_t on);
 int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n);
 

@@ -50,6 +50,8 @@ int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, in
 int run_m2l_hadamard(const float *, const float *, const int *, const int *, int, int, int, const uint8_t *,
                      const uint8_t *, float *, hipStream_t);
 int run_m2l_pair_mfma(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
+int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, const uint8_t *, float *, float *,
+                       float *, hipStream_t);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
 
@@ -187,6 +189,11 @@ struct kifmm_ops_s {
     int nfp = 0, mf = 0;
     std::vector<float *> fft_g, fft_f, fft_i;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
+    // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
+    // kernel of the 27 neighbour offsets [27][2304] complex, and per-leaf spectra of the
+    // sources and of the sums [nleaf][2304] complex (allocated when first enabled)
+    bool p2p_fft = false;
+    float *near_gh = nullptr, *near_q = nullptr, *near_p = nullptr;
     float *spec_e = nullptr, *spec_p = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
@@ -248,7 +255,7 @@ struct PassTimer {
     int slot = -1;
     hipStream_t st;
     PassTimer(kifmm_ops ops, int pass, hipStream_t s) : o(ops), st(s) {
-        if (!o->prof || 2 * (o->ev_used + 1) > (int)o->ev.size()) return;
+        if (pass < 0 || !o->prof || 2 * (o->ev_used + 1) > (int)o->ev.size()) return;
         slot = o->ev_used++;
         o->ev_pass[slot] = pass;
         (void)hipEventRecord(o->ev[2 * slot], st);
@@ -265,7 +272,8 @@ static void free_ops(kifmm_ops o) {
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
-                    o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p};
+                    o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
+                    o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -585,6 +593,92 @@ int max_abs_host(const double *d, size_t count, double *out, hipStream_t st) {
     return KIFMM_OK;
 }
 
+// Half spectra of the near-range kernel for leaves of 8^3 cells: for each neighbour offset o
+// (in leaves, o = 9 (ox+1) + 3 (oy+1) + oz+1), g_o(d) = G((d - 8 o) h) for cell differences
+// d in [-7, 7]^3 (the self value at d - 8 o = 0), placed at d mod 16, transformed over the
+// 16^3 cyclic grid in FP64 and stored at f = (ky * 9 + kz) * 16 + kx, kz <= 8.
+int build_near_spectra(DevBuf &db, kifmm_ops o, double h, hipStream_t st) {
+    const int nd = 15 * 15 * 15;
+    std::vector<double> dp(3 * nd), shifts(3 * 27);
+    for (int d = 0; d < nd; ++d) {   // points -d h: G(0, -d h + 8 o h) = g_o(d)
+        dp[3 * d] = -(d / 225 - 7) * h;
+        dp[3 * d + 1] = -((d / 15) % 15 - 7) * h;
+        dp[3 * d + 2] = -(d % 15 - 7) * h;
+    }
+    for (int t = 0; t < 27; ++t) {
+        shifts[3 * t] = 8.0 * (t / 9 - 1) * h;
+        shifts[3 * t + 1] = 8.0 * ((t / 3) % 3 - 1) * h;
+        shifts[3 * t + 2] = 8.0 * (t % 3 - 1) * h;
+    }
+    double *org, *dpd, *shd, *G;
+    KIFMM_TRY(upload(db, std::vector<double>(3, 0.0), &org, st));
+    KIFMM_TRY(upload(db, dp, &dpd, st));
+    KIFMM_TRY(upload(db, shifts, &shd, st));
+    KIFMM_TRY(db.get(&G, (size_t)27 * nd));
+    KIFMM_TRY(launch_kmat(org, 1, dpd, nd, nullptr, shd, 27, 0, o->kern, h, G, st));
+    std::vector<double> g((size_t)27 * nd);
+    KIFMM_HIP(hipMemcpyAsync(g.data(), G, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    KIFMM_HIP(hipStreamSynchronize(st));
+    std::vector<double> cs(16), sn(16);
+    for (int m = 0; m < 16; ++m) {
+        cs[m] = std::cos(2.0 * M_PI * m / 16.0);
+        sn[m] = std::sin(2.0 * M_PI * m / 16.0);
+    }
+    std::vector<float> out((size_t)27 * 2304 * 2);
+    std::vector<double> a((size_t)16 * 16 * 16), zr((size_t)16 * 16 * 9), zi(zr.size()), yr((size_t)16 * 16 * 9),
+        yi(yr.size());
+    for (int t = 0; t < 27; ++t) {
+        std::fill(a.begin(), a.end(), 0.0);
+        for (int d = 0; d < nd; ++d) {
+            const int x = (d / 225 - 7) & 15, y = ((d / 15) % 15 - 7) & 15, z = (d % 15 - 7) & 15;
+            a[(x * 16 + y) * 16 + z] = g[(size_t)t * nd + d];
+        }
+        for (int x = 0; x < 16; ++x)   // z
+            for (int y = 0; y < 16; ++y)
+                for (int kz = 0; kz < 9; ++kz) {
+                    double re = 0, im = 0;
+                    for (int z = 0; z < 16; ++z) {
+                        const double v = a[(x * 16 + y) * 16 + z];
+                        re += v * cs[(kz * z) & 15];
+                        im -= v * sn[(kz * z) & 15];
+                    }
+                    zr[(x * 16 + y) * 9 + kz] = re;
+                    zi[(x * 16 + y) * 9 + kz] = im;
+                }
+        for (int x = 0; x < 16; ++x)   // y
+            for (int ky = 0; ky < 16; ++ky)
+                for (int kz = 0; kz < 9; ++kz) {
+                    double re = 0, im = 0;
+                    for (int y = 0; y < 16; ++y) {
+                        const double vr = zr[(x * 16 + y) * 9 + kz], vi = zi[(x * 16 + y) * 9 + kz];
+                        const double c = cs[(ky * y) & 15], sv = sn[(ky * y) & 15];
+                        re += vr * c + vi * sv;
+                        im += vi * c - vr * sv;
+                    }
+                    yr[(x * 16 + ky) * 9 + kz] = re;
+                    yi[(x * 16 + ky) * 9 + kz] = im;
+                }
+        for (int kx = 0; kx < 16; ++kx)   // x
+            for (int ky = 0; ky < 16; ++ky)
+                for (int kz = 0; kz < 9; ++kz) {
+                    double re = 0, im = 0;
+                    for (int x = 0; x < 16; ++x) {
+                        const double vr = yr[(x * 16 + ky) * 9 + kz], vi = yi[(x * 16 + ky) * 9 + kz];
+                        const double c = cs[(kx * x) & 15], sv = sn[(kx * x) & 15];
+                        re += vr * c + vi * sv;
+                        im += vi * c - vr * sv;
+                    }
+                    const size_t f = (size_t)(ky * 9 + kz) * 16 + kx;
+                    out[((size_t)t * 2304 + f) * 2] = (float)re;
+                    out[((size_t)t * 2304 + f) * 2 + 1] = (float)im;
+                }
+    }
+    KIFMM_TRY(dmalloc(&o->near_gh, out.size()));
+    KIFMM_HIP(hipMemcpyAsync(o->near_gh, out.data(), out.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    KIFMM_HIP(hipStreamSynchronize(st));   // out is a host vector
+    return KIFMM_OK;
+}
+
 // FFT form of M2L for the lattice layout.  With y^u = x^d = the m0^3 lattice of spacing t
 // around the box centre, G(x^d_i, y^u_j + 2 r o) = g_o(i - j) with g_o(d) = G(d t - 2 r o).
 // On the cyclic grid of N = 2 m0 - 1 points per axis the differences i - j never wrap onto
@@ -728,6 +822,7 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(dmalloc(&o->p2p32, (size_t)27 * s * s));
     KIFMM_TRY(dmalloc(&o->p2p64, (size_t)27 * s * s));
     KIFMM_TRY(store_both(p2p, s, s, 27, o->p2p32, o->p2p64, s, s, st));
+    if (ell == 8) KIFMM_TRY(build_near_spectra(db, o, h, st));
     {
         double mx;
         KIFMM_TRY(max_abs_host(p2p, (size_t)27 * s * s, &mx, st));
@@ -1106,6 +1201,14 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
     const int s = o->s, nb = o->nb;
     const int64_t nleaf = (int64_t)nb * nb * nb;
     if constexpr (sizeof(T) == 4) {
+        if (o->p2p_fft && nb >= 4 && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
+            for (int stage = 0; stage < 3; ++stage) {
+                PassTimer pt(o, stage == 1 ? KIFMM_PASS_NEAR_PRODUCTS : -1, st);
+                KIFMM_TRY(run_near_fft_stage(stage, (const float *)q, o->near_gh, nb, want_of(o, o->D), nz_of(o, o->D),
+                                             o->near_q, o->near_p, (float *)out, st));
+            }
+            return KIFMM_OK;
+        }
         if (precision == KIFMM_BF16X3) {
             KIFMM_TRY(run_amax((const float *)q, nleaf * s, o->amax_q, o->n_amax, st));
             if (s > 64) {   // staged kernel on the split sources
@@ -1344,6 +1447,28 @@ int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable) {
         }
     }
     ops->skip_zero = true;
+    return KIFMM_OK;
+}
+
+int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    if (!enable) {
+        ops->p2p_fft = false;
+        return KIFMM_OK;
+    }
+    if (!ops->near_gh || ops->nb < 4)
+        return fail(KIFMM_EUNSUPPORTED, "the Fourier-space near field needs leaves of 8^3 cells and at least 4 per axis");
+    if (!ops->near_q) {
+        const size_t n = (size_t)ops->nb * ops->nb * ops->nb * 2304 * 2;
+        KIFMM_TRY(dmalloc(&ops->near_q, n));
+        const int rc = dmalloc(&ops->near_p, n);
+        if (rc != KIFMM_OK) {
+            (void)hipFree(ops->near_q);
+            ops->near_q = nullptr;
+            return rc;
+        }
+    }
+    ops->p2p_fft = true;
     return KIFMM_OK;
 }
 

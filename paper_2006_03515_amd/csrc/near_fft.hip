@@ -1,0 +1,234 @@
+// Near field in the Fourier domain (eq. (nearfar), direct part, with the self cell).
+//
+// On a uniform grid the near-range matrix between a target leaf and the leaf at offset o
+// (in leaves) has entries G(cell_i - cell_j - 8 o) that depend on i - j only: it applies
+// the kernel restricted to the differences d in [-7, 7]^3 + 8 o, a convolution.  On the
+// cyclic grid of 16 points per axis those differences never wrap onto one another, so
+//     S_t = inverse DFT( sum over the 27 neighbours o of Gh_o * DFT(q_{t+o}) )
+// restricted to the 8^3 cells of t, with Gh_o the half spectrum (16 x 16 x 9 complex
+// values) of the kernel of offset o, the self value included.  It is the same sum as the
+// dense near field up to FP32 rounding, with about a fourteenth of its arithmetic per leaf
+// (separable transforms and 27 complex products per frequency, against 27 dense 512 x 512
+// products).
+//
+// Frequencies (kx, ky, kz), kz <= 8, are stored per leaf at f = (ky * 9 + kz) * 16 + kx.
+//
+//   near_forward_kernel   one workgroup per source leaf: z, y and x transforms of the 8^3
+//                         values zero-padded to 16^3, through LDS; writes 2304 complex.
+//   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
+//                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
+//                         the block and the 27 kernel spectra are staged in LDS; lane = 16
+//                         frequencies x 16 groups of 4 targets, 27 taps at fixed offsets;
+//                         XCD-contiguous order of the workgroups.
+//   near_inverse_kernel   one workgroup per target leaf: x, y and z inverse transforms,
+//                         only the 8^3 cells of the leaf.
+#include "common.h"
+
+namespace kifmm {
+
+namespace {
+
+// cos and sin of 2 pi m / 16, m = 0..15; each kernel copies them to LDS, since the index
+// differs between lanes
+__constant__ float kCos16[16] = {1.0f,  0.92387953f,  0.70710678f,  0.38268343f,  0.0f, -0.38268343f, -0.70710678f, -0.92387953f,
+                                 -1.0f, -0.92387953f, -0.70710678f, -0.38268343f, -0.0f, 0.38268343f,  0.70710678f,  0.92387953f};
+__constant__ float kSin16[16] = {0.0f,  0.38268343f,  0.70710678f,  0.92387953f,  1.0f,  0.92387953f,  0.70710678f,  0.38268343f,
+                                 0.0f, -0.38268343f, -0.70710678f, -0.92387953f, -1.0f, -0.92387953f, -0.70710678f, -0.38268343f};
+
+constexpr int NF = 2304;   // 16 * 16 * 9 frequencies per leaf
+
+__global__ __launch_bounds__(256) void near_forward_kernel(const float *__restrict__ q, const uint8_t *__restrict__ in_nz,
+                                                           float2 *__restrict__ Q) {
+    __shared__ float qs[512];
+    __shared__ float2 Z[8 * 8 * 9];    // [x][y][kz]
+    __shared__ float2 Y[8 * 16 * 9];   // [x][ky][kz]
+    __shared__ float cs16[16], sn16[16];
+    const int tid = threadIdx.x;
+    const int64_t leaf = blockIdx.x;
+    if (in_nz && !in_nz[leaf]) return;   // never read: the products skip zero leaves
+    if (tid < 16) {
+        cs16[tid] = kCos16[tid];
+        sn16[tid] = kSin16[tid];
+    }
+    qs[tid] = q[leaf * 512 + tid];
+    qs[tid + 256] = q[leaf * 512 + 256 + tid];
+    __syncthreads();
+    for (int e = tid; e < 576; e += 256) {   // z: real in, kz = 0..8
+        const int x = e / 72, y = (e / 9) % 8, kz = e % 9;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            const float v = qs[(x * 8 + y) * 8 + z];
+            const int m = (kz * z) & 15;
+            re += v * cs16[m];
+            im -= v * sn16[m];
+        }
+        Z[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < 1152; e += 256) {   // y: ky = 0..15
+        const int x = e / 144, ky = (e / 9) % 16, kz = e % 9;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            const float2 v = Z[(x * 8 + y) * 9 + kz];
+            const int m = (ky * y) & 15;
+            const float c = cs16[m], s = sn16[m];
+            re += v.x * c + v.y * s;
+            im += v.y * c - v.x * s;
+        }
+        Y[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int f = tid; f < NF; f += 256) {   // x: kx = 0..15, written at f = (ky * 9 + kz) * 16 + kx
+        const int kx = f & 15, r = f >> 4;   // r = ky * 9 + kz
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const float2 v = Y[x * 144 + r];
+            const int m = (kx * x) & 15;
+            const float c = cs16[m], s = sn16[m];
+            re += v.x * c + v.y * s;
+            im += v.y * c - v.x * s;
+        }
+        Q[leaf * NF + f] = make_float2(re, im);
+    }
+}
+
+__global__ __launch_bounds__(256) void near_products_kernel(const float2 *__restrict__ Q, const float2 *__restrict__ Gh,
+                                                            int nb, const uint8_t *__restrict__ out_need,
+                                                            const uint8_t *__restrict__ in_nz, float2 *__restrict__ P) {
+    __shared__ float2 Es[216 * 16];   // [region leaf][kx]
+    __shared__ float2 Gs[27 * 16];    // [offset][kx]
+    const int tid = threadIdx.x, lane = tid & 63;
+    // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
+    // (frequency chunk, block) pairs, blocks fastest, so the neighbouring blocks that share
+    // source spectra run out of the same L2.
+    const int64_t nblk = (int64_t)nb * nb * nb / 64, total = nblk * (NF / 16);
+    const int64_t wg = blockIdx.x;
+    const int64_t lin = total % 8 == 0 ? (wg % 8) * (total / 8) + wg / 8 : wg;
+    const int64_t blk = lin % nblk;
+    const int f0 = (int)(lin / nblk) * 16;
+    if (out_need) {   // the same ballot in every wave: all return or none
+        if (__ballot(out_need[64 * blk + lane] != 0) == 0) return;
+    }
+    int bx, by, bz;
+    morton_decode((uint32_t)blk, bx, by, bz);
+    bx = 4 * bx - 1;
+    by = 4 * by - 1;
+    bz = 4 * bz - 1;
+    for (int e = tid; e < 216 * 8; e += 256) {   // 16 frequencies = 8 float4 per leaf
+        const int r = e >> 3, part = e & 7;
+        const int x = bx + r / 36, y = by + (r / 6) % 6, z = bz + r % 6;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (x >= 0 && y >= 0 && z >= 0 && x < nb && y < nb && z < nb) {
+            const int64_t src = morton_encode(x, y, z);
+            if (!in_nz || in_nz[src]) v = ((const float4 *)(Q + src * NF + f0))[part];
+        }
+        ((float4 *)Es)[e] = v;
+    }
+    for (int e = tid; e < 27 * 8; e += 256) ((float4 *)Gs)[e] = ((const float4 *)(Gh + (int64_t)(e >> 3) * NF + f0))[e & 7];
+    __syncthreads();
+    const int f = tid & 15, grp = tid >> 4;   // 16 groups of 4 targets
+    int tl[4], tr[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int n = 4 * grp + s;   // local Morton index of the target in the block
+        int a, b, c;
+        morton_decode((uint32_t)n, a, b, c);
+        tl[s] = n;
+        tr[s] = (((a + 1) * 6 + (b + 1)) * 6 + (c + 1)) * 16 + f;
+    }
+    float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        const int off = ((o / 9 - 1) * 36 + ((o / 3) % 3 - 1) * 6 + (o % 3 - 1)) * 16;
+        const float2 g = Gs[o * 16 + f];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float2 e = Es[tr[s] + off];
+            ar[s] += g.x * e.x - g.y * e.y;
+            ai[s] += g.x * e.y + g.y * e.x;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) P[(64 * blk + tl[s]) * NF + f0 + f] = make_float2(ar[s], ai[s]);
+}
+
+__global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ P,
+                                                           const uint8_t *__restrict__ out_need, float *__restrict__ S) {
+    __shared__ float2 Ps[NF];
+    __shared__ float2 U[8 * 144];   // [x][ky * 9 + kz]
+    __shared__ float2 V[8 * 8 * 9]; // [x][y][kz]
+    __shared__ float cs16[16], sn16[16];
+    const int tid = threadIdx.x;
+    const int64_t leaf = blockIdx.x;
+    if (out_need && !out_need[leaf]) return;   // never read: the final sum writes 0 there
+    if (tid < 16) {
+        cs16[tid] = kCos16[tid];
+        sn16[tid] = kSin16[tid];
+    }
+    for (int e = tid; e < NF / 2; e += 256) ((float4 *)Ps)[e] = ((const float4 *)(P + leaf * NF))[e];
+    __syncthreads();
+    for (int e = tid; e < 1152; e += 256) {   // x: e^{+i theta}
+        const int x = e / 144, r = e % 144;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int kx = 0; kx < 16; ++kx) {
+            const float2 v = Ps[r * 16 + kx];
+            const int m = (kx * x) & 15;
+            const float c = cs16[m], s = sn16[m];
+            re += v.x * c - v.y * s;
+            im += v.y * c + v.x * s;
+        }
+        U[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < 576; e += 256) {   // y
+        const int x = e / 72, y = (e / 9) % 8, kz = e % 9;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int ky = 0; ky < 16; ++ky) {
+            const float2 v = U[x * 144 + ky * 9 + kz];
+            const int m = (ky * y) & 15;
+            const float c = cs16[m], s = sn16[m];
+            re += v.x * c - v.y * s;
+            im += v.y * c + v.x * s;
+        }
+        V[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < 512; e += 256) {   // z: real part, the conjugate half counted twice
+        const int x = e >> 6, y = (e >> 3) & 7, z = e & 7;
+        float acc = 0.f;
+#pragma unroll
+        for (int kz = 0; kz < 9; ++kz) {
+            const float2 v = V[(x * 8 + y) * 9 + kz];
+            const int m = (kz * z) & 15;
+            const float w = (kz == 0 || kz == 8) ? 1.f : 2.f;
+            acc += w * (v.x * cs16[m] - v.y * sn16[m]);
+        }
+        S[leaf * 512 + e] = acc * (1.0f / 4096.0f);
+    }
+}
+
+}  // namespace
+
+// stage 0: spectra of the sources, 1: products, 2: inverse transforms into S
+int run_near_fft_stage(int stage, const float *q, const float *Gh, int nb, const uint8_t *out_need,
+                       const uint8_t *in_nz, float *Qbuf, float *Pbuf, float *S, hipStream_t st) {
+    if (nb < 4 || (nb & (nb - 1)) != 0) return fail(KIFMM_EINVAL, "near-field spectra: leaves per axis must be 4, 8, 16, ...");
+    const int64_t nleaf = (int64_t)nb * nb * nb;
+    if (stage == 0)
+        hipLaunchKernelGGL(near_forward_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, q, in_nz, (float2 *)Qbuf);
+    else if (stage == 1)
+        hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16))), dim3(256), 0, st,
+                           (const float2 *)Qbuf, (const float2 *)Gh, nb, out_need, in_nz, (float2 *)Pbuf);
+    else
+        hipLaunchKernelGGL(near_inverse_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, (const float2 *)Pbuf, out_need,
+                           S);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+}  // namespace kifmm

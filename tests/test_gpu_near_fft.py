@@ -1,0 +1,85 @@
+"""Near field in Fourier space (HIP) against the dense near field and the oracle's exact
+sum: the same sums of eq. (nearfar), direct part, up to FP32 rounding."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as odirect
+from paper_2006_03515_amd import embedding, workloads
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2006_03515_amd import kifmm
+    return kifmm
+
+
+@pytest.mark.parametrize("n,layout", [(32, "nested"), (64, "nested"), (128, "lattice")])
+def test_near_fft_is_the_dense_near_field(K, n, layout):
+    # random sources; leaves of 8^3 (4 to 16 per axis); FP32 and split BF16 evaluations with
+    # the near field in Fourier space against the dense near field and the exact sum
+    L, p_o2 = n * 1.5625e-3, 150.0
+    I = np.random.default_rng(50 + n).random((n, n, n)).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, L), 512)
+    lay = K.LAYOUT_NESTED if layout == "nested" else K.LAYOUT_LATTICE
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(lay, 5, 10, 1e-5))
+    It = torch.from_numpy(I.ravel()).cuda()
+    ref = odirect.fft_full(I.astype(np.float64), (L / n,) * 3, p_o2).ravel()
+    for prec in ("fp32", "bf16x3"):
+        ops.p2p_fft(False)
+        a = K.eval(tree, ops, It, 1.0, precision=prec).double().cpu().numpy()
+        ops.p2p_fft(True)
+        b = K.eval(tree, ops, It, 1.0, precision=prec).double().cpu().numpy()
+        assert rel_l2(b, a) < (1e-6 if prec == "fp32" else 1e-5), prec
+        assert rel_l2(b, ref) < 1e-4
+    ops.p2p_fft(False)
+
+
+def test_near_fft_streamer_256(K, record_property):
+    # the benchmark channel: a source spanning six orders of magnitude; the Fourier-space
+    # near field against the dense one, whole field and at 4,096 sampled cells
+    w = workloads.streamer_channel(n=256, L=0.4, p=760.0)
+    tree = K.build_tree(K.Grid.cube(256, w.L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(w.p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    It = torch.from_numpy(np.ascontiguousarray(w.I.astype(np.float32).ravel())).cuda()
+    a = K.eval(tree, ops, It, w.prefactor).double().cpu().numpy()
+    ops.p2p_fft(True)
+    b = K.eval(tree, ops, It, w.prefactor).double().cpu().numpy()
+    tg = workloads.sample_targets(256 ** 3, 4096, seed=1009)
+    full, samp = rel_l2(b, a), rel_l2(b[tg], a[tg])
+    record_property("near_fft_vs_dense_full", full)
+    print("near field in Fourier space vs dense: full %.2e, sampled %.2e" % (full, samp))
+    assert full < 1e-6 and samp < 2e-6
+
+
+def test_near_fft_with_skipping_and_restriction(K):
+    n, L, p_o2 = 64, 0.1, 150.0
+    shape = (40, 24, 36)
+    I = np.zeros((n, n, n), dtype=np.float32)
+    I[:shape[0], :shape[1], :shape[2]] = np.random.default_rng(52).random(shape).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5))
+    ops.p2p_fft(True)
+    It = torch.from_numpy(I.ravel()).cuda()
+    a = K.eval(tree, ops, It, 1.0).reshape(n, n, n)
+    ops.skip_zero_sources(True)
+    b = K.eval(tree, ops, It, 1.0).reshape(n, n, n)
+    assert float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a)) < 2e-6
+    m = embedding.leaf_mask(shape, n, tree.leaf_side)
+    ops.restrict_targets(m)
+    c = K.eval(tree, ops, It, 1.0).reshape(n, n, n)
+    cells = torch.from_numpy(np.kron(m, np.ones((tree.leaf_side,) * 3, dtype=np.uint8)) != 0).cuda()
+    assert torch.equal(c[cells], b[cells])
+    assert int(torch.count_nonzero(c[~cells])) == 0
+
+
+def test_near_fft_needs_leaves_of_8(K):
+    tree = K.build_tree(K.Grid.cube(32, 0.1), 64)
+    ops = K.precompute_operators(tree, K.Kernel(150.0), K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5))
+    ops.p2p_fft(False)
+    with pytest.raises(K.KifmmError) as e:
+        ops.p2p_fft(True)
+    assert e.value.code == K.EUNSUPPORTED
