@@ -93,10 +93,10 @@ __global__ __launch_bounds__(512) void m2l_hadamard_kernel(const float2 *__restr
         const float2 kv = g[(int64_t)op * nfp];
         const float2 e0 = Es[(tb[0] + delta) * HFC + f];
         const float2 e1 = Es[(tb[1] + delta) * HFC + f];
-        ar0 += kv.x * e0.x - kv.y * e0.y;
-        ai0 += kv.x * e0.y + kv.y * e0.x;
-        ar1 += kv.x * e1.x - kv.y * e1.y;
-        ai1 += kv.x * e1.y + kv.y * e1.x;
+        ar0 = fmaf(kv.x, e0.x, fmaf(-kv.y, e0.y, ar0));
+        ai0 = fmaf(kv.x, e0.y, fmaf(kv.y, e0.x, ai0));
+        ar1 = fmaf(kv.x, e1.x, fmaf(-kv.y, e1.y, ar1));
+        ai1 = fmaf(kv.x, e1.y, fmaf(kv.y, e1.x, ai1));
     }
     P[(64 * blk + tl[0]) * nfp + f0 + f] = make_float2(ar0, ai0);
     P[(64 * blk + tl[1]) * nfp + f0 + f] = make_float2(ar1, ai1);

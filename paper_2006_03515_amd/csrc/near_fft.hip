@@ -18,7 +18,9 @@
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
-//                         frequencies x 16 groups of 4 targets, 27 taps at fixed offsets;
+//                         frequencies x 16 groups of 4 targets, 27 taps at fixed offsets.
+//                         A workgroup takes 4 chunks of 16 frequencies in turn, the next
+//                         chunk's spectra in flight (registers) while one is multiplied;
 //                         XCD-contiguous order of the workgroups.
 //   near_inverse_kernel   one workgroup per target leaf: x, y and z inverse transforms,
 //                         only the 8^3 cells of the leaf.
@@ -60,8 +62,8 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
         for (int z = 0; z < 8; ++z) {
             const float v = qs[(x * 8 + y) * 8 + z];
             const int m = (kz * z) & 15;
-            re += v * cs16[m];
-            im -= v * sn16[m];
+            re = fmaf(v, cs16[m], re);
+            im = fmaf(-v, sn16[m], im);
         }
         Z[e] = make_float2(re, im);
     }
@@ -74,8 +76,8 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
             const float2 v = Z[(x * 8 + y) * 9 + kz];
             const int m = (ky * y) & 15;
             const float c = cs16[m], s = sn16[m];
-            re += v.x * c + v.y * s;
-            im += v.y * c - v.x * s;
+            re = fmaf(v.x, c, fmaf(v.y, s, re));
+            im = fmaf(v.y, c, fmaf(-v.x, s, im));
         }
         Y[e] = make_float2(re, im);
     }
@@ -88,12 +90,14 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
             const float2 v = Y[x * 144 + r];
             const int m = (kx * x) & 15;
             const float c = cs16[m], s = sn16[m];
-            re += v.x * c + v.y * s;
-            im += v.y * c - v.x * s;
+            re = fmaf(v.x, c, fmaf(v.y, s, re));
+            im = fmaf(v.y, c, fmaf(-v.x, s, im));
         }
         Q[leaf * NF + f] = make_float2(re, im);
     }
 }
+
+constexpr int NCH = 4;   // frequency chunks per products workgroup
 
 __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__restrict__ Q, const float2 *__restrict__ Gh,
                                                             int nb, const uint8_t *__restrict__ out_need,
@@ -102,13 +106,13 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
     __shared__ float2 Gs[27 * 16];    // [offset][kx]
     const int tid = threadIdx.x, lane = tid & 63;
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
-    // (frequency chunk, block) pairs, blocks fastest, so the neighbouring blocks that share
+    // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
     // source spectra run out of the same L2.
-    const int64_t nblk = (int64_t)nb * nb * nb / 64, total = nblk * (NF / 16);
+    const int64_t nblk = (int64_t)nb * nb * nb / 64, total = nblk * (NF / 16 / NCH);
     const int64_t wg = blockIdx.x;
     const int64_t lin = total % 8 == 0 ? (wg % 8) * (total / 8) + wg / 8 : wg;
     const int64_t blk = lin % nblk;
-    const int f0 = (int)(lin / nblk) * 16;
+    const int c0 = (int)(lin / nblk) * NCH;   // first of this workgroup's chunks of 16 frequencies
     if (out_need) {   // the same ballot in every wave: all return or none
         if (__ballot(out_need[64 * blk + lane] != 0) == 0) return;
     }
@@ -117,18 +121,27 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
     bx = 4 * bx - 1;
     by = 4 * by - 1;
     bz = 4 * bz - 1;
-    for (int e = tid; e < 216 * 8; e += 256) {   // 16 frequencies = 8 float4 per leaf
-        const int r = e >> 3, part = e & 7;
-        const int x = bx + r / 36, y = by + (r / 6) % 6, z = bz + r % 6;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (x >= 0 && y >= 0 && z >= 0 && x < nb && y < nb && z < nb) {
-            const int64_t src = morton_encode(x, y, z);
-            if (!in_nz || in_nz[src]) v = ((const float4 *)(Q + src * NF + f0))[part];
+    // this thread's share of the staging: region leaves of e = tid + 256 i (8 float4 each)
+    const float4 *src[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int e = tid + 256 * i, r = e >> 3;
+        src[i] = nullptr;
+        if (e < 216 * 8) {
+            const int x = bx + r / 36, y = by + (r / 6) % 6, z = bz + r % 6;
+            if (x >= 0 && y >= 0 && z >= 0 && x < nb && y < nb && z < nb) {
+                const int64_t leaf = morton_encode(x, y, z);
+                if (!in_nz || in_nz[leaf]) src[i] = (const float4 *)(Q + leaf * NF) + (e & 7);
+            }
         }
-        ((float4 *)Es)[e] = v;
     }
-    for (int e = tid; e < 27 * 8; e += 256) ((float4 *)Gs)[e] = ((const float4 *)(Gh + (int64_t)(e >> 3) * NF + f0))[e & 7];
-    __syncthreads();
+    const float4 *gsrc = tid < 27 * 8 ? (const float4 *)(Gh + (int64_t)(tid >> 3) * NF) + (tid & 7) : nullptr;
+    float4 pre[7], gpre;
+    auto fetch = [&](int c) {   // chunk c: frequencies 16 c .. 16 c + 15 (8 float4 per leaf)
+#pragma unroll
+        for (int i = 0; i < 7; ++i) pre[i] = src[i] ? src[i][c * 8] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gsrc) gpre = gsrc[c * 8];
+    };
     const int f = tid & 15, grp = tid >> 4;   // 16 groups of 4 targets
     int tl[4], tr[4];
 #pragma unroll
@@ -139,20 +152,30 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         tl[s] = n;
         tr[s] = (((a + 1) * 6 + (b + 1)) * 6 + (c + 1)) * 16 + f;
     }
-    float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+    fetch(c0);
+    for (int c = c0; c < c0 + NCH; ++c) {
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-        const int off = ((o / 9 - 1) * 36 + ((o / 3) % 3 - 1) * 6 + (o % 3 - 1)) * 16;
-        const float2 g = Gs[o * 16 + f];
+        for (int i = 0; i < 7; ++i)
+            if (tid + 256 * i < 216 * 8) ((float4 *)Es)[tid + 256 * i] = pre[i];
+        if (gsrc) ((float4 *)Gs)[tid] = gpre;
+        __syncthreads();
+        if (c + 1 < c0 + NCH) fetch(c + 1);   // in flight while this chunk is multiplied
+        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const float2 e = Es[tr[s] + off];
-            ar[s] += g.x * e.x - g.y * e.y;
-            ai[s] += g.x * e.y + g.y * e.x;
+        for (int o = 0; o < 27; ++o) {
+            const int off = ((o / 9 - 1) * 36 + ((o / 3) % 3 - 1) * 6 + (o % 3 - 1)) * 16;
+            const float2 g = Gs[o * 16 + f];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float2 e = Es[tr[s] + off];
+                ar[s] = fmaf(g.x, e.x, fmaf(-g.y, e.y, ar[s]));
+                ai[s] = fmaf(g.x, e.y, fmaf(g.y, e.x, ai[s]));
+            }
         }
-    }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) P[(64 * blk + tl[s]) * NF + f0 + f] = make_float2(ar[s], ai[s]);
+        for (int s = 0; s < 4; ++s) P[(64 * blk + tl[s]) * NF + c * 16 + f] = make_float2(ar[s], ai[s]);
+        __syncthreads();   // the staging of the next chunk overwrites Es and Gs
+    }
 }
 
 __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ P,
@@ -178,8 +201,8 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
             const float2 v = Ps[r * 16 + kx];
             const int m = (kx * x) & 15;
             const float c = cs16[m], s = sn16[m];
-            re += v.x * c - v.y * s;
-            im += v.y * c + v.x * s;
+            re = fmaf(v.x, c, fmaf(-v.y, s, re));
+            im = fmaf(v.y, c, fmaf(v.x, s, im));
         }
         U[e] = make_float2(re, im);
     }
@@ -192,8 +215,8 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
             const float2 v = U[x * 144 + ky * 9 + kz];
             const int m = (ky * y) & 15;
             const float c = cs16[m], s = sn16[m];
-            re += v.x * c - v.y * s;
-            im += v.y * c + v.x * s;
+            re = fmaf(v.x, c, fmaf(-v.y, s, re));
+            im = fmaf(v.y, c, fmaf(v.x, s, im));
         }
         V[e] = make_float2(re, im);
     }
@@ -206,7 +229,7 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
             const float2 v = V[(x * 8 + y) * 9 + kz];
             const int m = (kz * z) & 15;
             const float w = (kz == 0 || kz == 8) ? 1.f : 2.f;
-            acc += w * (v.x * cs16[m] - v.y * sn16[m]);
+            acc = fmaf(w * v.x, cs16[m], fmaf(-w * v.y, sn16[m], acc));
         }
         S[leaf * 512 + e] = acc * (1.0f / 4096.0f);
     }
@@ -222,7 +245,7 @@ int run_near_fft_stage(int stage, const float *q, const float *Gh, int nb, const
     if (stage == 0)
         hipLaunchKernelGGL(near_forward_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, q, in_nz, (float2 *)Qbuf);
     else if (stage == 1)
-        hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16))), dim3(256), 0, st,
+        hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16 / NCH))), dim3(256), 0, st,
                            (const float2 *)Qbuf, (const float2 *)Gh, nb, out_need, in_nz, (float2 *)Pbuf);
     else
         hipLaunchKernelGGL(near_inverse_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, (const float2 *)Pbuf, out_need,
