@@ -208,7 +208,7 @@ int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
  * 27 complex products per frequency against the kernel spectra of the 27 neighbour
  * offsets (built in FP64 with the operators), and the inverse transform at the 8^3 cells.
  * Same sum as the dense near field up to FP32 rounding (about 1e-7 of the result).  The
- * first enable allocates two spectra buffers of 18 KiB per leaf (owned by ops).  Returns
+ * first enable allocates spectra buffers of 27 KiB per leaf (owned by ops).  Returns
  * 0, KIFMM_EINVAL (ops NULL), KIFMM_EUNSUPPORTED (leaves other than 8^3, or fewer than 4
  * per axis) or KIFMM_ENOMEM. */
 int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable);

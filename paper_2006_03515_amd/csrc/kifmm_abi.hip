@@ -190,8 +190,9 @@ struct kifmm_ops_s {
     std::vector<float *> fft_g, fft_f, fft_i;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
-    // kernel of the 27 neighbour offsets [27][2304] complex, and per-leaf spectra of the
-    // sources and of the sums [nleaf][2304] complex (allocated when first enabled)
+    // kernel of the 27 neighbour offsets [27][2304] complex, per-leaf spectra of the sources
+    // [nleaf][2304] complex, and the sums after the first inverse stage [nleaf][144][8]
+    // complex (allocated when first enabled)
     bool p2p_fft = false;
     float *near_gh = nullptr, *near_q = nullptr, *near_p = nullptr;
     float *spec_e = nullptr, *spec_p = nullptr;
@@ -1461,7 +1462,7 @@ int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable) {
     if (!ops->near_q) {
         const size_t n = (size_t)ops->nb * ops->nb * ops->nb * 2304 * 2;
         KIFMM_TRY(dmalloc(&ops->near_q, n));
-        const int rc = dmalloc(&ops->near_p, n);
+        const int rc = dmalloc(&ops->near_p, n / 2);   // 8 of the 16 kx values: after the x stage
         if (rc != KIFMM_OK) {
             (void)hipFree(ops->near_q);
             ops->near_q = nullptr;

@@ -22,7 +22,9 @@
 //                         A workgroup takes 4 chunks of 16 frequencies in turn, the next
 //                         chunk's spectra in flight (registers) while one is multiplied;
 //                         XCD-contiguous order of the workgroups.
-//   near_inverse_kernel   one workgroup per target leaf: x, y and z inverse transforms,
+//                         Each chunk ends with the first inverse stage (over kx, at the 8
+//                         cells x of the leaf), so 8 values per (ky, kz) are written.
+//   near_inverse_kernel   one workgroup per target leaf: the y and z inverse transforms,
 //                         only the 8^3 cells of the leaf.
 #include "common.h"
 
@@ -104,7 +106,13 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
                                                             const uint8_t *__restrict__ in_nz, float2 *__restrict__ P) {
     __shared__ float2 Es[216 * 16];   // [region leaf][kx]
     __shared__ float2 Gs[27 * 16];    // [offset][kx]
+    __shared__ float2 Ps[64 * 17];    // [target][kx] sums of one chunk (padded row)
+    __shared__ float cs16[16], sn16[16];
     const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < 16) {
+        cs16[tid] = kCos16[tid];
+        sn16[tid] = kSin16[tid];
+    }
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
     // source spectra run out of the same L2.
@@ -173,16 +181,32 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
             }
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) P[(64 * blk + tl[s]) * NF + c * 16 + f] = make_float2(ar[s], ai[s]);
-        __syncthreads();   // the staging of the next chunk overwrites Es and Gs
+        for (int s = 0; s < 4; ++s) Ps[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
+        __syncthreads();
+        // first inverse stage, over kx, at the 8 cells x of each target: this chunk holds all
+        // 16 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 16}
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = tid >> 2, x = 2 * (tid & 3) + h;
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int kx = 0; kx < 16; ++kx) {
+                const float2 v = Ps[t * 17 + kx];
+                const int m = (kx * x) & 15;
+                const float cc = cs16[m], ss = sn16[m];
+                re = fmaf(v.x, cc, fmaf(-v.y, ss, re));
+                im = fmaf(v.y, cc, fmaf(v.x, ss, im));
+            }
+            P[((64 * blk + t) * (NF / 16) + c) * 8 + x] = make_float2(re, im);
+        }
+        __syncthreads();   // the staging of the next chunk overwrites Es, Gs and Ps
     }
 }
 
-__global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ P,
+__global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ U,
                                                            const uint8_t *__restrict__ out_need, float *__restrict__ S) {
-    __shared__ float2 Ps[NF];
-    __shared__ float2 U[8 * 144];   // [x][ky * 9 + kz]
-    __shared__ float2 V[8 * 8 * 9]; // [x][y][kz]
+    __shared__ float2 Us[144 * 8];   // [ky * 9 + kz][x], after the x stage (products kernel)
+    __shared__ float2 V[8 * 8 * 9];  // [x][y][kz]
     __shared__ float cs16[16], sn16[16];
     const int tid = threadIdx.x;
     const int64_t leaf = blockIdx.x;
@@ -191,28 +215,14 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
         cs16[tid] = kCos16[tid];
         sn16[tid] = kSin16[tid];
     }
-    for (int e = tid; e < NF / 2; e += 256) ((float4 *)Ps)[e] = ((const float4 *)(P + leaf * NF))[e];
+    for (int e = tid; e < 144 * 4; e += 256) ((float4 *)Us)[e] = ((const float4 *)(U + leaf * 1152))[e];
     __syncthreads();
-    for (int e = tid; e < 1152; e += 256) {   // x: e^{+i theta}
-        const int x = e / 144, r = e % 144;
-        float re = 0.f, im = 0.f;
-#pragma unroll
-        for (int kx = 0; kx < 16; ++kx) {
-            const float2 v = Ps[r * 16 + kx];
-            const int m = (kx * x) & 15;
-            const float c = cs16[m], s = sn16[m];
-            re = fmaf(v.x, c, fmaf(-v.y, s, re));
-            im = fmaf(v.y, c, fmaf(v.x, s, im));
-        }
-        U[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    for (int e = tid; e < 576; e += 256) {   // y
+    for (int e = tid; e < 576; e += 256) {   // y: e^{+i theta}
         const int x = e / 72, y = (e / 9) % 8, kz = e % 9;
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int ky = 0; ky < 16; ++ky) {
-            const float2 v = U[x * 144 + ky * 9 + kz];
+            const float2 v = Us[(ky * 9 + kz) * 8 + x];
             const int m = (ky * y) & 15;
             const float c = cs16[m], s = sn16[m];
             re = fmaf(v.x, c, fmaf(-v.y, s, re));
