@@ -18,7 +18,8 @@
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
-//                         frequencies x 16 groups of 4 targets, 27 taps at fixed offsets.
+//                         frequencies x 16 columns of 4 targets along z (the 12 taps of a
+//                         column at one (ox, oy) read 6 source spectra).
 //                         A workgroup takes 4 chunks of 16 frequencies in turn, the next
 //                         chunk's spectra in flight (registers) while one is multiplied;
 //                         XCD-contiguous order of the workgroups.
@@ -150,16 +151,13 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         for (int i = 0; i < 7; ++i) pre[i] = src[i] ? src[i][c * 8] : make_float4(0.f, 0.f, 0.f, 0.f);
         if (gsrc) gpre = gsrc[c * 8];
     };
-    const int f = tid & 15, grp = tid >> 4;   // 16 groups of 4 targets
-    int tl[4], tr[4];
+    // lane: frequency f and a column of 4 targets (a, b, 0..3) of the block, so that for
+    // each (ox, oy) the 4 targets' 12 taps read 6 source spectra
+    const int f = tid & 15, grp = tid >> 4, ta = grp >> 2, tb = grp & 3;
+    int tl[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int n = 4 * grp + s;   // local Morton index of the target in the block
-        int a, b, c;
-        morton_decode((uint32_t)n, a, b, c);
-        tl[s] = n;
-        tr[s] = (((a + 1) * 6 + (b + 1)) * 6 + (c + 1)) * 16 + f;
-    }
+    for (int s = 0; s < 4; ++s) tl[s] = (int)morton_encode(ta, tb, s);
+    const int col = (((ta + 1) * 6 + (tb + 1)) * 6) * 16 + f;   // region (ta+1, tb+1, 0)
     fetch(c0);
     for (int c = c0; c < c0 + NCH; ++c) {
 #pragma unroll
@@ -170,15 +168,21 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         if (c + 1 < c0 + NCH) fetch(c + 1);   // in flight while this chunk is multiplied
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int o = 0; o < 27; ++o) {
-            const int off = ((o / 9 - 1) * 36 + ((o / 3) % 3 - 1) * 6 + (o % 3 - 1)) * 16;
-            const float2 g = Gs[o * 16 + f];
+        for (int oxy = 0; oxy < 9; ++oxy) {   // (ox, oy); oz and the 4 targets share 6 sources
+            const int base = col + ((oxy / 3 - 1) * 36 + (oxy % 3 - 1) * 6) * 16;
+            float2 e[6], g[3];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const float2 e = Es[tr[s] + off];
-                ar[s] = fmaf(g.x, e.x, fmaf(-g.y, e.y, ar[s]));
-                ai[s] = fmaf(g.x, e.y, fmaf(g.y, e.x, ai[s]));
-            }
+            for (int z = 0; z < 6; ++z) e[z] = Es[base + z * 16];
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) g[oz] = Gs[(oxy * 3 + oz) * 16 + f];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int oz = 0; oz < 3; ++oz) {   // source z = s + oz - 1, region z = s + oz
+                    const float2 v = e[s + oz];
+                    ar[s] = fmaf(g[oz].x, v.x, fmaf(-g[oz].y, v.y, ar[s]));
+                    ai[s] = fmaf(g[oz].x, v.y, fmaf(g[oz].y, v.x, ai[s]));
+                }
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) Ps[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
