@@ -28,7 +28,7 @@ int hip_fail(hipError_t e, const char *what) {
 int launch_direct(const kifmm_grid *, const kifmm_kernel *, const float *, double, const int64_t *,
                   int64_t, double *, int, hipStream_t);
 int launch_morton_scatter(const Tree &, hipStream_t);
-template <typename T> int launch_permute_in(const Tree &, const T *, T *, hipStream_t);
+template <typename T> int launch_permute_in(const Tree &, const T *, T, T *, hipStream_t);
 template <typename T> int launch_permute_out(const Tree &, const T *, T, const uint8_t *, T *, hipStream_t);
 int launch_perm_i64(const Tree &, int64_t *, hipStream_t);
 int launch_kmat(const double *, int, const double *, int, const double *, const double *, int, int,
@@ -1293,10 +1293,12 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     T *q = (T *)o->q, *Sp = (T *)o->Sp, *SpN = (T *)o->SpN;
     const int D = o->D, s = o->s, nb = o->nb, KU = o->KU, KD = o->KD;
     const int64_t nleaf = (int64_t)nb * nb * nb;
-    const T scale = (T)(prefactor * t->h * t->h * t->h);
+    // the cell volume goes in with the sources (q = I h^3), the prefactor on the way out:
+    // FP32 sums of G I alone reach 1e37 for fine cells and bright sources
+    const T vol = (T)(t->h * t->h * t->h), scale = (T)prefactor;
     {
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
-        KIFMM_TRY(launch_permute_in<T>(*t, I, q, st));
+        KIFMM_TRY(launch_permute_in<T>(*t, I, vol, q, st));
     }
     if (o->skip_zero && D >= 2) KIFMM_TRY(mark_nonzero_sources<T>(o, q, st));
     if (D < 2) {   // every leaf is in every other leaf's near range

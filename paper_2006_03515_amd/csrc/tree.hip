@@ -41,12 +41,12 @@ __device__ inline int64_t cell_of_slot(int64_t p, int n, int lg_ell) {
     return ((int64_t)i * n + j) * n + k;
 }
 
-// q[p] = I[cell(p)] (FP32 or FP64 in, same type out)
+// q[p] = scale * I[cell(p)] (FP32 or FP64 in, same type out)
 template <typename T>
-__global__ void permute_in_kernel(const T *__restrict__ I, int n, int lg_ell, int64_t N, T *__restrict__ q) {
+__global__ void permute_in_kernel(const T *__restrict__ I, int n, int lg_ell, int64_t N, T scale, T *__restrict__ q) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
-        q[p] = I[cell_of_slot(p, n, lg_ell)];
+        q[p] = I[cell_of_slot(p, n, lg_ell)] * scale;
 }
 
 // S[cell(p)] = scale * Sp[p], or 0 where want (one byte per leaf, Morton order; null: every
@@ -101,9 +101,9 @@ int launch_morton_scatter(const Tree &t, hipStream_t st) {
 }
 
 template <typename T>
-int launch_permute_in(const Tree &t, const T *I, T *q, hipStream_t st) {
+int launch_permute_in(const Tree &t, const T *I, T scale, T *q, hipStream_t st) {
     hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.n, lg_of(t.ell),
-                       t.N, q);
+                       t.N, scale, q);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
@@ -136,8 +136,8 @@ int launch_perm_i64(const Tree &t, int64_t *out, hipStream_t st) {
     return KIFMM_OK;
 }
 
-template int launch_permute_in<float>(const Tree &, const float *, float *, hipStream_t);
-template int launch_permute_in<double>(const Tree &, const double *, double *, hipStream_t);
+template int launch_permute_in<float>(const Tree &, const float *, float, float *, hipStream_t);
+template int launch_permute_in<double>(const Tree &, const double *, double, double *, hipStream_t);
 template int launch_permute_out<float>(const Tree &, const float *, float, const uint8_t *, float *,
                                        hipStream_t);
 template int launch_permute_out<double>(const Tree &, const double *, double, const uint8_t *, double *,

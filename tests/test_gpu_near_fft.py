@@ -83,3 +83,20 @@ def test_near_fft_needs_leaves_of_8(K):
     with pytest.raises(K.KifmmError) as e:
         ops.p2p_fft(True)
     assert e.value.code == K.EUNSUPPORTED
+
+
+def test_bright_sources_on_fine_cells_stay_finite(K):
+    # the Section 4.1 case-2 regime: cells of 1.25 um and sources near 1.5e25; the cell volume
+    # enters with the sources, so neither the spectra nor the dense sums leave FP32's range
+    n, h, p_o2 = 32, 1.25e-4, 150.0
+    I = (1.5e25 * (0.5 + 0.5 * np.random.default_rng(53).random((n, n, n)))).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, n * h), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5))
+    It = torch.from_numpy(I.ravel()).cuda()
+    a = K.eval(tree, ops, It, 1.0).double().cpu().numpy()
+    ops.p2p_fft(True)
+    b = K.eval(tree, ops, It, 1.0).double().cpu().numpy()
+    assert np.isfinite(a).all() and np.isfinite(b).all()
+    assert rel_l2(b, a) < 1e-6
+    ref = odirect.fft_full(I.astype(np.float64), (h,) * 3, p_o2).ravel()
+    assert rel_l2(b, ref) < 1e-4
