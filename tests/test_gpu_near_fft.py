@@ -100,3 +100,29 @@ def test_bright_sources_on_fine_cells_stay_finite(K):
     assert rel_l2(b, a) < 1e-6
     ref = odirect.fft_full(I.astype(np.float64), (h,) * 3, p_o2).ravel()
     assert rel_l2(b, ref) < 1e-4
+
+
+def test_benchmark_configuration_against_the_oracle(K, record_property):
+    # exactly what bench.py times: 256^3 channel at 760 Torr, lattice layout R = 1.0, M2L in
+    # its FFT form, near field in Fourier space, FP32; against the oracle's exact field (its
+    # FFT form, checked at sampled cells against its one-target-at-a-time direct sum), over
+    # the whole field and at bench.py's 4,096 cells (seed 1009).  A rel-L2 over few random
+    # cells weighs the dim background, where the method's relative error is largest.
+    w = workloads.streamer_channel(n=256, L=0.4, p=760.0)
+    I = np.ascontiguousarray(w.I.astype(np.float32).ravel())
+    tree = K.build_tree(K.Grid.cube(256, w.L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(w.p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    ops.m2l_fft(True)
+    ops.p2p_fft(True)
+    S = K.eval(tree, ops, torch.from_numpy(I).cuda(), w.prefactor).double().cpu().numpy()
+    I3 = I.reshape(256, 256, 256).astype(np.float64)
+    ref = odirect.fft_full(I3, (w.h,) * 3, w.p_o2, prefactor=w.prefactor, workers=16).ravel()
+    t64 = workloads.sample_targets(256 ** 3, 64, seed=1010)
+    d = odirect.direct_targets(I3, (w.h,) * 3, w.p_o2, t64, prefactor=w.prefactor)
+    assert np.max(np.abs(ref[t64] / d - 1)) < 1e-10
+    tg = workloads.sample_targets(256 ** 3, 4096, seed=1009)
+    full, samp = rel_l2(S, ref), rel_l2(S[tg], ref[tg])
+    record_property("rel_l2_full", full)
+    record_property("rel_l2_sampled", samp)
+    print("benchmark configuration: full field %.2e, 4,096 cells %.2e" % (full, samp))
+    assert full < 3e-5 and samp < 1e-4
