@@ -271,9 +271,11 @@ def main():
     peak = PEAK_FP32_MFMA if args.precision in ("fp32", "fp64") else PEAK_BF16_MFMA
     if args.p2p == "fft" and pass_ms.get("near_products", 0) > 0:
         # near field in Fourier space: the dominant kernel is the products kernel, one
-        # complex multiply-add (8 flops) per frequency (16 x 16 x 9) and existing leaf pair
+        # complex multiply-add (8 flops) per frequency of the half spectrum (15 x 15 x 8;
+        # the kernel's 16th slot per column, kept zero for alignment, is not counted) and
+        # existing leaf pair
         leaf_pairs = float(3 * nb - 2) ** 3
-        prod_flops = 8.0 * 2304 * leaf_pairs
+        prod_flops = 8.0 * 1800 * leaf_pairs
         t = pass_ms["near_products"]
         achieved = prod_flops / (t * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": "near_products (near field in Fourier space)",

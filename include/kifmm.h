@@ -204,11 +204,11 @@ int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 /* Near field in Fourier space (eq. (nearfar), direct part, with the self cell).  On the
  * uniform grid the matrix between a leaf of 8^3 cells and a neighbour leaf is a block of a
  * convolution, so with enable != 0 the near field of FP32 and KIFMM_BF16X3 evaluations
- * runs as: half spectra (16 x 16 x 9) of every leaf's sources zero-padded to 16^3,
+ * runs as: half spectra (15 x 15 x 8) of every leaf's sources zero-padded to 15^3,
  * 27 complex products per frequency against the kernel spectra of the 27 neighbour
  * offsets (built in FP64 with the operators), and the inverse transform at the 8^3 cells.
  * Same sum as the dense near field up to FP32 rounding (about 1e-7 of the result).  The
- * first enable allocates spectra buffers of 27 KiB per leaf (owned by ops).  Returns
+ * first enable allocates spectra buffers of 22.5 KiB per leaf (owned by ops).  Returns
  * 0, KIFMM_EINVAL (ops NULL), KIFMM_EUNSUPPORTED (leaves other than 8^3, or fewer than 4
  * per axis) or KIFMM_ENOMEM. */
 int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable);

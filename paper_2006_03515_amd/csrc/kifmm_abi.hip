@@ -190,8 +190,8 @@ struct kifmm_ops_s {
     std::vector<float *> fft_g, fft_f, fft_i;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
-    // kernel of the 27 neighbour offsets [27][2304] complex, per-leaf spectra of the sources
-    // [nleaf][2304] complex, and the sums after the first inverse stage [nleaf][144][8]
+    // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
+    // [nleaf][1920] complex, and the sums after the first inverse stage [nleaf][120][8]
     // complex (allocated when first enabled)
     bool p2p_fft = false;
     float *near_gh = nullptr, *near_q = nullptr, *near_p = nullptr;
@@ -596,8 +596,9 @@ int max_abs_host(const double *d, size_t count, double *out, hipStream_t st) {
 
 // Half spectra of the near-range kernel for leaves of 8^3 cells: for each neighbour offset o
 // (in leaves, o = 9 (ox+1) + 3 (oy+1) + oz+1), g_o(d) = G((d - 8 o) h) for cell differences
-// d in [-7, 7]^3 (the self value at d - 8 o = 0), placed at d mod 16, transformed over the
-// 16^3 cyclic grid in FP64 and stored at f = (ky * 9 + kz) * 16 + kx, kz <= 8.
+// d in [-7, 7]^3 (the self value at d - 8 o = 0), placed at d mod 15, transformed over the
+// 15^3 cyclic grid in FP64 and stored at f = (ky * 8 + kz) * 16 + kx, kz <= 7 (120 columns
+// (ky, kz) of 16 slots, the 16th zero).
 int build_near_spectra(DevBuf &db, kifmm_ops o, double h, hipStream_t st) {
     const int nd = 15 * 15 * 15;
     std::vector<double> dp(3 * nd), shifts(3 * 27);
@@ -620,58 +621,58 @@ int build_near_spectra(DevBuf &db, kifmm_ops o, double h, hipStream_t st) {
     std::vector<double> g((size_t)27 * nd);
     KIFMM_HIP(hipMemcpyAsync(g.data(), G, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     KIFMM_HIP(hipStreamSynchronize(st));
-    std::vector<double> cs(16), sn(16);
-    for (int m = 0; m < 16; ++m) {
-        cs[m] = std::cos(2.0 * M_PI * m / 16.0);
-        sn[m] = std::sin(2.0 * M_PI * m / 16.0);
+    // 15-point transforms: 15 values per axis hold the differences -7..7 without overlap
+    constexpr int N = 15, NZ = 8, NSLOT = 120 * 16;
+    std::vector<double> cs(N), sn(N);
+    for (int m = 0; m < N; ++m) {
+        cs[m] = std::cos(2.0 * M_PI * m / N);
+        sn[m] = std::sin(2.0 * M_PI * m / N);
     }
-    std::vector<float> out((size_t)27 * 2304 * 2);
-    std::vector<double> a((size_t)16 * 16 * 16), zr((size_t)16 * 16 * 9), zi(zr.size()), yr((size_t)16 * 16 * 9),
-        yi(yr.size());
+    std::vector<float> out((size_t)27 * NSLOT * 2, 0.0f);   // slot kx = 15 of every column stays 0
+    std::vector<double> a((size_t)N * N * N), zr((size_t)N * N * NZ), zi(zr.size()), yr(zr.size()), yi(zr.size());
     for (int t = 0; t < 27; ++t) {
-        std::fill(a.begin(), a.end(), 0.0);
-        for (int d = 0; d < nd; ++d) {
-            const int x = (d / 225 - 7) & 15, y = ((d / 15) % 15 - 7) & 15, z = (d % 15 - 7) & 15;
-            a[(x * 16 + y) * 16 + z] = g[(size_t)t * nd + d];
+        for (int d = 0; d < nd; ++d) {   // every point of the cyclic grid is one difference
+            const int x = (d / 225 - 7 + N) % N, y = ((d / 15) % 15 - 7 + N) % N, z = (d % 15 - 7 + N) % N;
+            a[(x * N + y) * N + z] = g[(size_t)t * nd + d];
         }
-        for (int x = 0; x < 16; ++x)   // z
-            for (int y = 0; y < 16; ++y)
-                for (int kz = 0; kz < 9; ++kz) {
+        for (int x = 0; x < N; ++x)   // z
+            for (int y = 0; y < N; ++y)
+                for (int kz = 0; kz < NZ; ++kz) {
                     double re = 0, im = 0;
-                    for (int z = 0; z < 16; ++z) {
-                        const double v = a[(x * 16 + y) * 16 + z];
-                        re += v * cs[(kz * z) & 15];
-                        im -= v * sn[(kz * z) & 15];
+                    for (int z = 0; z < N; ++z) {
+                        const double v = a[(x * N + y) * N + z];
+                        re += v * cs[(kz * z) % N];
+                        im -= v * sn[(kz * z) % N];
                     }
-                    zr[(x * 16 + y) * 9 + kz] = re;
-                    zi[(x * 16 + y) * 9 + kz] = im;
+                    zr[(x * N + y) * NZ + kz] = re;
+                    zi[(x * N + y) * NZ + kz] = im;
                 }
-        for (int x = 0; x < 16; ++x)   // y
-            for (int ky = 0; ky < 16; ++ky)
-                for (int kz = 0; kz < 9; ++kz) {
+        for (int x = 0; x < N; ++x)   // y
+            for (int ky = 0; ky < N; ++ky)
+                for (int kz = 0; kz < NZ; ++kz) {
                     double re = 0, im = 0;
-                    for (int y = 0; y < 16; ++y) {
-                        const double vr = zr[(x * 16 + y) * 9 + kz], vi = zi[(x * 16 + y) * 9 + kz];
-                        const double c = cs[(ky * y) & 15], sv = sn[(ky * y) & 15];
+                    for (int y = 0; y < N; ++y) {
+                        const double vr = zr[(x * N + y) * NZ + kz], vi = zi[(x * N + y) * NZ + kz];
+                        const double c = cs[(ky * y) % N], sv = sn[(ky * y) % N];
                         re += vr * c + vi * sv;
                         im += vi * c - vr * sv;
                     }
-                    yr[(x * 16 + ky) * 9 + kz] = re;
-                    yi[(x * 16 + ky) * 9 + kz] = im;
+                    yr[(x * N + ky) * NZ + kz] = re;
+                    yi[(x * N + ky) * NZ + kz] = im;
                 }
-        for (int kx = 0; kx < 16; ++kx)   // x
-            for (int ky = 0; ky < 16; ++ky)
-                for (int kz = 0; kz < 9; ++kz) {
+        for (int kx = 0; kx < N; ++kx)   // x
+            for (int ky = 0; ky < N; ++ky)
+                for (int kz = 0; kz < NZ; ++kz) {
                     double re = 0, im = 0;
-                    for (int x = 0; x < 16; ++x) {
-                        const double vr = yr[(x * 16 + ky) * 9 + kz], vi = yi[(x * 16 + ky) * 9 + kz];
-                        const double c = cs[(kx * x) & 15], sv = sn[(kx * x) & 15];
+                    for (int x = 0; x < N; ++x) {
+                        const double vr = yr[(x * N + ky) * NZ + kz], vi = yi[(x * N + ky) * NZ + kz];
+                        const double c = cs[(kx * x) % N], sv = sn[(kx * x) % N];
                         re += vr * c + vi * sv;
                         im += vi * c - vr * sv;
                     }
-                    const size_t f = (size_t)(ky * 9 + kz) * 16 + kx;
-                    out[((size_t)t * 2304 + f) * 2] = (float)re;
-                    out[((size_t)t * 2304 + f) * 2 + 1] = (float)im;
+                    const size_t f = (size_t)(ky * NZ + kz) * 16 + kx;
+                    out[((size_t)t * NSLOT + f) * 2] = (float)re;
+                    out[((size_t)t * NSLOT + f) * 2 + 1] = (float)im;
                 }
     }
     KIFMM_TRY(dmalloc(&o->near_gh, out.size()));
@@ -1462,9 +1463,9 @@ int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable) {
     if (!ops->near_gh || ops->nb < 4)
         return fail(KIFMM_EUNSUPPORTED, "the Fourier-space near field needs leaves of 8^3 cells and at least 4 per axis");
     if (!ops->near_q) {
-        const size_t n = (size_t)ops->nb * ops->nb * ops->nb * 2304 * 2;
+        const size_t n = (size_t)ops->nb * ops->nb * ops->nb * 1920 * 2;
         KIFMM_TRY(dmalloc(&ops->near_q, n));
-        const int rc = dmalloc(&ops->near_p, n / 2);   // 8 of the 16 kx values: after the x stage
+        const int rc = dmalloc(&ops->near_p, n / 2);   // [nleaf][120][8]: after the x stage
         if (rc != KIFMM_OK) {
             (void)hipFree(ops->near_q);
             ops->near_q = nullptr;

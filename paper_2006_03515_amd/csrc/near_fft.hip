@@ -3,18 +3,20 @@
 // On a uniform grid the near-range matrix between a target leaf and the leaf at offset o
 // (in leaves) has entries G(cell_i - cell_j - 8 o) that depend on i - j only: it applies
 // the kernel restricted to the differences d in [-7, 7]^3 + 8 o, a convolution.  On the
-// cyclic grid of 16 points per axis those differences never wrap onto one another, so
+// cyclic grid of 15 points per axis (the fewest that keep the 15 differences per axis
+// apart) those differences never wrap onto one another, so
 //     S_t = inverse DFT( sum over the 27 neighbours o of Gh_o * DFT(q_{t+o}) )
-// restricted to the 8^3 cells of t, with Gh_o the half spectrum (16 x 16 x 9 complex
+// restricted to the 8^3 cells of t, with Gh_o the half spectrum (15 x 15 x 8 complex
 // values) of the kernel of offset o, the self value included.  It is the same sum as the
 // dense near field up to FP32 rounding, with about a fourteenth of its arithmetic per leaf
 // (separable transforms and 27 complex products per frequency, against 27 dense 512 x 512
 // products).
 //
-// Frequencies (kx, ky, kz), kz <= 8, are stored per leaf at f = (ky * 9 + kz) * 16 + kx.
+// Frequencies (kx, ky, kz), kz <= 7, are stored per leaf at f = (ky * 8 + kz) * 16 + kx:
+// 120 columns (ky, kz) of 16 slots, the last slot of each zero.
 //
 //   near_forward_kernel   one workgroup per source leaf: z, y and x transforms of the 8^3
-//                         values zero-padded to 16^3, through LDS; writes 2304 complex.
+//                         values zero-padded to 15^3, through LDS; writes 1920 slots.
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
@@ -33,70 +35,75 @@ namespace kifmm {
 
 namespace {
 
-// cos and sin of 2 pi m / 16, m = 0..15; each kernel copies them to LDS, since the index
+// cos and sin of 2 pi m / 15, m = 0..14; each kernel copies them to LDS, since the index
 // differs between lanes
-__constant__ float kCos16[16] = {1.0f,  0.92387953f,  0.70710678f,  0.38268343f,  0.0f, -0.38268343f, -0.70710678f, -0.92387953f,
-                                 -1.0f, -0.92387953f, -0.70710678f, -0.38268343f, -0.0f, 0.38268343f,  0.70710678f,  0.92387953f};
-__constant__ float kSin16[16] = {0.0f,  0.38268343f,  0.70710678f,  0.92387953f,  1.0f,  0.92387953f,  0.70710678f,  0.38268343f,
-                                 0.0f, -0.38268343f, -0.70710678f, -0.92387953f, -1.0f, -0.92387953f, -0.70710678f, -0.38268343f};
+__constant__ float kCos15[15] = {1.000000000f, 0.913545458f, 0.669130606f, 0.309016994f, -0.104528463f, -0.500000000f, -0.809016994f, -0.978147601f, -0.978147601f, -0.809016994f, -0.500000000f, -0.104528463f, 0.309016994f, 0.669130606f, 0.913545458f};
+__constant__ float kSin15[15] = {0.000000000f, 0.406736643f, 0.743144825f, 0.951056516f, 0.994521895f, 0.866025404f, 0.587785252f, 0.207911691f, -0.207911691f, -0.587785252f, -0.866025404f, -0.994521895f, -0.951056516f, -0.743144825f, -0.406736643f};
 
-constexpr int NF = 2304;   // 16 * 16 * 9 frequencies per leaf
+constexpr int NCOL = 120;       // columns (ky, kz): 15 x 8
+constexpr int NF = NCOL * 16;   // frequency slots per leaf
+
+// m + k mod 15 for m, k in [0, 15): the twiddle index of the next term of a sum
+__device__ __forceinline__ int next15(int m, int k) {
+    m += k;
+    return m >= 15 ? m - 15 : m;
+}
 
 __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restrict__ q, const uint8_t *__restrict__ in_nz,
                                                            float2 *__restrict__ Q) {
     __shared__ float qs[512];
-    __shared__ float2 Z[8 * 8 * 9];    // [x][y][kz]
-    __shared__ float2 Y[8 * 16 * 9];   // [x][ky][kz]
-    __shared__ float cs16[16], sn16[16];
+    __shared__ float2 Z[8 * 8 * 8];   // [x][y][kz]
+    __shared__ float2 Y[8 * NCOL];    // [x][ky][kz]
+    __shared__ float cs15[15], sn15[15];
     const int tid = threadIdx.x;
     const int64_t leaf = blockIdx.x;
     if (in_nz && !in_nz[leaf]) return;   // never read: the products skip zero leaves
-    if (tid < 16) {
-        cs16[tid] = kCos16[tid];
-        sn16[tid] = kSin16[tid];
+    if (tid < 15) {
+        cs15[tid] = kCos15[tid];
+        sn15[tid] = kSin15[tid];
     }
     qs[tid] = q[leaf * 512 + tid];
     qs[tid + 256] = q[leaf * 512 + 256 + tid];
     __syncthreads();
-    for (int e = tid; e < 576; e += 256) {   // z: real in, kz = 0..8
-        const int x = e / 72, y = (e / 9) % 8, kz = e % 9;
+    for (int e = tid; e < 512; e += 256) {   // z: real in, kz = 0..7
+        const int x = e >> 6, y = (e >> 3) & 7, kz = e & 7;
         float re = 0.f, im = 0.f;
+        int m = 0;   // kz z mod 15
 #pragma unroll
-        for (int z = 0; z < 8; ++z) {
+        for (int z = 0; z < 8; ++z, m = next15(m, kz)) {
             const float v = qs[(x * 8 + y) * 8 + z];
-            const int m = (kz * z) & 15;
-            re = fmaf(v, cs16[m], re);
-            im = fmaf(-v, sn16[m], im);
+            re = fmaf(v, cs15[m], re);
+            im = fmaf(-v, sn15[m], im);
         }
         Z[e] = make_float2(re, im);
     }
     __syncthreads();
-    for (int e = tid; e < 1152; e += 256) {   // y: ky = 0..15
-        const int x = e / 144, ky = (e / 9) % 16, kz = e % 9;
+    for (int e = tid; e < 8 * NCOL; e += 256) {   // y: ky = 0..14
+        const int x = e / NCOL, ky = (e >> 3) % 15, kz = e & 7;
         float re = 0.f, im = 0.f;
+        int m = 0;   // ky y mod 15
 #pragma unroll
-        for (int y = 0; y < 8; ++y) {
-            const float2 v = Z[(x * 8 + y) * 9 + kz];
-            const int m = (ky * y) & 15;
-            const float c = cs16[m], s = sn16[m];
+        for (int y = 0; y < 8; ++y, m = next15(m, ky)) {
+            const float2 v = Z[(x * 8 + y) * 8 + kz];
+            const float c = cs15[m], s = sn15[m];
             re = fmaf(v.x, c, fmaf(v.y, s, re));
             im = fmaf(v.y, c, fmaf(-v.x, s, im));
         }
         Y[e] = make_float2(re, im);
     }
     __syncthreads();
-    for (int f = tid; f < NF; f += 256) {   // x: kx = 0..15, written at f = (ky * 9 + kz) * 16 + kx
-        const int kx = f & 15, r = f >> 4;   // r = ky * 9 + kz
+    for (int f = tid; f < NF; f += 256) {   // x: kx = 0..14, written at f = (ky * 8 + kz) * 16 + kx
+        const int kx = f & 15, r = f >> 4;   // r = ky * 8 + kz; slot kx = 15 is written as zero
         float re = 0.f, im = 0.f;
+        int m = 0;   // kx x mod 15
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const float2 v = Y[x * 144 + r];
-            const int m = (kx * x) & 15;
-            const float c = cs16[m], s = sn16[m];
+        for (int x = 0; x < 8; ++x, m = next15(m, kx)) {
+            const float2 v = Y[x * NCOL + r];
+            const float c = cs15[m], s = sn15[m];
             re = fmaf(v.x, c, fmaf(v.y, s, re));
             im = fmaf(v.y, c, fmaf(-v.x, s, im));
         }
-        Q[leaf * NF + f] = make_float2(re, im);
+        Q[leaf * NF + f] = kx < 15 ? make_float2(re, im) : make_float2(0.f, 0.f);
     }
 }
 
@@ -108,11 +115,11 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
     __shared__ float2 Es[216 * 16];   // [region leaf][kx]
     __shared__ float2 Gs[27 * 16];    // [offset][kx]
     __shared__ float2 Ps[64 * 17];    // [target][kx] sums of one chunk (padded row)
-    __shared__ float cs16[16], sn16[16];
+    __shared__ float cs15[15], sn15[15];
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid < 16) {
-        cs16[tid] = kCos16[tid];
-        sn16[tid] = kSin16[tid];
+    if (tid < 15) {
+        cs15[tid] = kCos15[tid];
+        sn15[tid] = kSin15[tid];
     }
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
@@ -188,16 +195,16 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         for (int s = 0; s < 4; ++s) Ps[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
         __syncthreads();
         // first inverse stage, over kx, at the 8 cells x of each target: this chunk holds all
-        // 16 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 16}
+        // 15 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 15}
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = tid >> 2, x = 2 * (tid & 3) + h;
             float re = 0.f, im = 0.f;
+            int m = 0;   // kx x mod 15
 #pragma unroll
-            for (int kx = 0; kx < 16; ++kx) {
+            for (int kx = 0; kx < 15; ++kx, m = next15(m, x)) {
                 const float2 v = Ps[t * 17 + kx];
-                const int m = (kx * x) & 15;
-                const float cc = cs16[m], ss = sn16[m];
+                const float cc = cs15[m], ss = sn15[m];
                 re = fmaf(v.x, cc, fmaf(-v.y, ss, re));
                 im = fmaf(v.y, cc, fmaf(v.x, ss, im));
             }
@@ -209,26 +216,26 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
 
 __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ U,
                                                            const uint8_t *__restrict__ out_need, float *__restrict__ S) {
-    __shared__ float2 Us[144 * 8];   // [ky * 9 + kz][x], after the x stage (products kernel)
-    __shared__ float2 V[8 * 8 * 9];  // [x][y][kz]
-    __shared__ float cs16[16], sn16[16];
+    __shared__ float2 Us[NCOL * 8];   // [ky * 8 + kz][x], after the x stage (products kernel)
+    __shared__ float2 V[8 * 8 * 8];   // [x][y][kz]
+    __shared__ float cs15[15], sn15[15];
     const int tid = threadIdx.x;
     const int64_t leaf = blockIdx.x;
     if (out_need && !out_need[leaf]) return;   // never read: the final sum writes 0 there
-    if (tid < 16) {
-        cs16[tid] = kCos16[tid];
-        sn16[tid] = kSin16[tid];
+    if (tid < 15) {
+        cs15[tid] = kCos15[tid];
+        sn15[tid] = kSin15[tid];
     }
-    for (int e = tid; e < 144 * 4; e += 256) ((float4 *)Us)[e] = ((const float4 *)(U + leaf * 1152))[e];
+    for (int e = tid; e < NCOL * 4; e += 256) ((float4 *)Us)[e] = ((const float4 *)(U + leaf * NCOL * 8))[e];
     __syncthreads();
-    for (int e = tid; e < 576; e += 256) {   // y: e^{+i theta}
-        const int x = e / 72, y = (e / 9) % 8, kz = e % 9;
+    for (int e = tid; e < 512; e += 256) {   // y: e^{+i theta}
+        const int x = e >> 6, y = (e >> 3) & 7, kz = e & 7;
         float re = 0.f, im = 0.f;
+        int m = 0;   // ky y mod 15
 #pragma unroll
-        for (int ky = 0; ky < 16; ++ky) {
-            const float2 v = Us[(ky * 9 + kz) * 8 + x];
-            const int m = (ky * y) & 15;
-            const float c = cs16[m], s = sn16[m];
+        for (int ky = 0; ky < 15; ++ky, m = next15(m, y)) {
+            const float2 v = Us[(ky * 8 + kz) * 8 + x];
+            const float c = cs15[m], s = sn15[m];
             re = fmaf(v.x, c, fmaf(-v.y, s, re));
             im = fmaf(v.y, c, fmaf(v.x, s, im));
         }
@@ -238,14 +245,14 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
     for (int e = tid; e < 512; e += 256) {   // z: real part, the conjugate half counted twice
         const int x = e >> 6, y = (e >> 3) & 7, z = e & 7;
         float acc = 0.f;
+        int m = 0;   // kz z mod 15
 #pragma unroll
-        for (int kz = 0; kz < 9; ++kz) {
-            const float2 v = V[(x * 8 + y) * 9 + kz];
-            const int m = (kz * z) & 15;
-            const float w = (kz == 0 || kz == 8) ? 1.f : 2.f;
-            acc = fmaf(w * v.x, cs16[m], fmaf(-w * v.y, sn16[m], acc));
+        for (int kz = 0; kz < 8; ++kz, m = next15(m, z)) {
+            const float2 v = V[(x * 8 + y) * 8 + kz];
+            const float w = kz == 0 ? 1.f : 2.f;
+            acc = fmaf(w * v.x, cs15[m], fmaf(-w * v.y, sn15[m], acc));
         }
-        S[leaf * 512 + e] = acc * (1.0f / 4096.0f);
+        S[leaf * 512 + e] = acc * (1.0f / 3375.0f);
     }
 }
 
