@@ -50,6 +50,7 @@ int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, in
 int run_m2l_hadamard(const float *, const float *, const int *, const int *, int, int, int, const uint8_t *,
                      const uint8_t *, float *, hipStream_t);
 int run_m2l_pair_mfma(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
+int run_m2l_lattice(int, int, const float *, int64_t, int, int, const uint8_t *, float *, hipStream_t);
 int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, const uint8_t *, float *, float *,
                        float *, hipStream_t);
 template <typename T>
@@ -182,12 +183,16 @@ struct kifmm_ops_s {
     std::vector<uint8_t *> want;
     _Float16 *m2lh = nullptr;
     // FFT form of M2L (layout LATTICE): per level l, the kernel spectra of the 316 offsets
-    // (fft_g[l], 316 x nfp complex), coefficients -> half spectra (fft_f[l], mf x KU) and
-    // spectra -> coefficients (fft_i[l], KD x mf), mf = 2 nfp; spectra of one level's
-    // densities and sums (spec_e, spec_p: boxes of level D x mf)
+    // (fft_g[l], 316 x nfp complex), upward coefficients -> equivalent densities on the
+    // lattice (lat_w[l] = W_u, lrow x KU, rows past m0^3 zero) and lattice check potentials
+    // -> downward coefficients (lat_u[l] = U_d^T, KD x lrow), lrow = m0^3 padded to 32,
+    // mf = 2 nfp; lattice values of the finest level (lat_buf: boxes of level D x lrow) and
+    // its spectra (spec_e, spec_p: boxes of level D x mf), and the same for the coarser
+    // levels (the _c buffers, boxes of level D - 1), which run at the same time
     bool m2l_fft = false;
-    int nfp = 0, mf = 0;
-    std::vector<float *> fft_g, fft_f, fft_i;
+    int nfp = 0, mf = 0, lrow = 0;
+    std::vector<float *> fft_g, lat_w, lat_u;
+    float *lat_buf = nullptr, *lat_buf_c = nullptr, *spec_e_c = nullptr, *spec_p_c = nullptr;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
     // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
@@ -206,9 +211,10 @@ struct kifmm_ops_s {
     int n_amax = 256;
     float *part = nullptr;             // tap-group partial sums of the M2L launches
     int64_t part_capacity = 0;         // floats
-    // the near field runs on a second stream, joined by events
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    // the near field runs on a second stream, joined by events; with the FFT form of M2L
+    // the finest level's M2L runs on a third, beside the upward pass and the coarse levels
+    hipStream_t side = nullptr, fine = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
     // per-pass timing (kifmm_profile_enable)
     bool prof = false;
     std::vector<hipEvent_t> ev;        // pool of events, recorded in pairs
@@ -270,11 +276,12 @@ static void free_ops(kifmm_ops o) {
     if (!o) return;
     clear_profile(o);
     if (o->side) (void)hipStreamSynchronize(o->side);
+    if (o->fine) (void)hipStreamSynchronize(o->fine);
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
-                    o->near_gh, o->near_q, o->near_p};
+                    o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -283,7 +290,7 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
-    for (auto *v : {&o->fft_g, &o->fft_f, &o->fft_i, &o->fft_pair})
+    for (auto *v : {&o->fft_g, &o->lat_w, &o->lat_u, &o->fft_pair})
         for (float *p : *v)
             if (p) (void)hipFree(p);
     for (double *p : o->cd)
@@ -291,6 +298,9 @@ static void free_ops(kifmm_ops o) {
     if (o->fork) (void)hipEventDestroy(o->fork);
     if (o->join) (void)hipEventDestroy(o->join);
     if (o->side) (void)hipStreamDestroy(o->side);
+    if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
+    if (o->join_fine) (void)hipEventDestroy(o->join_fine);
+    if (o->fine) (void)hipStreamDestroy(o->fine);
     delete o;
 }
 
@@ -686,10 +696,11 @@ int build_near_spectra(DevBuf &db, kifmm_ops o, double h, hipStream_t st) {
 // On the cyclic grid of N = 2 m0 - 1 points per axis the differences i - j never wrap onto
 // one another, so the M2L product is the inverse DFT of DFT(g_o) times DFT(density).  Per
 // level: the half spectra (frequencies (kx, ky, kz), kz < m0, index (kx N + ky) m0 + kz,
-// real and imaginary parts interleaved) of g_o for the 316 offsets; the map from upward
-// coefficients to the half spectrum of the equivalent density, DFT . W_u; and the map from
-// a check-potential half spectrum to downward coefficients, U_d^T . inverse DFT (the
-// conjugate-symmetric half counted twice where kz > 0).
+// real and imaginary parts interleaved) of g_o for the 316 offsets, with the MFMA operator
+// fragments of the parent-pair form; the map from upward coefficients to the equivalent
+// density on the lattice, W_u; and the map from check potentials on the lattice to
+// downward coefficients, U_d^T.  The transforms between lattice values and spectra run
+// separably on the device (the conjugate-symmetric half counted twice where kz > 0).
 int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::vector<int> &m2lo,
                   const std::vector<Factor> &fu, const std::vector<Factor> &fd, hipStream_t st) {
     const int m = o->opts.m0, N = 2 * m - 1, D = o->D, KU = o->KU, KD = o->KD;
@@ -698,13 +709,14 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
     const int nd = N * N * N, nlat = m * m * m;
     o->nfp = nfp;
     o->mf = mf;
+    o->lrow = pad_to(nlat, 32);
     const double twopi_n = 2.0 * M_PI / N;
     auto phase = [&](int f, int x, int y, int z) {   // exact integer phase, reduced mod N
         const int kx = f / (N * m), ky = (f / m) % N, kz = f % m;
         const int64_t ph = (int64_t)kx * x + (int64_t)ky * y + (int64_t)kz * z;
         return twopi_n * (double)(((ph % N) + N) % N);
     };
-    std::vector<double> FD((size_t)nd * 2 * nf), FY((size_t)2 * nf * nlat), BI((size_t)nlat * 2 * nf);
+    std::vector<double> FD((size_t)nd * 2 * nf);
     for (int d = 0; d < nd; ++d) {   // difference d = (dx, dy, dz) in [-(m-1), m-1]^3, C order
         const int dx = d / (N * N) - (m - 1), dy = (d / N) % N - (m - 1), dz = d % N - (m - 1);
         for (int f = 0; f < nf; ++f) {
@@ -713,29 +725,16 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             FD[(size_t)d * 2 * nf + 2 * f + 1] = -std::sin(a);
         }
     }
-    const double inv = 1.0 / ((double)N * N * N);
-    for (int j = 0; j < nlat; ++j) {   // lattice point (jx, jy, jz), C order
-        const int jx = j / (m * m), jy = (j / m) % m, jz = j % m;
-        for (int f = 0; f < nf; ++f) {
-            const double a = phase(f, jx, jy, jz), w = (f % m == 0 ? 1.0 : 2.0) * inv;
-            FY[(size_t)(2 * f) * nlat + j] = std::cos(a);
-            FY[(size_t)(2 * f + 1) * nlat + j] = -std::sin(a);
-            BI[(size_t)j * 2 * nf + 2 * f] = w * std::cos(a);
-            BI[(size_t)j * 2 * nf + 2 * f + 1] = -w * std::sin(a);
-        }
-    }
-    double *FDd, *FYd, *BId, *org, *Dp, *sh, *G, *tmp;
+    double *FDd, *org, *Dp, *sh, *G, *tmp;
     KIFMM_TRY(upload(db, FD, &FDd, st));
-    KIFMM_TRY(upload(db, FY, &FYd, st));
-    KIFMM_TRY(upload(db, BI, &BId, st));
     KIFMM_TRY(upload(db, std::vector<double>(3, 0.0), &org, st));
     KIFMM_TRY(db.get(&Dp, (size_t)3 * nd));
     KIFMM_TRY(db.get(&sh, (size_t)3 * n316));
     KIFMM_TRY(db.get(&G, (size_t)n316 * nd));
     KIFMM_TRY(db.get(&tmp, (size_t)std::max(n316, std::max(KU, KD)) * 2 * nf));
     o->fft_g.assign(D + 1, nullptr);
-    o->fft_f.assign(D + 1, nullptr);
-    o->fft_i.assign(D + 1, nullptr);
+    o->lat_w.assign(D + 1, nullptr);
+    o->lat_u.assign(D + 1, nullptr);
     o->fft_pair.assign(D + 1, nullptr);
     // offset -> index into the 316 offsets, for the parent-pair matrices
     std::vector<int> oidx(343, -1);
@@ -784,17 +783,21 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             KIFMM_HIP(hipStreamSynchronize(st));   // am is a host vector of this iteration
         }
         const Factor &u = fu[l - 2], &dn = fd[l - 2];
-        KIFMM_TRY(launch_gemm_f64(2 * nf, u.k, nlat, FYd, nlat, 0, u.W, u.k, 0, tmp, u.k, 0, 1, st));
-        KIFMM_TRY(dmalloc(&o->fft_f[l], (size_t)mf * KU));
-        KIFMM_TRY(store<float>(tmp, 2 * nf, u.k, 1, o->fft_f[l], mf, KU, 1.0, st));
-        KIFMM_TRY(launch_gemm_f64(dn.k, 2 * nf, nlat, dn.UT, nlat, 0, BId, 2 * nf, 0, tmp, 2 * nf, 0, 1, st));
-        KIFMM_TRY(dmalloc(&o->fft_i[l], (size_t)KD * mf));
-        KIFMM_TRY(store<float>(tmp, dn.k, 2 * nf, 1, o->fft_i[l], KD, mf, 1.0, st));
+        KIFMM_TRY(dmalloc(&o->lat_w[l], (size_t)o->lrow * KU));
+        KIFMM_TRY(store<float>(u.W, nlat, u.k, 1, o->lat_w[l], o->lrow, KU, 1.0, st));
+        KIFMM_TRY(dmalloc(&o->lat_u[l], (size_t)KD * o->lrow));
+        KIFMM_TRY(store<float>(dn.UT, dn.k, nlat, 1, o->lat_u[l], KD, o->lrow, 1.0, st));
         KIFMM_HIP(hipStreamSynchronize(st));   // dp and shifts are reused by the next level
     }
     const size_t nbx = (size_t)1 << (3 * D);
     KIFMM_TRY(dmalloc(&o->spec_e, nbx * mf));
     KIFMM_TRY(dmalloc(&o->spec_p, nbx * mf));
+    KIFMM_TRY(dmalloc(&o->lat_buf, nbx * o->lrow));
+    if (D >= 3) {
+        KIFMM_TRY(dmalloc(&o->spec_e_c, nbx / 8 * mf));
+        KIFMM_TRY(dmalloc(&o->spec_p_c, nbx / 8 * mf));
+        KIFMM_TRY(dmalloc(&o->lat_buf_c, nbx / 8 * o->lrow));
+    }
     o->m2l_fft = true;
     return KIFMM_OK;
 }
@@ -899,6 +902,9 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_HIP(hipStreamCreateWithFlags(&o->side, hipStreamNonBlocking));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
+    KIFMM_HIP(hipStreamCreateWithFlags(&o->fine, hipStreamNonBlocking));
+    KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
+    KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
     KIFMM_TRY(dmalloc(&o->amax_q, (size_t)o->n_amax));
     o->cu.assign(D + 1, nullptr);
@@ -1114,19 +1120,25 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
     const size_t so = (size_t)(l - 2) * per;
     if constexpr (sizeof(T) == 4) {
         if (o->m2l_fft && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
-            // FFT form: spectra of the densities, pointwise products, coefficients
+            // FFT form: equivalent densities on the lattice, their spectra, pointwise
+            // products, check potentials on the lattice, coefficients
             const int64_t nbx = (int64_t)1 << (3 * l);
-            auto pf = tap<float, float>(o->fft_f[l], 0, o->mf, KU, (const float *)o->cu[l], KU, o->spec_e, o->mf,
-                                        SRC_SAME, 0, o->t_single, 1, nbx, 0);
+            const int lr = o->lrow;
+            const bool fine = l == o->D;   // the coarser levels have buffers of their own
+            float *lat = fine ? o->lat_buf : o->lat_buf_c, *se = fine ? o->spec_e : o->spec_e_c,
+                  *sp = fine ? o->spec_p : o->spec_p_c;
+            auto pf = tap<float, float>(o->lat_w[l], 0, lr, KU, (const float *)o->cu[l], KU, lat, lr, SRC_SAME, 0,
+                                        o->t_single, 1, nbx, 0);
             pf.in_nz = nz_of(o, l);
             KIFMM_TRY(run(pf, st));
+            KIFMM_TRY(run_m2l_lattice(0, o->opts.m0, lat, nbx, o->nfp, lr, nz_of(o, l), se, st));
             if (o->fft_pair[l])
-                KIFMM_TRY(run_m2l_pair_mfma(o->spec_e, o->fft_pair[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l),
-                                            o->spec_p, st));
+                KIFMM_TRY(run_m2l_pair_mfma(se, o->fft_pair[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
             else
-                KIFMM_TRY(run_m2l_hadamard(o->spec_e, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev,
-                                           o->t_m2l.ntaps, 1 << l, o->nfp, want_of(o, l), nz_of(o, l), o->spec_p, st));
-            auto pi = tap<float, float>(o->fft_i[l], 0, KD, o->mf, (const float *)o->spec_p, o->mf, (float *)o->cd[l],
+                KIFMM_TRY(run_m2l_hadamard(se, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev, o->t_m2l.ntaps, 1 << l,
+                                           o->nfp, want_of(o, l), nz_of(o, l), sp, st));
+            KIFMM_TRY(run_m2l_lattice(1, o->opts.m0, sp, nbx, o->nfp, lr, want_of(o, l), lat, st));
+            auto pi = tap<float, float>(o->lat_u[l], 0, KD, lr, (const float *)lat, lr, (float *)o->cd[l],
                                         KD, SRC_SAME, 0, o->t_single, 1, nbx, acc);
             pi.out_need = want_of(o, l);
             pi.pass = PASS_M2L;
@@ -1327,6 +1339,21 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         p.in_nz = nz_of(o, D);
         KIFMM_TRY(run(p, st));
     }
+    // FFT form of M2L: the finest level's M2L needs only the leaves' coefficients, so it runs
+    // on its own stream beside the upward pass and the coarse levels (their latency-bound
+    // small launches leave most of the chip to it), into cd[D]; the L2L into level D then
+    // adds to it.  The coarse levels use spectra buffers of their own.
+    const bool fine_apart = sizeof(T) == 4 && D >= 3 && o->m2l_fft &&
+                            (precision == KIFMM_FP32 || precision == KIFMM_BF16X3);
+    if (fine_apart) {
+        KIFMM_HIP(hipEventRecord(o->fork_fine, st));
+        KIFMM_HIP(hipStreamWaitEvent(o->fine, o->fork_fine, 0));
+        {
+            PassTimer pt(o, KIFMM_PASS_M2L, o->fine);
+            KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 0, o->fine));
+        }
+        KIFMM_HIP(hipEventRecord(o->join_fine, o->fine));
+    }
     for (int l = D - 1; l >= 2; --l) {
         const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
         PassTimer pt(o, KIFMM_PASS_M2M, st);
@@ -1340,14 +1367,17 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         KIFMM_TRY(run(p, st));
     }
     for (int l = 2; l <= D; ++l) {
+        const bool m2l_done = fine_apart && l == D;   // cd[D] holds the M2L sum already
         if (l > 2) {
+            if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
             const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
-                               0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), 0);
+                               0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), m2l_done ? 1 : 0);
             p.out_need = want_of(o, l);
             KIFMM_TRY(run(p, st));
         }
+        if (m2l_done) continue;
         PassTimer pt(o, KIFMM_PASS_M2L, st);
         KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > 2 ? 1 : 0, st));
     }

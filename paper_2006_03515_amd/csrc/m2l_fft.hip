@@ -6,9 +6,9 @@
 // of N = 2 m0 - 1 points per axis the product becomes a pointwise product of spectra:
 //     P_t(f) = sum over the interaction list of t:  Gh_o(f) * E_s(f)
 // with E_s the half spectrum (N x N x (N+1)/2 complex values) of source box s's
-// equivalent density and Gh_o the spectrum of g_o.  The transforms to and from the
-// spectra are dense per-box matrices folded into the coefficient bases and run as tap
-// GEMMs; this file holds the sums of pointwise products.
+// equivalent density and Gh_o the spectrum of g_o.  Coefficients become lattice values
+// through the bases (tap GEMMs, W_u and U_d^T); this file holds the separable transforms
+// between lattice values and half spectra, and the sums of pointwise products.
 //
 // For one frequency the sum is a 189-tap stencil over the boxes, with no contraction of its
 // own.  Grouped by parents it becomes one: the 8 children c_t of a target parent p take
@@ -17,6 +17,9 @@
 // reals (re, im interleaved), that is a 16 x 432 matrix per frequency applied to 432 gathered
 // values per parent: a GEMM with 16 rows, K = 432 and one column per parent.
 //
+//   m2l_lattice_forward_kernel / m2l_lattice_inverse_kernel  a few boxes per workgroup:
+//                        the separable transforms between the m0^3 lattice values and the
+//                        half spectrum (z, y, x stages through LDS; inverse x, y, z).
 //   m2l_pair_mfma_kernel one workgroup per aligned 4^3 block of parents (512 target boxes) and
 //                        4 frequencies; the spectra of the block's source region (6^3
 //                        parents x 8 children) are staged in LDS, [frequency][child][re/im]
@@ -34,6 +37,8 @@
 //                        8 targets of class w (the child position, which fixes the tap
 //                        list); lane = 16 frequencies x 4 pairs of targets, so every
 //                        tap's operator entry is read once per two targets.
+#include <cmath>
+
 #include "common.h"
 #include "tapgemm.h"
 
@@ -42,6 +47,10 @@ namespace kifmm {
 namespace {
 
 constexpr int HFC = 16;   // frequencies per workgroup
+
+struct LatticeTwiddles {   // cos and sin of 2 pi k / N, k < N <= 15
+    float c[16], s[16];
+};
 
 __global__ __launch_bounds__(512) void m2l_hadamard_kernel(const float2 *__restrict__ E, const float2 *__restrict__ Gh,
                                                            const int *__restrict__ tap_op,
@@ -197,7 +206,200 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     }
 }
 
+// Transforms between the lattice values of a box (m0^3 equivalent densities or check
+// potentials, C order (x, y, z), rows of m0^3 padded to 32 floats) and its half spectrum on the cyclic
+// N^3 grid, N = 2 m0 - 1: frequency (kx, ky, kz), kz < m0, at f = (kx N + ky) m0 + kz.
+// Separable: three one-dimensional DFTs through LDS, NB boxes per workgroup.  The
+// spectra rows hold nfp = f padded to 16 complex values, the padding written as zeros.
+template <int M>
+struct LatticeDims {
+    static constexpr int N = 2 * M - 1, NF = N * N * M, NFP = (NF + 15) / 16 * 16, M3 = M * M * M;
+    static constexpr int ROW = (M3 + 31) / 32 * 32;   // lattice row length
+    static constexpr int NB = M >= 7 ? 2 : 4;   // boxes per workgroup (LDS: at most 52 KB)
+};
+
+// i + k mod n for i, k in [0, n): the twiddle index of the next term of a sum
+template <int N>
+__device__ __forceinline__ int next_mod(int i, int k) {
+    i += k;
+    return i >= N ? i - N : i;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void m2l_lattice_forward_kernel(const float *__restrict__ dens, int64_t nbx,
+                                                                  const uint8_t *__restrict__ in_nz, LatticeTwiddles tw,
+                                                                  float2 *__restrict__ E) {
+    using L = LatticeDims<M>;
+    constexpr int N = L::N, NB = L::NB, M3 = L::M3;
+    __shared__ float ds[NB * M3];
+    __shared__ float2 Z[NB * M3];       // [b][x][y][kz]
+    __shared__ float2 Y[NB * M * N * M];  // [b][x][ky][kz]
+    __shared__ float cs[N], sn[N];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * NB;
+    if (tid < N) {
+        cs[tid] = tw.c[tid];
+        sn[tid] = tw.s[tid];
+    }
+    for (int e = tid; e < NB * M3; e += 256) {
+        const int64_t box = b0 + e / M3;
+        ds[e] = box < nbx ? dens[box * L::ROW + e % M3] : 0.f;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * M3; e += 256) {   // z: real in, kz = 0..M-1
+        const int b = e / M3, r = e % M3, xy = r / M, kz = r % M;
+        float re = 0.f, im = 0.f;
+        int i = 0;   // kz z mod N
+#pragma unroll
+        for (int z = 0; z < M; ++z, i = next_mod<N>(i, kz)) {
+            const float v = ds[b * M3 + xy * M + z];
+            re = fmaf(v, cs[i], re);
+            im = fmaf(-v, sn[i], im);
+        }
+        Z[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * M * N * M; e += 256) {   // y: ky = 0..N-1
+        const int b = e / (M * N * M), r = e % (M * N * M), x = r / (N * M), ky = (r / M) % N, kz = r % M;
+        float re = 0.f, im = 0.f;
+        int i = 0;   // ky y mod N
+#pragma unroll
+        for (int y = 0; y < M; ++y, i = next_mod<N>(i, ky)) {
+            const float2 v = Z[b * M3 + (x * M + y) * M + kz];
+            re = fmaf(v.x, cs[i], fmaf(v.y, sn[i], re));
+            im = fmaf(v.y, cs[i], fmaf(-v.x, sn[i], im));
+        }
+        Y[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * L::NFP; e += 256) {   // x: kx = 0..N-1, written in frequency order
+        const int b = e / L::NFP, f = e % L::NFP;
+        const int64_t box = b0 + b;
+        if (box >= nbx || (in_nz && !in_nz[box])) continue;   // never read: zero boxes are skipped
+        float re = 0.f, im = 0.f;
+        if (f < L::NF) {
+            const int kx = f / (N * M), c = f % (N * M);
+            int i = 0;   // kx x mod N
+#pragma unroll
+            for (int x = 0; x < M; ++x, i = next_mod<N>(i, kx)) {
+                const float2 v = Y[b * M * N * M + x * N * M + c];
+                re = fmaf(v.x, cs[i], fmaf(v.y, sn[i], re));
+                im = fmaf(v.y, cs[i], fmaf(-v.x, sn[i], im));
+            }
+        }
+        E[box * L::NFP + f] = make_float2(re, im);
+    }
+}
+
+// Inverse: the real lattice values (1 / N^3) sum_f w_kz Re(P(f) e^{+i theta}), w_kz = 1 at
+// kz = 0 and 2 above (the conjugate half); the padding values of a row are zeros,
+// and so is the whole row of a box that is not wanted.
+template <int M>
+__global__ __launch_bounds__(256) void m2l_lattice_inverse_kernel(const float2 *__restrict__ P, int64_t nbx,
+                                                                  const uint8_t *__restrict__ out_need, LatticeTwiddles tw,
+                                                                  float *__restrict__ dens) {
+    using L = LatticeDims<M>;
+    constexpr int N = L::N, NB = L::NB, M3 = L::M3, NF = L::NF;
+    __shared__ float2 Ps[NB * NF];        // [b][kx][ky][kz]
+    __shared__ float2 A[NB * M * N * M];  // [b][x][ky][kz]
+    __shared__ float2 B[NB * M3];         // [b][x][y][kz]
+    __shared__ float cs[N], sn[N];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * NB;
+    if (tid < N) {
+        cs[tid] = tw.c[tid];
+        sn[tid] = tw.s[tid];
+    }
+    for (int e = tid; e < NB * NF; e += 256) {
+        const int64_t box = b0 + e / NF;
+        Ps[e] = box < nbx ? P[box * L::NFP + e % NF] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * M * N * M; e += 256) {   // x: e^{+i theta}
+        const int b = e / (M * N * M), r = e % (M * N * M), x = r / (N * M), c = r % (N * M);
+        float re = 0.f, im = 0.f;
+        int i = 0;   // kx x mod N
+#pragma unroll
+        for (int kx = 0; kx < N; ++kx, i = next_mod<N>(i, x)) {
+            const float2 v = Ps[b * NF + kx * N * M + c];
+            re = fmaf(v.x, cs[i], fmaf(-v.y, sn[i], re));
+            im = fmaf(v.y, cs[i], fmaf(v.x, sn[i], im));
+        }
+        A[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * M3; e += 256) {   // y
+        const int b = e / M3, r = e % M3, x = r / (M * M), y = (r / M) % M, kz = r % M;
+        float re = 0.f, im = 0.f;
+        int i = 0;   // ky y mod N
+#pragma unroll
+        for (int ky = 0; ky < N; ++ky, i = next_mod<N>(i, y)) {
+            const float2 v = A[b * M * N * M + (x * N + ky) * M + kz];
+            re = fmaf(v.x, cs[i], fmaf(-v.y, sn[i], re));
+            im = fmaf(v.y, cs[i], fmaf(v.x, sn[i], im));
+        }
+        B[e] = make_float2(re, im);
+    }
+    __syncthreads();
+    constexpr float inv = 1.0f / (float)(N * N * N);
+    for (int e = tid; e < NB * L::ROW; e += 256) {   // z: real part, written with the row padding
+        const int b = e / L::ROW, j = e % L::ROW;
+        const int64_t box = b0 + b;
+        if (box >= nbx) continue;
+        float acc = 0.f;
+        if (j < M3 && (!out_need || out_need[box])) {
+            const int xy = j / M, z = j % M;
+            int i = 0;   // kz z mod N
+#pragma unroll
+            for (int kz = 0; kz < M; ++kz, i = next_mod<N>(i, z)) {
+                const float2 v = B[b * M3 + xy * M + kz];
+                const float w = kz == 0 ? inv : 2.f * inv;
+                acc = fmaf(w * v.x, cs[i], fmaf(-w * v.y, sn[i], acc));
+            }
+        }
+        dens[box * L::ROW + j] = acc;
+    }
+}
+
+template <int M>
+int launch_lattice(int dir, const float *in, int64_t nbx, int nfp, int row, const uint8_t *flags, float *out,
+                   hipStream_t st) {
+    using L = LatticeDims<M>;
+    if (nfp != L::NFP || row != L::ROW)
+        return fail(KIFMM_EINVAL, "lattice transform: spectrum or lattice row length does not match m0");
+    LatticeTwiddles tw{};
+    for (int k = 0; k < L::N; ++k) {
+        tw.c[k] = (float)std::cos(2.0 * M_PI * k / L::N);
+        tw.s[k] = (float)std::sin(2.0 * M_PI * k / L::N);
+    }
+    const unsigned grid = (unsigned)((nbx + L::NB - 1) / L::NB);
+    if (dir == 0)
+        hipLaunchKernelGGL(m2l_lattice_forward_kernel<M>, dim3(grid), dim3(256), 0, st, in, nbx, flags, tw, (float2 *)out);
+    else
+        hipLaunchKernelGGL(m2l_lattice_inverse_kernel<M>, dim3(grid), dim3(256), 0, st, (const float2 *)in, nbx, flags, tw,
+                           out);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
 }  // namespace
+
+// dir 0: lattice values [nbx][row] -> half spectra [nbx][nfp] complex (boxes with
+// in_nz = 0 skipped); dir 1: half spectra -> lattice values (boxes with out_need = 0
+// written as zeros).  m0 in [3, 8], row = m0^3 padded to 32.
+int run_m2l_lattice(int dir, int m0, const float *in, int64_t nbx, int nfp, int row, const uint8_t *flags,
+                    float *out, hipStream_t st) {
+    if (nbx <= 0) return KIFMM_OK;
+    switch (m0) {
+    case 3: return launch_lattice<3>(dir, in, nbx, nfp, row, flags, out, st);
+    case 4: return launch_lattice<4>(dir, in, nbx, nfp, row, flags, out, st);
+    case 5: return launch_lattice<5>(dir, in, nbx, nfp, row, flags, out, st);
+    case 6: return launch_lattice<6>(dir, in, nbx, nfp, row, flags, out, st);
+    case 7: return launch_lattice<7>(dir, in, nbx, nfp, row, flags, out, st);
+    case 8: return launch_lattice<8>(dir, in, nbx, nfp, row, flags, out, st);
+    default: return fail(KIFMM_EINVAL, "lattice transform: m0 must lie in [3, 8]");
+    }
+}
 
 int run_m2l_pair_mfma(const float *E, const float *Am, int nl, int nfp, const uint8_t *out_need,
                       const uint8_t *in_nz, float *P, hipStream_t st) {

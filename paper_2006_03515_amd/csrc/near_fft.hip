@@ -15,8 +15,10 @@
 // Frequencies (kx, ky, kz), kz <= 7, are stored per leaf at f = (ky * 8 + kz) * 16 + kx:
 // 120 columns (ky, kz) of 16 slots, the last slot of each zero.
 //
-//   near_forward_kernel   one workgroup per source leaf: z, y and x transforms of the 8^3
-//                         values zero-padded to 15^3, through LDS; writes 1920 slots.
+//   near_forward_kernel   one wave per source leaf: z, y and x transforms of the 8^3 values
+//                         zero-padded to 15^3, each lane holding a line in registers and
+//                         forming all its frequencies (twiddles as immediates); writes
+//                         1920 slots.
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
@@ -27,8 +29,8 @@
 //                         XCD-contiguous order of the workgroups.
 //                         Each chunk ends with the first inverse stage (over kx, at the 8
 //                         cells x of the leaf), so 8 values per (ky, kz) are written.
-//   near_inverse_kernel   one workgroup per target leaf: the y and z inverse transforms,
-//                         only the 8^3 cells of the leaf.
+//   near_inverse_kernel   one wave per target leaf: the y and z inverse transforms, only
+//                         the 8^3 cells of the leaf.
 #include "common.h"
 
 namespace kifmm {
@@ -49,61 +51,92 @@ __device__ __forceinline__ int next15(int m, int k) {
     return m >= 15 ? m - 15 : m;
 }
 
+// The same values as compile-time constants, for the transforms below: with every loop
+// over frequencies and cells unrolled, each twiddle is an immediate operand.
+constexpr float kC15[15] = {1.000000000e+00f, 9.135454576e-01f, 6.691306064e-01f, 3.090169944e-01f, -1.045284633e-01f, -5.000000000e-01f, -8.090169944e-01f, -9.781476007e-01f, -9.781476007e-01f, -8.090169944e-01f, -5.000000000e-01f, -1.045284633e-01f, 3.090169944e-01f, 6.691306064e-01f, 9.135454576e-01f};
+constexpr float kS15[15] = {0.000000000e+00f, 4.067366431e-01f, 7.431448255e-01f, 9.510565163e-01f, 9.945218954e-01f, 8.660254038e-01f, 5.877852523e-01f, 2.079116908e-01f, -2.079116908e-01f, -5.877852523e-01f, -8.660254038e-01f, -9.945218954e-01f, -9.510565163e-01f, -7.431448255e-01f, -4.067366431e-01f};
+
+// LDS handoff between the lanes of one wave (the transforms below use no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int LPW = 4;   // leaves per workgroup of the transforms: one per wave
+
+// One wave per leaf.  z: lane = (x, y) reads its 8 contiguous values and forms kz = 0..7;
+// y: lane = (x, kz) forms ky = 0..14 (twiddles as immediates); x: 15 groups of 8 columns
+// (ky, kz), lane = (column, slot pair).  Each lane keeps its inputs in registers, so LDS
+// carries only the hand-offs.
 __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restrict__ q, const uint8_t *__restrict__ in_nz,
-                                                           float2 *__restrict__ Q) {
-    __shared__ float qs[512];
-    __shared__ float2 Z[8 * 8 * 8];   // [x][y][kz]
-    __shared__ float2 Y[8 * NCOL];    // [x][ky][kz]
-    __shared__ float cs15[15], sn15[15];
-    const int tid = threadIdx.x;
-    const int64_t leaf = blockIdx.x;
-    if (in_nz && !in_nz[leaf]) return;   // never read: the products skip zero leaves
-    if (tid < 15) {
-        cs15[tid] = kCos15[tid];
-        sn15[tid] = kSin15[tid];
-    }
-    qs[tid] = q[leaf * 512 + tid];
-    qs[tid + 256] = q[leaf * 512 + 256 + tid];
-    __syncthreads();
-    for (int e = tid; e < 512; e += 256) {   // z: real in, kz = 0..7
-        const int x = e >> 6, y = (e >> 3) & 7, kz = e & 7;
-        float re = 0.f, im = 0.f;
-        int m = 0;   // kz z mod 15
+                                                           int64_t nleaf, float2 *__restrict__ Q) {
+    __shared__ float2 W[LPW][8 * NCOL];   // per wave: Z [kz][x][y], then Y [x][ky][kz]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * LPW + w;
+    if (leaf >= nleaf || (in_nz && !in_nz[leaf])) return;   // never read: the products skip zero leaves
+    float2 *Wb = W[w];
+    {
+        const float4 *src = (const float4 *)(q + leaf * 512 + lane * 8);
+        const float4 a = src[0], b = src[1];
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int z = 0; z < 8; ++z, m = next15(m, kz)) {
-            const float v = qs[(x * 8 + y) * 8 + z];
-            re = fmaf(v, cs15[m], re);
-            im = fmaf(-v, sn15[m], im);
-        }
-        Z[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    for (int e = tid; e < 8 * NCOL; e += 256) {   // y: ky = 0..14
-        const int x = e / NCOL, ky = (e >> 3) % 15, kz = e & 7;
-        float re = 0.f, im = 0.f;
-        int m = 0;   // ky y mod 15
+        for (int kz = 0; kz < 8; ++kz) {
+            float re = 0.f, im = 0.f;
 #pragma unroll
-        for (int y = 0; y < 8; ++y, m = next15(m, ky)) {
-            const float2 v = Z[(x * 8 + y) * 8 + kz];
-            const float c = cs15[m], s = sn15[m];
-            re = fmaf(v.x, c, fmaf(v.y, s, re));
-            im = fmaf(v.y, c, fmaf(-v.x, s, im));
+            for (int z = 0; z < 8; ++z) {
+                re = fmaf(v[z], kC15[(kz * z) % 15], re);
+                im = fmaf(-v[z], kS15[(kz * z) % 15], im);
+            }
+            Wb[kz * 64 + lane] = make_float2(re, im);
         }
-        Y[e] = make_float2(re, im);
     }
-    __syncthreads();
-    for (int f = tid; f < NF; f += 256) {   // x: kx = 0..14, written at f = (ky * 8 + kz) * 16 + kx
-        const int kx = f & 15, r = f >> 4;   // r = ky * 8 + kz; slot kx = 15 is written as zero
-        float re = 0.f, im = 0.f;
-        int m = 0;   // kx x mod 15
+    wave_sync();
+    {
+        const int x = lane >> 3, kz = lane & 7;
+        float2 v[8];
 #pragma unroll
-        for (int x = 0; x < 8; ++x, m = next15(m, kx)) {
-            const float2 v = Y[x * NCOL + r];
-            const float c = cs15[m], s = sn15[m];
-            re = fmaf(v.x, c, fmaf(v.y, s, re));
-            im = fmaf(v.y, c, fmaf(-v.x, s, im));
+        for (int y = 0; y < 8; ++y) v[y] = Wb[kz * 64 + x * 8 + y];
+        wave_sync();   // Y overwrites Z
+#pragma unroll
+        for (int ky = 0; ky < 15; ++ky) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int y = 0; y < 8; ++y) {
+                const float c = kC15[(ky * y) % 15], sv = kS15[(ky * y) % 15];
+                re = fmaf(v[y].x, c, fmaf(v[y].y, sv, re));
+                im = fmaf(v[y].y, c, fmaf(-v[y].x, sv, im));
+            }
+            Wb[x * NCOL + ky * 8 + kz] = make_float2(re, im);
         }
-        Q[leaf * NF + f] = kx < 15 ? make_float2(re, im) : make_float2(0.f, 0.f);
+    }
+    wave_sync();
+    // x: lane = (column of a group of 8, slot pair kp): the slots 2 kp, 2 kp + 1 of the
+    // column, so one store of the wave writes 8 whole columns (1 KB, contiguous)
+    const int kp = lane & 7;
+    float c0[8], s0[8], c1[8], s1[8];   // twiddles of kx = 2 kp and 2 kp + 1 (15: slot kept 0)
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const int m0 = (2 * kp * x) % 15, m1 = ((2 * kp + 1) * x) % 15;
+        c0[x] = kCos15[m0];
+        s0[x] = kSin15[m0];
+        c1[x] = kp == 7 ? 0.f : kCos15[m1];
+        s1[x] = kp == 7 ? 0.f : kSin15[m1];
+    }
+    float4 *dst = (float4 *)(Q + leaf * NF) + lane;
+#pragma unroll 3
+    for (int g = 0; g < NCOL / 8; ++g) {
+        const int r = 8 * g + (lane >> 3);   // column ky * 8 + kz
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const float2 v = Wb[x * NCOL + r];
+            o.x = fmaf(v.x, c0[x], fmaf(v.y, s0[x], o.x));
+            o.y = fmaf(v.y, c0[x], fmaf(-v.x, s0[x], o.y));
+            o.z = fmaf(v.x, c1[x], fmaf(v.y, s1[x], o.z));
+            o.w = fmaf(v.y, c1[x], fmaf(-v.x, s1[x], o.w));
+        }
+        dst[64 * g] = o;
     }
 }
 
@@ -214,46 +247,52 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
     }
 }
 
+// One wave per leaf.  y: lane = (kz, x) reads its 15 values (ky = 0..14) of the sums after
+// the x stage, coalesced, and forms y = 0..7; z: lane = (x, y) forms the 8 real values
+// along z (the conjugate half counted twice) and writes them, contiguous.
 __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restrict__ U,
-                                                           const uint8_t *__restrict__ out_need, float *__restrict__ S) {
-    __shared__ float2 Us[NCOL * 8];   // [ky * 8 + kz][x], after the x stage (products kernel)
-    __shared__ float2 V[8 * 8 * 8];   // [x][y][kz]
-    __shared__ float cs15[15], sn15[15];
-    const int tid = threadIdx.x;
-    const int64_t leaf = blockIdx.x;
-    if (out_need && !out_need[leaf]) return;   // never read: the final sum writes 0 there
-    if (tid < 15) {
-        cs15[tid] = kCos15[tid];
-        sn15[tid] = kSin15[tid];
-    }
-    for (int e = tid; e < NCOL * 4; e += 256) ((float4 *)Us)[e] = ((const float4 *)(U + leaf * NCOL * 8))[e];
-    __syncthreads();
-    for (int e = tid; e < 512; e += 256) {   // y: e^{+i theta}
-        const int x = e >> 6, y = (e >> 3) & 7, kz = e & 7;
-        float re = 0.f, im = 0.f;
-        int m = 0;   // ky y mod 15
+                                                           const uint8_t *__restrict__ out_need, int64_t nleaf,
+                                                           float *__restrict__ S) {
+    __shared__ float2 V[LPW][512];   // per wave: [x][y][kz]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * LPW + w;
+    if (leaf >= nleaf || (out_need && !out_need[leaf])) return;   // never read: the final sum writes 0 there
+    float2 *Vb = V[w];
+    {
+        const int kz = lane >> 3, x = lane & 7;
+        float2 u[15];
 #pragma unroll
-        for (int ky = 0; ky < 15; ++ky, m = next15(m, y)) {
-            const float2 v = Us[(ky * 8 + kz) * 8 + x];
-            const float c = cs15[m], s = sn15[m];
-            re = fmaf(v.x, c, fmaf(-v.y, s, re));
-            im = fmaf(v.y, c, fmaf(v.x, s, im));
+        for (int ky = 0; ky < 15; ++ky) u[ky] = U[leaf * NCOL * 8 + ky * 64 + lane];   // [ky * 8 + kz][x]
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int ky = 0; ky < 15; ++ky) {
+                const float c = kC15[(ky * y) % 15], sv = kS15[(ky * y) % 15];
+                re = fmaf(u[ky].x, c, fmaf(-u[ky].y, sv, re));
+                im = fmaf(u[ky].y, c, fmaf(u[ky].x, sv, im));
+            }
+            Vb[(x * 8 + y) * 8 + kz] = make_float2(re, im);
         }
-        V[e] = make_float2(re, im);
     }
-    __syncthreads();
-    for (int e = tid; e < 512; e += 256) {   // z: real part, the conjugate half counted twice
-        const int x = e >> 6, y = (e >> 3) & 7, z = e & 7;
+    wave_sync();
+    float2 v[8];
+#pragma unroll
+    for (int kz = 0; kz < 8; ++kz) v[kz] = Vb[lane * 8 + kz];
+    float o[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
         float acc = 0.f;
-        int m = 0;   // kz z mod 15
 #pragma unroll
-        for (int kz = 0; kz < 8; ++kz, m = next15(m, z)) {
-            const float2 v = V[(x * 8 + y) * 8 + kz];
-            const float w = kz == 0 ? 1.f : 2.f;
-            acc = fmaf(w * v.x, cs15[m], fmaf(-w * v.y, sn15[m], acc));
+        for (int kz = 0; kz < 8; ++kz) {
+            const float wgt = (kz == 0 ? 1.0f : 2.0f) / 3375.0f;
+            acc = fmaf(v[kz].x, wgt * kC15[(kz * z) % 15], fmaf(-v[kz].y, wgt * kS15[(kz * z) % 15], acc));
         }
-        S[leaf * 512 + e] = acc * (1.0f / 3375.0f);
+        o[z] = acc;
     }
+    float4 *dst = (float4 *)(S + leaf * 512 + lane * 8);
+    dst[0] = make_float4(o[0], o[1], o[2], o[3]);
+    dst[1] = make_float4(o[4], o[5], o[6], o[7]);
 }
 
 }  // namespace
@@ -264,12 +303,14 @@ int run_near_fft_stage(int stage, const float *q, const float *Gh, int nb, const
     if (nb < 4 || (nb & (nb - 1)) != 0) return fail(KIFMM_EINVAL, "near-field spectra: leaves per axis must be 4, 8, 16, ...");
     const int64_t nleaf = (int64_t)nb * nb * nb;
     if (stage == 0)
-        hipLaunchKernelGGL(near_forward_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, q, in_nz, (float2 *)Qbuf);
+        hipLaunchKernelGGL(near_forward_kernel, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st, q, in_nz,
+                           nleaf, (float2 *)Qbuf);
     else if (stage == 1)
         hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16 / NCH))), dim3(256), 0, st,
                            (const float2 *)Qbuf, (const float2 *)Gh, nb, out_need, in_nz, (float2 *)Pbuf);
     else
-        hipLaunchKernelGGL(near_inverse_kernel, dim3((unsigned)nleaf), dim3(256), 0, st, (const float2 *)Pbuf, out_need,
+        hipLaunchKernelGGL(near_inverse_kernel, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st,
+                           (const float2 *)Pbuf, out_need, nleaf,
                            S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
