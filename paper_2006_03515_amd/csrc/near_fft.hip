@@ -37,22 +37,15 @@ namespace kifmm {
 
 namespace {
 
-// cos and sin of 2 pi m / 15, m = 0..14; each kernel copies them to LDS, since the index
-// differs between lanes
+// cos and sin of 2 pi m / 15, m = 0..14, for twiddles whose index differs between lanes
 __constant__ float kCos15[15] = {1.000000000f, 0.913545458f, 0.669130606f, 0.309016994f, -0.104528463f, -0.500000000f, -0.809016994f, -0.978147601f, -0.978147601f, -0.809016994f, -0.500000000f, -0.104528463f, 0.309016994f, 0.669130606f, 0.913545458f};
 __constant__ float kSin15[15] = {0.000000000f, 0.406736643f, 0.743144825f, 0.951056516f, 0.994521895f, 0.866025404f, 0.587785252f, 0.207911691f, -0.207911691f, -0.587785252f, -0.866025404f, -0.994521895f, -0.951056516f, -0.743144825f, -0.406736643f};
 
 constexpr int NCOL = 120;       // columns (ky, kz): 15 x 8
 constexpr int NF = NCOL * 16;   // frequency slots per leaf
 
-// m + k mod 15 for m, k in [0, 15): the twiddle index of the next term of a sum
-__device__ __forceinline__ int next15(int m, int k) {
-    m += k;
-    return m >= 15 ? m - 15 : m;
-}
-
-// The same values as compile-time constants, for the transforms below: with every loop
-// over frequencies and cells unrolled, each twiddle is an immediate operand.
+// The same values as compile-time constants: with every loop over frequencies and cells
+// unrolled, each twiddle is an immediate operand.
 constexpr float kC15[15] = {1.000000000e+00f, 9.135454576e-01f, 6.691306064e-01f, 3.090169944e-01f, -1.045284633e-01f, -5.000000000e-01f, -8.090169944e-01f, -9.781476007e-01f, -9.781476007e-01f, -8.090169944e-01f, -5.000000000e-01f, -1.045284633e-01f, 3.090169944e-01f, 6.691306064e-01f, 9.135454576e-01f};
 constexpr float kS15[15] = {0.000000000e+00f, 4.067366431e-01f, 7.431448255e-01f, 9.510565163e-01f, 9.945218954e-01f, 8.660254038e-01f, 5.877852523e-01f, 2.079116908e-01f, -2.079116908e-01f, -5.877852523e-01f, -8.660254038e-01f, -9.945218954e-01f, -9.510565163e-01f, -7.431448255e-01f, -4.067366431e-01f};
 
@@ -142,18 +135,15 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
 
 constexpr int NCH = 4;   // frequency chunks per products workgroup
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__restrict__ Q, const float2 *__restrict__ Gh,
                                                             int nb, const uint8_t *__restrict__ out_need,
                                                             const uint8_t *__restrict__ in_nz, float2 *__restrict__ P) {
     __shared__ float2 Es[216 * 16];   // [region leaf][kx]
     __shared__ float2 Gs[27 * 16];    // [offset][kx]
     __shared__ float2 Ps[64 * 17];    // [target][kx] sums of one chunk (padded row)
-    __shared__ float cs15[15], sn15[15];
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid < 15) {
-        cs15[tid] = kCos15[tid];
-        sn15[tid] = kSin15[tid];
-    }
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
     // source spectra run out of the same L2.
@@ -170,7 +160,8 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
     bx = 4 * bx - 1;
     by = 4 * by - 1;
     bz = 4 * bz - 1;
-    // this thread's share of the staging: region leaves of e = tid + 256 i (8 float4 each)
+    // this thread's share of the staging: region leaves of e = tid + 256 i (8 float4 each);
+    // leaves outside the grid and zero leaves are not read
     const float4 *src[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
@@ -191,6 +182,20 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         for (int i = 0; i < 7; ++i) pre[i] = src[i] ? src[i][c * 8] : make_float4(0.f, 0.f, 0.f, 0.f);
         if (gsrc) gpre = gsrc[c * 8];
     };
+    // the first inverse stage as an MFMA: this lane's entries of the real 32 x 16 DFT matrix
+    // (k = 2 kx + re/im, n = 2 x + re/im; the padding slot kx = 15 has zero rows), in the
+    // A-operand layout of v_mfma_f32_16x16x4f32 for the transposed product (row n = lane
+    // % 16, k = 4 ks + lane / 16)
+    const int g4 = lane >> 4, n16 = lane & 15;
+    float wdft[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const int k = 4 * ks + g4, kx = k >> 1, x = n16 >> 1;
+        const int m = (kx * x) % 15;
+        const float cv = kCos15[m], sv = kSin15[m];
+        const float re_row = (k & 1) ? -sv : cv, im_row = (k & 1) ? cv : sv;   // U += P e^{+i theta}
+        wdft[ks] = kx >= 15 ? 0.f : ((n16 & 1) ? im_row : re_row);
+    }
     // lane: frequency f and a column of 4 targets (a, b, 0..3) of the block, so that for
     // each (ox, oy) the 4 targets' 12 taps read 6 source spectra
     const int f = tid & 15, grp = tid >> 4, ta = grp >> 2, tb = grp & 3;
@@ -228,20 +233,18 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         for (int s = 0; s < 4; ++s) Ps[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
         __syncthreads();
         // first inverse stage, over kx, at the 8 cells x of each target: this chunk holds all
-        // 15 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 15}
+        // 15 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 15}.  Wave
+        // w: the 16 targets 16 w .. 16 w + 15, as U^T = W^T P^T over the reals (K = 32); the
+        // B operand (k = 4 ks + lane / 16, target lane % 16) is read from Ps, and the lane's
+        // 4 results (n = 4 (lane / 16) + v) are x = 2 (lane / 16), + 1, re and im.
+        {
+            const int w = tid >> 6, t = 16 * w + n16;
+            const float *pt = (const float *)(Ps + t * 17);
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int t = tid >> 2, x = 2 * (tid & 3) + h;
-            float re = 0.f, im = 0.f;
-            int m = 0;   // kx x mod 15
-#pragma unroll
-            for (int kx = 0; kx < 15; ++kx, m = next15(m, x)) {
-                const float2 v = Ps[t * 17 + kx];
-                const float cc = cs15[m], ss = sn15[m];
-                re = fmaf(v.x, cc, fmaf(-v.y, ss, re));
-                im = fmaf(v.y, cc, fmaf(v.x, ss, im));
-            }
-            P[((64 * blk + t) * (NF / 16) + c) * 8 + x] = make_float2(re, im);
+            for (int ks = 0; ks < 8; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wdft[ks], pt[(2 * ks + (g4 >> 1)) * 2 + (g4 & 1)], acc, 0, 0, 0);
+            *(float4 *)(P + ((64 * blk + t) * NCOL + c) * 8 + 2 * g4) = make_float4(acc[0], acc[1], acc[2], acc[3]);
         }
         __syncthreads();   // the staging of the next chunk overwrites Es, Gs and Ps
     }
