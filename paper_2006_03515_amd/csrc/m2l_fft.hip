@@ -17,9 +17,9 @@
 // reals (re, im interleaved), that is a 16 x 432 matrix per frequency applied to 432 gathered
 // values per parent: a GEMM with 16 rows, K = 432 and one column per parent.
 //
-//   m2l_lattice_forward_kernel / m2l_lattice_inverse_kernel  a few boxes per workgroup:
-//                        the separable transforms between the m0^3 lattice values and the
-//                        half spectrum (z, y, x stages through LDS; inverse x, y, z).
+//   m2l_lattice_forward_kernel / m2l_lattice_inverse_kernel  one wave per box: the
+//                        separable transforms between the m0^3 lattice values and the half
+//                        spectrum (z, y, x stages; inverse x, y, z).
 //   m2l_pair_mfma_kernel one workgroup per aligned 4^3 block of parents (512 target boxes) and
 //                        4 frequencies; the spectra of the block's source region (6^3
 //                        parents x 8 children) are staged in LDS, [frequency][child][re/im]
@@ -37,8 +37,6 @@
 //                        8 targets of class w (the child position, which fixes the tap
 //                        list); lane = 16 frequencies x 4 pairs of targets, so every
 //                        tap's operator entry is read once per two targets.
-#include <cmath>
-
 #include "common.h"
 #include "tapgemm.h"
 
@@ -48,9 +46,6 @@ namespace {
 
 constexpr int HFC = 16;   // frequencies per workgroup
 
-struct LatticeTwiddles {   // cos and sin of 2 pi k / N, k < N <= 15
-    float c[16], s[16];
-};
 
 __global__ __launch_bounds__(512) void m2l_hadamard_kernel(const float2 *__restrict__ E, const float2 *__restrict__ Gh,
                                                            const int *__restrict__ tap_op,
@@ -207,158 +202,203 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
 }
 
 // Transforms between the lattice values of a box (m0^3 equivalent densities or check
-// potentials, C order (x, y, z), rows of m0^3 padded to 32 floats) and its half spectrum on the cyclic
-// N^3 grid, N = 2 m0 - 1: frequency (kx, ky, kz), kz < m0, at f = (kx N + ky) m0 + kz.
-// Separable: three one-dimensional DFTs through LDS, NB boxes per workgroup.  The
-// spectra rows hold nfp = f padded to 16 complex values, the padding written as zeros.
+// potentials, C order (x, y, z), rows of m0^3 padded to 32 floats) and its half spectrum on
+// the cyclic N^3 grid, N = 2 m0 - 1: frequency (kx, ky, kz), kz < m0, at
+// f = (kx N + ky) m0 + kz.  Separable, one wave per box (four per workgroup): each lane
+// holds one line of a stage in registers and forms all its outputs, with the twiddles as
+// immediates (every loop over cells and frequencies is unrolled); LDS carries the two
+// hand-offs between stages.  The spectra rows hold nfp = f padded to 16 complex values, the
+// padding written as zeros.
 template <int M>
 struct LatticeDims {
     static constexpr int N = 2 * M - 1, NF = N * N * M, NFP = (NF + 15) / 16 * 16, M3 = M * M * M;
+    static constexpr int NM = N * M;                  // columns (ky, kz) of the x stage
     static constexpr int ROW = (M3 + 31) / 32 * 32;   // lattice row length
-    static constexpr int NB = M >= 7 ? 2 : 4;   // boxes per workgroup (LDS: at most 52 KB)
 };
 
-// i + k mod n for i, k in [0, n): the twiddle index of the next term of a sum
+// cos and sin of 2 pi m / N, m < N, for the odd N = 2 m0 - 1 of m0 = 3 .. 8
 template <int N>
-__device__ __forceinline__ int next_mod(int i, int k) {
-    i += k;
-    return i >= N ? i - N : i;
+struct TwTab;
+template <>
+struct TwTab<5> {
+    static constexpr float c[5] = {1.000000000e+00f, 3.090169944e-01f, -8.090169944e-01f, -8.090169944e-01f, 3.090169944e-01f};
+    static constexpr float s[5] = {0.000000000e+00f, 9.510565163e-01f, 5.877852523e-01f, -5.877852523e-01f, -9.510565163e-01f};
+};
+template <>
+struct TwTab<7> {
+    static constexpr float c[7] = {1.000000000e+00f, 6.234898019e-01f, -2.225209340e-01f, -9.009688679e-01f, -9.009688679e-01f, -2.225209340e-01f, 6.234898019e-01f};
+    static constexpr float s[7] = {0.000000000e+00f, 7.818314825e-01f, 9.749279122e-01f, 4.338837391e-01f, -4.338837391e-01f, -9.749279122e-01f, -7.818314825e-01f};
+};
+template <>
+struct TwTab<9> {
+    static constexpr float c[9] = {1.000000000e+00f, 7.660444431e-01f, 1.736481777e-01f, -5.000000000e-01f, -9.396926208e-01f, -9.396926208e-01f, -5.000000000e-01f, 1.736481777e-01f, 7.660444431e-01f};
+    static constexpr float s[9] = {0.000000000e+00f, 6.427876097e-01f, 9.848077530e-01f, 8.660254038e-01f, 3.420201433e-01f, -3.420201433e-01f, -8.660254038e-01f, -9.848077530e-01f, -6.427876097e-01f};
+};
+template <>
+struct TwTab<11> {
+    static constexpr float c[11] = {1.000000000e+00f, 8.412535328e-01f, 4.154150130e-01f, -1.423148383e-01f, -6.548607339e-01f, -9.594929736e-01f, -9.594929736e-01f, -6.548607339e-01f, -1.423148383e-01f, 4.154150130e-01f, 8.412535328e-01f};
+    static constexpr float s[11] = {0.000000000e+00f, 5.406408175e-01f, 9.096319954e-01f, 9.898214419e-01f, 7.557495744e-01f, 2.817325568e-01f, -2.817325568e-01f, -7.557495744e-01f, -9.898214419e-01f, -9.096319954e-01f, -5.406408175e-01f};
+};
+template <>
+struct TwTab<13> {
+    static constexpr float c[13] = {1.000000000e+00f, 8.854560257e-01f, 5.680647467e-01f, 1.205366803e-01f, -3.546048870e-01f, -7.485107482e-01f, -9.709418174e-01f, -9.709418174e-01f, -7.485107482e-01f, -3.546048870e-01f, 1.205366803e-01f, 5.680647467e-01f, 8.854560257e-01f};
+    static constexpr float s[13] = {0.000000000e+00f, 4.647231720e-01f, 8.229838659e-01f, 9.927088741e-01f, 9.350162427e-01f, 6.631226582e-01f, 2.393156643e-01f, -2.393156643e-01f, -6.631226582e-01f, -9.350162427e-01f, -9.927088741e-01f, -8.229838659e-01f, -4.647231720e-01f};
+};
+template <>
+struct TwTab<15> {
+    static constexpr float c[15] = {1.000000000e+00f, 9.135454576e-01f, 6.691306064e-01f, 3.090169944e-01f, -1.045284633e-01f, -5.000000000e-01f, -8.090169944e-01f, -9.781476007e-01f, -9.781476007e-01f, -8.090169944e-01f, -5.000000000e-01f, -1.045284633e-01f, 3.090169944e-01f, 6.691306064e-01f, 9.135454576e-01f};
+    static constexpr float s[15] = {0.000000000e+00f, 4.067366431e-01f, 7.431448255e-01f, 9.510565163e-01f, 9.945218954e-01f, 8.660254038e-01f, 5.877852523e-01f, 2.079116908e-01f, -2.079116908e-01f, -5.877852523e-01f, -8.660254038e-01f, -9.945218954e-01f, -9.510565163e-01f, -7.431448255e-01f, -4.067366431e-01f};
+};
+
+// LDS hand-off between the lanes of one wave
+__device__ __forceinline__ void lattice_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+constexpr int LBW = 4;   // boxes per workgroup of the lattice transforms: one per wave
 
 template <int M>
 __global__ __launch_bounds__(256) void m2l_lattice_forward_kernel(const float *__restrict__ dens, int64_t nbx,
-                                                                  const uint8_t *__restrict__ in_nz, LatticeTwiddles tw,
+                                                                  const uint8_t *__restrict__ in_nz,
                                                                   float2 *__restrict__ E) {
     using L = LatticeDims<M>;
-    constexpr int N = L::N, NB = L::NB, M3 = L::M3;
-    __shared__ float ds[NB * M3];
-    __shared__ float2 Z[NB * M3];       // [b][x][y][kz]
-    __shared__ float2 Y[NB * M * N * M];  // [b][x][ky][kz]
-    __shared__ float cs[N], sn[N];
-    const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * NB;
-    if (tid < N) {
-        cs[tid] = tw.c[tid];
-        sn[tid] = tw.s[tid];
-    }
-    for (int e = tid; e < NB * M3; e += 256) {
-        const int64_t box = b0 + e / M3;
-        ds[e] = box < nbx ? dens[box * L::ROW + e % M3] : 0.f;
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * M3; e += 256) {   // z: real in, kz = 0..M-1
-        const int b = e / M3, r = e % M3, xy = r / M, kz = r % M;
-        float re = 0.f, im = 0.f;
-        int i = 0;   // kz z mod N
+    using T = TwTab<L::N>;
+    constexpr int N = L::N, NM = L::NM, MM = M * M;
+    __shared__ float2 Z[LBW][L::M3];      // [kz][x][y]
+    __shared__ float2 Y[LBW][M * NM];     // [x][ky][kz]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t box = (int64_t)blockIdx.x * LBW + w;
+    if (box >= nbx || (in_nz && !in_nz[box])) return;   // never read: zero boxes are skipped
+    if (lane < MM) {   // z: lane = (x, y), real in, kz = 0..M-1
+        const float *src = dens + box * L::ROW + lane * M;
+        float v[M];
 #pragma unroll
-        for (int z = 0; z < M; ++z, i = next_mod<N>(i, kz)) {
-            const float v = ds[b * M3 + xy * M + z];
-            re = fmaf(v, cs[i], re);
-            im = fmaf(-v, sn[i], im);
-        }
-        Z[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * M * N * M; e += 256) {   // y: ky = 0..N-1
-        const int b = e / (M * N * M), r = e % (M * N * M), x = r / (N * M), ky = (r / M) % N, kz = r % M;
-        float re = 0.f, im = 0.f;
-        int i = 0;   // ky y mod N
+        for (int z = 0; z < M; ++z) v[z] = src[z];
 #pragma unroll
-        for (int y = 0; y < M; ++y, i = next_mod<N>(i, ky)) {
-            const float2 v = Z[b * M3 + (x * M + y) * M + kz];
-            re = fmaf(v.x, cs[i], fmaf(v.y, sn[i], re));
-            im = fmaf(v.y, cs[i], fmaf(-v.x, sn[i], im));
-        }
-        Y[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * L::NFP; e += 256) {   // x: kx = 0..N-1, written in frequency order
-        const int b = e / L::NFP, f = e % L::NFP;
-        const int64_t box = b0 + b;
-        if (box >= nbx || (in_nz && !in_nz[box])) continue;   // never read: zero boxes are skipped
-        float re = 0.f, im = 0.f;
-        if (f < L::NF) {
-            const int kx = f / (N * M), c = f % (N * M);
-            int i = 0;   // kx x mod N
+        for (int kz = 0; kz < M; ++kz) {
+            float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int x = 0; x < M; ++x, i = next_mod<N>(i, kx)) {
-                const float2 v = Y[b * M * N * M + x * N * M + c];
-                re = fmaf(v.x, cs[i], fmaf(v.y, sn[i], re));
-                im = fmaf(v.y, cs[i], fmaf(-v.x, sn[i], im));
+            for (int z = 0; z < M; ++z) {
+                re = fmaf(v[z], T::c[(kz * z) % N], re);
+                im = fmaf(-v[z], T::s[(kz * z) % N], im);
             }
+            Z[w][kz * MM + lane] = make_float2(re, im);
         }
-        E[box * L::NFP + f] = make_float2(re, im);
     }
+    lattice_wave_sync();
+    if (lane < MM) {   // y: lane = (x, kz), ky = 0..N-1
+        const int x = lane / M, kz = lane % M;
+        float2 v[M];
+#pragma unroll
+        for (int y = 0; y < M; ++y) v[y] = Z[w][kz * MM + x * M + y];
+#pragma unroll
+        for (int ky = 0; ky < N; ++ky) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int y = 0; y < M; ++y) {
+                const float c = T::c[(ky * y) % N], sv = T::s[(ky * y) % N];
+                re = fmaf(v[y].x, c, fmaf(v[y].y, sv, re));
+                im = fmaf(v[y].y, c, fmaf(-v[y].x, sv, im));
+            }
+            Y[w][x * NM + ky * M + kz] = make_float2(re, im);
+        }
+    }
+    lattice_wave_sync();
+    float2 *dst = E + box * L::NFP;
+    for (int c = lane; c < NM; c += 64) {   // x: lane = column (ky, kz), kx = 0..N-1
+        float2 v[M];
+#pragma unroll
+        for (int x = 0; x < M; ++x) v[x] = Y[w][x * NM + c];
+#pragma unroll
+        for (int kx = 0; kx < N; ++kx) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int x = 0; x < M; ++x) {
+                const float cv = T::c[(kx * x) % N], sv = T::s[(kx * x) % N];
+                re = fmaf(v[x].x, cv, fmaf(v[x].y, sv, re));
+                im = fmaf(v[x].y, cv, fmaf(-v[x].x, sv, im));
+            }
+            dst[kx * NM + c] = make_float2(re, im);
+        }
+    }
+    for (int f = L::NF + lane; f < L::NFP; f += 64) dst[f] = make_float2(0.f, 0.f);
 }
 
 // Inverse: the real lattice values (1 / N^3) sum_f w_kz Re(P(f) e^{+i theta}), w_kz = 1 at
-// kz = 0 and 2 above (the conjugate half); the padding values of a row are zeros,
-// and so is the whole row of a box that is not wanted.
+// kz = 0 and 2 above (the conjugate half); the padding values of a row are zeros, and so is
+// the whole row of a box that is not wanted.
 template <int M>
 __global__ __launch_bounds__(256) void m2l_lattice_inverse_kernel(const float2 *__restrict__ P, int64_t nbx,
-                                                                  const uint8_t *__restrict__ out_need, LatticeTwiddles tw,
+                                                                  const uint8_t *__restrict__ out_need,
                                                                   float *__restrict__ dens) {
     using L = LatticeDims<M>;
-    constexpr int N = L::N, NB = L::NB, M3 = L::M3, NF = L::NF;
-    __shared__ float2 Ps[NB * NF];        // [b][kx][ky][kz]
-    __shared__ float2 A[NB * M * N * M];  // [b][x][ky][kz]
-    __shared__ float2 B[NB * M3];         // [b][x][y][kz]
-    __shared__ float cs[N], sn[N];
-    const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * NB;
-    if (tid < N) {
-        cs[tid] = tw.c[tid];
-        sn[tid] = tw.s[tid];
+    using T = TwTab<L::N>;
+    constexpr int N = L::N, NM = L::NM, MM = M * M;
+    __shared__ float2 A[LBW][M * NM];   // [x][ky][kz]
+    __shared__ float2 B[LBW][L::M3];    // [x][y][kz]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t box = (int64_t)blockIdx.x * LBW + w;
+    if (box >= nbx) return;
+    float *dst = dens + box * L::ROW;
+    if (out_need && !out_need[box]) {
+        for (int j = lane; j < L::ROW; j += 64) dst[j] = 0.f;
+        return;
     }
-    for (int e = tid; e < NB * NF; e += 256) {
-        const int64_t box = b0 + e / NF;
-        Ps[e] = box < nbx ? P[box * L::NFP + e % NF] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * M * N * M; e += 256) {   // x: e^{+i theta}
-        const int b = e / (M * N * M), r = e % (M * N * M), x = r / (N * M), c = r % (N * M);
-        float re = 0.f, im = 0.f;
-        int i = 0;   // kx x mod N
+    const float2 *src = P + box * L::NFP;
+    for (int c = lane; c < NM; c += 64) {   // x: lane = column (ky, kz), e^{+i theta}
+        float2 u[N];
 #pragma unroll
-        for (int kx = 0; kx < N; ++kx, i = next_mod<N>(i, x)) {
-            const float2 v = Ps[b * NF + kx * N * M + c];
-            re = fmaf(v.x, cs[i], fmaf(-v.y, sn[i], re));
-            im = fmaf(v.y, cs[i], fmaf(v.x, sn[i], im));
-        }
-        A[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * M3; e += 256) {   // y
-        const int b = e / M3, r = e % M3, x = r / (M * M), y = (r / M) % M, kz = r % M;
-        float re = 0.f, im = 0.f;
-        int i = 0;   // ky y mod N
+        for (int kx = 0; kx < N; ++kx) u[kx] = src[kx * NM + c];
 #pragma unroll
-        for (int ky = 0; ky < N; ++ky, i = next_mod<N>(i, y)) {
-            const float2 v = A[b * M * N * M + (x * N + ky) * M + kz];
-            re = fmaf(v.x, cs[i], fmaf(-v.y, sn[i], re));
-            im = fmaf(v.y, cs[i], fmaf(v.x, sn[i], im));
-        }
-        B[e] = make_float2(re, im);
-    }
-    __syncthreads();
-    constexpr float inv = 1.0f / (float)(N * N * N);
-    for (int e = tid; e < NB * L::ROW; e += 256) {   // z: real part, written with the row padding
-        const int b = e / L::ROW, j = e % L::ROW;
-        const int64_t box = b0 + b;
-        if (box >= nbx) continue;
-        float acc = 0.f;
-        if (j < M3 && (!out_need || out_need[box])) {
-            const int xy = j / M, z = j % M;
-            int i = 0;   // kz z mod N
+        for (int x = 0; x < M; ++x) {
+            float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int kz = 0; kz < M; ++kz, i = next_mod<N>(i, z)) {
-                const float2 v = B[b * M3 + xy * M + kz];
-                const float w = kz == 0 ? inv : 2.f * inv;
-                acc = fmaf(w * v.x, cs[i], fmaf(-w * v.y, sn[i], acc));
+            for (int kx = 0; kx < N; ++kx) {
+                const float cv = T::c[(kx * x) % N], sv = T::s[(kx * x) % N];
+                re = fmaf(u[kx].x, cv, fmaf(-u[kx].y, sv, re));
+                im = fmaf(u[kx].y, cv, fmaf(u[kx].x, sv, im));
             }
+            A[w][x * NM + c] = make_float2(re, im);
         }
-        dens[box * L::ROW + j] = acc;
     }
+    lattice_wave_sync();
+    if (lane < MM) {   // y: lane = (x, kz)
+        const int x = lane / M, kz = lane % M;
+        float2 u[N];
+#pragma unroll
+        for (int ky = 0; ky < N; ++ky) u[ky] = A[w][x * NM + ky * M + kz];
+#pragma unroll
+        for (int y = 0; y < M; ++y) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int ky = 0; ky < N; ++ky) {
+                const float cv = T::c[(ky * y) % N], sv = T::s[(ky * y) % N];
+                re = fmaf(u[ky].x, cv, fmaf(-u[ky].y, sv, re));
+                im = fmaf(u[ky].y, cv, fmaf(u[ky].x, sv, im));
+            }
+            B[w][(x * M + y) * M + kz] = make_float2(re, im);
+        }
+    }
+    lattice_wave_sync();
+    if (lane < MM) {   // z: lane = (x, y), the real part
+        float2 u[M];
+#pragma unroll
+        for (int kz = 0; kz < M; ++kz) u[kz] = B[w][lane * M + kz];
+        constexpr float inv = 1.0f / (float)(N * N * N);
+#pragma unroll
+        for (int z = 0; z < M; ++z) {
+            float acc = 0.f;
+#pragma unroll
+            for (int kz = 0; kz < M; ++kz) {
+                const float wgt = kz == 0 ? inv : 2.f * inv;
+                acc = fmaf(u[kz].x, wgt * T::c[(kz * z) % N], fmaf(-u[kz].y, wgt * T::s[(kz * z) % N], acc));
+            }
+            dst[lane * M + z] = acc;
+        }
+    }
+    for (int j = L::M3 + lane; j < L::ROW; j += 64) dst[j] = 0.f;
 }
 
 template <int M>
@@ -367,16 +407,11 @@ int launch_lattice(int dir, const float *in, int64_t nbx, int nfp, int row, cons
     using L = LatticeDims<M>;
     if (nfp != L::NFP || row != L::ROW)
         return fail(KIFMM_EINVAL, "lattice transform: spectrum or lattice row length does not match m0");
-    LatticeTwiddles tw{};
-    for (int k = 0; k < L::N; ++k) {
-        tw.c[k] = (float)std::cos(2.0 * M_PI * k / L::N);
-        tw.s[k] = (float)std::sin(2.0 * M_PI * k / L::N);
-    }
-    const unsigned grid = (unsigned)((nbx + L::NB - 1) / L::NB);
+    const unsigned grid = (unsigned)((nbx + LBW - 1) / LBW);
     if (dir == 0)
-        hipLaunchKernelGGL(m2l_lattice_forward_kernel<M>, dim3(grid), dim3(256), 0, st, in, nbx, flags, tw, (float2 *)out);
+        hipLaunchKernelGGL(m2l_lattice_forward_kernel<M>, dim3(grid), dim3(256), 0, st, in, nbx, flags, (float2 *)out);
     else
-        hipLaunchKernelGGL(m2l_lattice_inverse_kernel<M>, dim3(grid), dim3(256), 0, st, (const float2 *)in, nbx, flags, tw,
+        hipLaunchKernelGGL(m2l_lattice_inverse_kernel<M>, dim3(grid), dim3(256), 0, st, (const float2 *)in, nbx, flags,
                            out);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;

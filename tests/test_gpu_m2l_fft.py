@@ -63,6 +63,19 @@ def test_fft_m2l_is_the_dense_m2l(K, g32, p_o2):
     assert rel_l2(c, ora) < 1e-5
 
 
+@pytest.mark.parametrize("m0", [3, 4, 6, 7, 8])
+def test_fft_m2l_other_lattice_sizes(K, g32, m0):
+    # the separable lattice transforms for every supported lattice (N = 2 m0 - 1 = 5 .. 15):
+    # the FFT form is the dense form of the same operators up to FP32 rounding
+    I, L, refs = g32
+    tree = K.build_tree(K.Grid.cube(32, L), 64)
+    ops = K.precompute_operators(tree, K.Kernel(150.0), K.Opts(K.LAYOUT_LATTICE, m0, 10, 1e-7))
+    a = run(K, tree, ops, I, "fp32", True)
+    b = run(K, tree, ops, I, "fp32", False)
+    assert rel_l2(a, b) < 2e-6
+    assert rel_l2(a, refs[150.0]) < 1e-2
+
+
 def test_fft_m2l_deep_tree_random_sources(K):
     # 128^3 with leaves of 8^3: M2L on levels 2..4 (up to 4096 boxes), random sources
     n, L, p_o2 = 128, 0.2, 150.0
