@@ -53,7 +53,7 @@ enum {
     KIFMM_EUNSUPPORTED = -2, /* valid request this library does not implement (e.g. non-cubic grid) */
     KIFMM_EMISMATCH = -3,    /* operators used with a tree they were not built for */
     KIFMM_ENOMEM = -4,       /* device allocation failed */
-    KIFMM_EHIP = -5          /* a HIP runtime call failed; message holds hipGetErrorString */
+    KIFMM_EHIP = -5          /* a HIP runtime or rocBLAS call failed; the message names it */
 };
 
 /* Uniform grid of cell centres (Section 4: V = V' = a box of equal cells). */

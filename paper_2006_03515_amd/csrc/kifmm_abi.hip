@@ -7,6 +7,8 @@
 #include <cstring>
 #include <numeric>
 
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 #include "tapgemm.h"
 
@@ -214,6 +216,7 @@ struct kifmm_ops_s {
     // the near field runs on a second stream, joined by events; with the FFT form of M2L
     // the finest level's M2L runs on a third, beside the upward pass and the coarse levels
     hipStream_t side = nullptr, fine = nullptr;
+    rocblas_handle blas = nullptr;   // FP32 P2M and L2P over all leaves (plain GEMMs)
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
     // per-pass timing (kifmm_profile_enable)
     bool prof = false;
@@ -301,6 +304,7 @@ static void free_ops(kifmm_ops o) {
     if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
     if (o->join_fine) (void)hipEventDestroy(o->join_fine);
     if (o->fine) (void)hipStreamDestroy(o->fine);
+    if (o->blas) (void)rocblas_destroy_handle(o->blas);
     delete o;
 }
 
@@ -903,6 +907,10 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
     KIFMM_HIP(hipStreamCreateWithFlags(&o->fine, hipStreamNonBlocking));
+    if (rocblas_create_handle(&o->blas) != rocblas_status_success) {
+        o->blas = nullptr;
+        return fail(KIFMM_EHIP, "rocblas_create_handle failed");
+    }
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
@@ -1104,6 +1112,18 @@ TapArgs<TA, TI, TO> tap(const TA *A, int64_t a_stride, int M, int K, const TI *i
 }
 
 int run(const TapArgs<float, float, float> &p, hipStream_t st) { return run_tap_f32(p, st); }
+
+// out[b][0:M] = A (M x K, row-major) . in[b][0:K] for the n boxes b, in FP32 through rocBLAS:
+// column-major C (M x n) = A^T^T B with A read as its K x M column-major transpose
+int blas_gemm_tn(kifmm_ops o, int M, int64_t n, int K, const float *A, const float *in, float *out, hipStream_t st) {
+    if (n > INT32_MAX) return fail(KIFMM_EINVAL, "P2M/L2P: too many leaves for one GEMM");
+    if (rocblas_set_stream(o->blas, st) != rocblas_status_success) return fail(KIFMM_EHIP, "rocblas_set_stream failed");
+    const float one = 1.f, zero = 0.f;
+    const rocblas_status r = rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, M, (int)n, K,
+                                           &one, A, K, in, K, &zero, out, M);
+    if (r != rocblas_status_success) return fail(KIFMM_EHIP, std::string("rocblas_sgemm failed: ") + rocblas_status_to_string(r));
+    return KIFMM_OK;
+}
 int run(const TapArgs<double, double, double> &p, hipStream_t st) { return run_tap_f64(p, st); }
 
 template <typename T>
@@ -1335,9 +1355,13 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // far field: upward pass, downward pass, local expansion at the cells
     {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        auto p = tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
-        p.in_nz = nz_of(o, D);
-        KIFMM_TRY(run(p, st));
+        if (sizeof(T) == 4 && !nz_of(o, D)) {   // every leaf: one plain GEMM
+            KIFMM_TRY(blas_gemm_tn(o, KU, nleaf, s, (const float *)ops.p2m, (const float *)q, (float *)o->cu[D], st));
+        } else {
+            auto p = tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
+            p.in_nz = nz_of(o, D);
+            KIFMM_TRY(run(p, st));
+        }
     }
     // FFT form of M2L: the finest level's M2L needs only the leaves' coefficients, so it runs
     // on its own stream beside the upward pass and the coarse levels (their latency-bound
@@ -1383,9 +1407,16 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     }
     {
         PassTimer pt(o, KIFMM_PASS_L2P, st);
-        auto p = tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
-        p.out_need = want_of(o, D);
-        KIFMM_TRY(run(p, st));
+        // every leaf, also when targets are restricted: the wanted leaves then keep the
+        // unrestricted values bit for bit (the others are written as zeros at the end; their
+        // coefficients are finite, every level's coefficients being written in full)
+        if (sizeof(T) == 4) {
+            KIFMM_TRY(blas_gemm_tn(o, s, nleaf, KD, (const float *)ops.l2p, (const float *)o->cd[D], (float *)Sp, st));
+        } else {
+            auto p = tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
+            p.out_need = want_of(o, D);
+            KIFMM_TRY(run(p, st));
+        }
     }
     KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
     PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
