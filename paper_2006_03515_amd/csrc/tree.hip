@@ -74,6 +74,60 @@ __global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restric
     }
 }
 
+// Leaves of 8^3 cells on a grid with n a multiple of 32: one thread per run of 32 cells along
+// k of a grid row (i, j), 128 contiguous bytes on the grid side; on the leaf side the run is
+// the 8-cell lines (i & 7, j & 7) of 4 leaves, 32 contiguous bytes each.  Thread order
+// t = (i n + j) (n / 32) + k / 32.
+__device__ inline void row_of_thread(int64_t t, int n, int &i, int &j, int &kb) {
+    const int nk = n >> 5;
+    kb = (int)(t % nk);
+    const int64_t ij = t / nk;
+    j = (int)(ij % n);
+    i = (int)(ij / n);
+}
+
+__global__ __launch_bounds__(256) void permute_in_rows_kernel(const float *__restrict__ I, int n, int64_t nrows,
+                                                              float scale, float *__restrict__ q) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows) return;
+    int i, j, kb;
+    row_of_thread(t, n, i, j, kb);
+    const float4 *src = (const float4 *)(I + ((int64_t)i * n + j) * n + 32 * kb);
+    const int local = ((i & 7) * 8 + (j & 7)) * 8;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 a = src[2 * c], b = src[2 * c + 1];
+        float4 *dst = (float4 *)(q + (int64_t)morton_encode(i >> 3, j >> 3, 4 * kb + c) * 512 + local);
+        dst[0] = make_float4(a.x * scale, a.y * scale, a.z * scale, a.w * scale);
+        dst[1] = make_float4(b.x * scale, b.y * scale, b.z * scale, b.w * scale);
+    }
+}
+
+// Leaves of 8^3 cells: one thread per 8-cell line (i & 7, j & 7) of a leaf, read contiguous
+// in leaf order (a wave reads 2 KB in one piece) and written as 32 contiguous bytes of grid
+// row (i, j).
+__global__ __launch_bounds__(256) void permute_out2_lines_kernel(const float *__restrict__ Sa, const float *__restrict__ Sb,
+                                                                 int n, int64_t nlines, float scale,
+                                                                 const uint8_t *__restrict__ want, float *__restrict__ S) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nlines) return;
+    const uint32_t leaf = (uint32_t)(t >> 6);
+    const int line = (int)(t & 63);
+    int lx, ly, lz;
+    morton_decode(leaf, lx, ly, lz);
+    const int i = (lx << 3) | (line >> 3), j = (ly << 3) | (line & 7);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    if (!want || want[leaf]) {
+        const float4 a0 = ((const float4 *)Sa)[2 * t], a1 = ((const float4 *)Sa)[2 * t + 1];
+        const float4 b0 = ((const float4 *)Sb)[2 * t], b1 = ((const float4 *)Sb)[2 * t + 1];
+        a = make_float4((a0.x + b0.x) * scale, (a0.y + b0.y) * scale, (a0.z + b0.z) * scale, (a0.w + b0.w) * scale);
+        b = make_float4((a1.x + b1.x) * scale, (a1.y + b1.y) * scale, (a1.z + b1.z) * scale, (a1.w + b1.w) * scale);
+    }
+    float4 *dst = (float4 *)(S + ((int64_t)i * n + j) * n + (lz << 3));
+    dst[0] = a;
+    dst[1] = b;
+}
+
 __global__ void perm_to_i64_kernel(const int32_t *perm, int64_t N, int64_t *out) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
@@ -102,6 +156,13 @@ int launch_morton_scatter(const Tree &t, hipStream_t st) {
 
 template <typename T>
 int launch_permute_in(const Tree &t, const T *I, T scale, T *q, hipStream_t st) {
+    if (sizeof(T) == 4 && t.ell == 8 && t.n % 32 == 0 && (uintptr_t)I % 16 == 0) {   // whole 128-byte rows
+        const int64_t nrows = t.N / 32;
+        hipLaunchKernelGGL(permute_in_rows_kernel, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
+                           (const float *)I, t.n, nrows, (float)scale, (float *)q);
+        KIFMM_HIP(hipGetLastError());
+        return KIFMM_OK;
+    }
     hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.n, lg_of(t.ell),
                        t.N, scale, q);
     KIFMM_HIP(hipGetLastError());
@@ -119,6 +180,13 @@ int launch_permute_out(const Tree &t, const T *Sp, T scale, const uint8_t *want,
 template <typename T>
 int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, const uint8_t *want, T *S,
                         hipStream_t st) {
+    if (sizeof(T) == 4 && t.ell == 8 && (uintptr_t)S % 16 == 0) {   // whole 8-cell lines
+        const int64_t nlines = t.N / 8;
+        hipLaunchKernelGGL(permute_out2_lines_kernel, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st,
+                           (const float *)Sa, (const float *)Sb, t.n, nlines, (float)scale, want, (float *)S);
+        KIFMM_HIP(hipGetLastError());
+        return KIFMM_OK;
+    }
     hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.n,
                        lg_of(t.ell), t.N, scale, want, S);
     KIFMM_HIP(hipGetLastError());
