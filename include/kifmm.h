@@ -190,14 +190,16 @@ int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask);
 /* FFT form of M2L (Section 3 remark: the translation between equivalent and check
  * points on regular grids is a convolution).  Operators built with
  * KIFMM_LAYOUT_LATTICE hold, per level, the spectra of the kernel on the
- * (2 m0 - 1)^3 cyclic grid for the 316 offsets and the maps from coefficients to
- * the half spectra of the equivalent densities and from check-potential spectra
- * back to coefficients.  With enable != 0 (the default for that layout), the M2L
- * of FP32 and KIFMM_BF16X3 evaluations runs as: spectra of every box's density
- * (FP32 MFMA GEMM), a pointwise complex multiply-add over each box's interaction
- * list, then coefficients from the summed spectra (FP32 MFMA GEMM).  It computes
- * the same sum as the dense M2L of the same layout up to FP32 rounding; enable = 0
- * selects the dense M2L (other precisions always use it).  Returns 0,
+ * (2 m0 - 1)^3 cyclic grid for the 316 offsets and the maps between coefficients
+ * and lattice values (W_u, U_d^T).  With enable != 0 (the default for that layout),
+ * the M2L of FP32 and KIFMM_BF16X3 evaluations runs as: equivalent densities on the
+ * lattice (FP32 MFMA GEMM), their half spectra (separable DFT), per frequency the
+ * products with the kernel spectra over each box's interaction list (grouped by
+ * parents into one 16 x 432 real matrix per frequency: FP32 MFMA, or split bfloat16
+ * MFMA for KIFMM_BF16X3), check potentials on the lattice (separable inverse DFT)
+ * and coefficients (FP32 MFMA GEMM).  FP32 computes the same sum as the dense M2L of
+ * the same layout up to FP32 rounding; enable = 0 selects the dense M2L (other
+ * precisions always use it).  Returns 0,
  * KIFMM_EINVAL (ops NULL) or KIFMM_EUNSUPPORTED (another layout). */
 int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 

@@ -52,6 +52,7 @@ int launch_cast_pad_lo(const double *, int, int, int64_t, __bf16 *, int, int, in
 int run_m2l_hadamard(const float *, const float *, const int *, const int *, int, int, int, const uint8_t *,
                      const uint8_t *, float *, hipStream_t);
 int run_m2l_pair_mfma(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
+int run_m2l_pair_bf16x3(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
 int run_m2l_lattice(int, int, const float *, int64_t, int, int, const uint8_t *, float *, hipStream_t);
 int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, const uint8_t *, float *, float *,
                        float *, hipStream_t);
@@ -196,6 +197,7 @@ struct kifmm_ops_s {
     std::vector<float *> fft_g, lat_w, lat_u;
     float *lat_buf = nullptr, *lat_buf_c = nullptr, *spec_e_c = nullptr, *spec_p_c = nullptr;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
+    std::vector<float *> fft_pair_bf;   // the same as split BF16 fragments [nfp][14][64][16] (KIFMM_BF16X3)
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
     // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
     // [nleaf][1920] complex, and the sums after the first inverse stage [nleaf][120][8]
@@ -293,7 +295,7 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
-    for (auto *v : {&o->fft_g, &o->lat_w, &o->lat_u, &o->fft_pair})
+    for (auto *v : {&o->fft_g, &o->lat_w, &o->lat_u, &o->fft_pair, &o->fft_pair_bf})
         for (float *p : *v)
             if (p) (void)hipFree(p);
     for (double *p : o->cd)
@@ -740,6 +742,7 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
     o->lat_w.assign(D + 1, nullptr);
     o->lat_u.assign(D + 1, nullptr);
     o->fft_pair.assign(D + 1, nullptr);
+    o->fft_pair_bf.assign(D + 1, nullptr);
     // offset -> index into the 316 offsets, for the parent-pair matrices
     std::vector<int> oidx(343, -1);
     for (int t = 0; t < n316; ++t)
@@ -767,24 +770,64 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             std::vector<double> gh((size_t)n316 * 2 * nf);
             KIFMM_HIP(hipMemcpyAsync(gh.data(), tmp, gh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
             KIFMM_HIP(hipStreamSynchronize(st));
+            // entry (row, k) of frequency f's matrix; offset index t = -1 where the two children
+            // are adjacent (no M2L term)
+            auto offset_of = [&](int row, int k) {
+                const int ct = row >> 1, d = k / 16, cs = (k / 2) % 8;
+                const int ov[3] = {2 * (d / 9 - 1) + ((cs >> 2) & 1) - ((ct >> 2) & 1),
+                                   2 * ((d / 3) % 3 - 1) + ((cs >> 1) & 1) - ((ct >> 1) & 1),
+                                   2 * (d % 3 - 1) + (cs & 1) - (ct & 1)};
+                return oidx[((ov[0] + 3) * 7 + (ov[1] + 3)) * 7 + (ov[2] + 3)];
+            };
+            auto entry = [&](int t, int f, int row, int k) {
+                const double gr = gh[(size_t)t * 2 * nf + 2 * f], gi = gh[(size_t)t * 2 * nf + 2 * f + 1];
+                return (row & 1) == 0 ? ((k & 1) == 0 ? gr : -gi) : ((k & 1) == 0 ? gi : gr);
+            };
             std::vector<float> am((size_t)nfp * 108 * 64, 0.f);
             for (int ks = 0; ks < 108; ++ks)
                 for (int ln = 0; ln < 64; ++ln) {
-                    const int row = ln & 15, ct = row >> 1, rt = row & 1;
-                    const int k = 4 * ks + (ln >> 4), d = k / 16, cs = (k / 2) % 8, rs = k & 1;
-                    const int ov[3] = {2 * (d / 9 - 1) + ((cs >> 2) & 1) - ((ct >> 2) & 1),
-                                       2 * ((d / 3) % 3 - 1) + ((cs >> 1) & 1) - ((ct >> 1) & 1),
-                                       2 * (d % 3 - 1) + (cs & 1) - (ct & 1)};
-                    const int t = oidx[((ov[0] + 3) * 7 + (ov[1] + 3)) * 7 + (ov[2] + 3)];
-                    if (t < 0) continue;   // adjacent children: no M2L term
-                    for (int f = 0; f < nf; ++f) {
-                        const double gr = gh[(size_t)t * 2 * nf + 2 * f], gi = gh[(size_t)t * 2 * nf + 2 * f + 1];
-                        am[((size_t)f * 108 + ks) * 64 + ln] = (float)(rt == 0 ? (rs == 0 ? gr : -gi) : (rs == 0 ? gi : gr));
-                    }
+                    const int row = ln & 15, k = 4 * ks + (ln >> 4), t = offset_of(row, k);
+                    if (t < 0) continue;
+                    for (int f = 0; f < nf; ++f) am[((size_t)f * 108 + ks) * 64 + ln] = (float)entry(t, f, row, k);
                 }
             KIFMM_TRY(dmalloc(&o->fft_pair[l], am.size()));
             KIFMM_HIP(hipMemcpyAsync(o->fft_pair[l], am.data(), am.size() * sizeof(float), hipMemcpyHostToDevice, st));
             KIFMM_HIP(hipStreamSynchronize(st));   // am is a host vector of this iteration
+            // The same matrices split into BF16 high and low parts (v = hi + lo, both rounded
+            // to nearest even) as fragments of v_mfma_f32_16x16x32_bf16, K padded to 448:
+            // [f][k-step (14)][lane][hi 8, lo 8], lane l holding (row l % 16, k = 32 k-step +
+            // 8 (l / 16) + 0..7).
+            auto bf16_bits = [](float v) {
+                uint32_t u;
+                std::memcpy(&u, &v, 4);
+                u += 0x7fffu + ((u >> 16) & 1u);
+                return (uint16_t)(u >> 16);
+            };
+            auto bf16_value = [](uint16_t b) {
+                const uint32_t u = (uint32_t)b << 16;
+                float v;
+                std::memcpy(&v, &u, 4);
+                return v;
+            };
+            std::vector<uint16_t> ab((size_t)nfp * 14 * 64 * 16, 0);
+            for (int ks = 0; ks < 14; ++ks)
+                for (int ln = 0; ln < 64; ++ln)
+                    for (int j = 0; j < 8; ++j) {
+                        const int row = ln & 15, k = 32 * ks + 8 * (ln >> 4) + j;
+                        if (k >= 432) continue;
+                        const int t = offset_of(row, k);
+                        if (t < 0) continue;
+                        for (int f = 0; f < nf; ++f) {
+                            const double v = entry(t, f, row, k);
+                            const uint16_t hi = bf16_bits((float)v), lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+                            const size_t at = (((size_t)f * 14 + ks) * 64 + ln) * 16 + j;
+                            ab[at] = hi;
+                            ab[at + 8] = lo;
+                        }
+                    }
+            KIFMM_TRY(dmalloc(&o->fft_pair_bf[l], ab.size() / 2));   // counted in floats
+            KIFMM_HIP(hipMemcpyAsync(o->fft_pair_bf[l], ab.data(), ab.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+            KIFMM_HIP(hipStreamSynchronize(st));
         }
         const Factor &u = fu[l - 2], &dn = fd[l - 2];
         KIFMM_TRY(dmalloc(&o->lat_w[l], (size_t)o->lrow * KU));
@@ -1152,7 +1195,9 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             pf.in_nz = nz_of(o, l);
             KIFMM_TRY(run(pf, st));
             KIFMM_TRY(run_m2l_lattice(0, o->opts.m0, lat, nbx, o->nfp, lr, nz_of(o, l), se, st));
-            if (o->fft_pair[l])
+            if (o->fft_pair[l] && precision == KIFMM_BF16X3)
+                KIFMM_TRY(run_m2l_pair_bf16x3(se, o->fft_pair_bf[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
+            else if (o->fft_pair[l])
                 KIFMM_TRY(run_m2l_pair_mfma(se, o->fft_pair[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
             else
                 KIFMM_TRY(run_m2l_hadamard(se, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev, o->t_m2l.ntaps, 1 << l,

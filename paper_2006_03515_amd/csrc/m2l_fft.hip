@@ -28,6 +28,8 @@
 //                        v_mfma_f32_16x16x4f32, operator fragments read from a table laid out
 //                        per frequency as [108 k-steps][64 lanes].  Levels with at least 4
 //                        parents per axis.
+//   m2l_pair_bf16x3_kernel the same in split BF16 on v_mfma_f32_16x16x32_bf16 (precision
+//                        KIFMM_BF16X3).
 //   m2l_hadamard_kernel  (levels with fewer parents) one workgroup per aligned 4^3 block
 //                        of target boxes (64 consecutive Morton indices) and 16
 //                        frequencies, on the FP32 VALU.  The block's
@@ -185,6 +187,120 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     __syncthreads();
     // D layout of 16x16x4: lane holds rows 4 g + v of column lane % 16; row = 2 c_t + re/im
     float *Os = Es;   // [parent][c_t][f][re/im] = the 512 target boxes' 4 frequencies, in order
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int n = 16 * nb + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * g + v;
+            Os[((n * 8 + (row >> 1)) * PF + w) * 2 + (row & 1)] = acc[nb][v];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 512 * 2; e += 256) {
+        const int bl = e >> 1, half = e & 1;
+        ((float4 *)(P + (512 * pt + bl) * nfp + f0))[half] = ((const float4 *)Os)[bl * 2 + half];
+    }
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 value -> BF16 high part (round to nearest even) and the BF16 of what remains
+__device__ __forceinline__ void split_bf16(float v, uint16_t &hi, uint16_t &lo) {
+    uint32_t u = __float_as_uint(v);
+    const uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    hi = (uint16_t)(h >> 16);
+    const float r = v - __uint_as_float(h);
+    const uint32_t ur = __float_as_uint(r);
+    lo = (uint16_t)((ur + 0x7fffu + ((ur >> 16) & 1u)) >> 16);
+}
+
+// The parent-pair products in split BF16 (A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32
+// accumulation, about 16 mantissa bits) on v_mfma_f32_16x16x32_bf16: the same workgroup
+// shape as m2l_pair_mfma_kernel, spectra staged as BF16 pairs [f][region parent][c_s][re/im]
+// (16 values per parent, hi and lo planes), K = 432 padded to 448 (14 k-steps).  Lane group
+// g = lane / 16 of k-step ks reads the 8 values of source parent d = 2 ks + g / 2, children
+// 4 (g % 2) .. + 3.
+__global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__restrict__ E, const uint16_t *__restrict__ Ab,
+                                                              int nl, int nfp, const uint8_t *__restrict__ out_need,
+                                                              const uint8_t *__restrict__ in_nz,
+                                                              float2 *__restrict__ P) {
+    __shared__ __align__(16) uint16_t Eh[PF * 216 * 16], El[PF * 216 * 16];
+    __shared__ int any_wanted;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int np = nl / 2;
+    const int64_t pt = blockIdx.x;
+    const int f0 = blockIdx.y * PF;
+    if (out_need) {
+        if (tid == 0) any_wanted = 0;
+        __syncthreads();
+        if (out_need[512 * pt + tid] || out_need[512 * pt + 256 + tid]) any_wanted = 1;
+        __syncthreads();
+        if (!any_wanted) return;
+    }
+    int ox, oy, oz;
+    morton_decode((uint32_t)pt, ox, oy, oz);
+    ox = 4 * ox - 1;
+    oy = 4 * oy - 1;
+    oz = 4 * oz - 1;
+    for (int e = tid; e < 216 * 8; e += 256) {
+        const int q = e >> 3, c = e & 7;
+        const int x = ox + q / 36, y = oy + (q / 6) % 6, z = oz + q % 6;
+        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+        if (x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
+            const int64_t box = 8 * (int64_t)morton_encode(x, y, z) + c;
+            if (!in_nz || in_nz[box]) {
+                const float4 *src = (const float4 *)(E + box * nfp + f0);
+                v0 = src[0];
+                v1 = src[1];
+            }
+        }
+        const float vals[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};   // (f, re/im)
+#pragma unroll
+        for (int f = 0; f < PF; ++f) {
+            uint16_t hr, lr, hi, li;
+            split_bf16(vals[2 * f], hr, lr);
+            split_bf16(vals[2 * f + 1], hi, li);
+            const int at = ((f * 216 + q) * 16 + 2 * c) >> 1;   // a (re, im) pair as one 32-bit word
+            ((uint32_t *)Eh)[at] = (uint32_t)hr | ((uint32_t)hi << 16);
+            ((uint32_t *)El)[at] = (uint32_t)lr | ((uint32_t)li << 16);
+        }
+    }
+    __syncthreads();
+    const int g = lane >> 4;
+    int qn[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        int a, b, c;
+        morton_decode((uint32_t)(16 * nb + (lane & 15)), a, b, c);
+        qn[nb] = ((a + 1) * 6 + (b + 1)) * 6 + (c + 1);
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint4 *Af = (const uint4 *)(Ab + ((int64_t)(f0 + w) * 14 * 64 + lane) * 16);
+    const uint16_t *Ehw = Eh + w * 216 * 16 + 8 * (g & 1), *Elw = El + w * 216 * 16 + 8 * (g & 1);
+#pragma unroll 2
+    for (int ks = 0; ks < 14; ++ks) {
+        const int d = min(2 * ks + (g >> 1), 26);   // d = 27 (padding) has zero operator entries
+        const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
+        const uint4 ah = Af[ks * 64 * 2], al = Af[ks * 64 * 2 + 1];
+        bf16x8 a_hi, a_lo;
+        __builtin_memcpy(&a_hi, &ah, 16);
+        __builtin_memcpy(&a_lo, &al, 16);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int q = qn[nb] + dq;
+            bf16x8 b_hi, b_lo;
+            __builtin_memcpy(&b_hi, Ehw + q * 16, 16);
+            __builtin_memcpy(&b_lo, Elw + q * 16, 16);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi, acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo, acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi, acc[nb], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    float *Os = (float *)Eh;   // [parent][c_t][f][re/im]: 512 boxes x PF frequencies (16 KB)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         const int n = 16 * nb + (lane & 15);
@@ -434,6 +550,18 @@ int run_m2l_lattice(int dir, int m0, const float *in, int64_t nbx, int nfp, int 
     case 8: return launch_lattice<8>(dir, in, nbx, nfp, row, flags, out, st);
     default: return fail(KIFMM_EINVAL, "lattice transform: m0 must lie in [3, 8]");
     }
+}
+
+int run_m2l_pair_bf16x3(const float *E, const float *Ab, int nl, int nfp, const uint8_t *out_need,
+                        const uint8_t *in_nz, float *P, hipStream_t st) {
+    if (nl < 8 || (nl & (nl - 1)) != 0) return fail(KIFMM_EINVAL, "M2L spectra: boxes per axis must be 8, 16, ...");
+    if (nfp % PF != 0) return fail(KIFMM_EINVAL, "M2L spectra: frequency count not a multiple of 4");
+    if (!Ab) return fail(KIFMM_EINVAL, "M2L spectra: no split-BF16 operator fragments");
+    const int64_t ntile = (int64_t)nl * nl * nl / 512;
+    hipLaunchKernelGGL(m2l_pair_bf16x3_kernel, dim3((unsigned)ntile, (unsigned)(nfp / PF)), dim3(256), 0, st,
+                       (const float2 *)E, (const uint16_t *)Ab, nl, nfp, out_need, in_nz, (float2 *)P);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
 }
 
 int run_m2l_pair_mfma(const float *E, const float *Am, int nl, int nfp, const uint8_t *out_need,
