@@ -254,12 +254,12 @@ def main():
     nb, s = tree.grid.n[0] // tree.leaf_side, tree.leaf_side ** 3
     p2p_flops = 2.0 * near_pairs(nb, s)
     if m2l_form == "fft":
-        # FFT form: coefficients -> half spectra and back (two GEMMs per box), plus one
-        # complex multiply-add (8 flops) per interaction pair and frequency (all three on
+        # FFT form: coefficients -> lattice values and back (two GEMMs per box, m0^3 x rank),
+        # plus one complex multiply-add (8 flops) per interaction pair and frequency (all on
         # MFMA at levels >= 3; the parent-pair products also multiply the zero entries of
-        # adjacent children, which are not counted)
+        # adjacent children, and the separable transforms run on the VALU: neither counted)
         nf = (2 * args.m0 - 1) ** 2 * args.m0
-        m2l_flops = sum(2.0 * 8 ** l * 2 * nf * (ranks[l][0] + ranks[l][1]) + 8.0 * m2l_pairs(l) * nf
+        m2l_flops = sum(2.0 * 8 ** l * args.m0 ** 3 * (ranks[l][0] + ranks[l][1]) + 8.0 * m2l_pairs(l) * nf
                         for l in ranks)
     else:
         m2l_flops = sum(2.0 * m2l_pairs(l) * ranks[l][0] * ranks[l][1] for l in ranks)
