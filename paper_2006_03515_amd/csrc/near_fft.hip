@@ -137,12 +137,13 @@ constexpr int NCH = 4;   // frequency chunks per products workgroup
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void near_products_kernel(const float2 *__restrict__ Q, const float2 *__restrict__ Gh,
+__global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__restrict__ Q, const float2 *__restrict__ Gh,
                                                             int nb, const uint8_t *__restrict__ out_need,
                                                             const uint8_t *__restrict__ in_nz, float2 *__restrict__ P) {
-    __shared__ float2 Es[216 * 16];   // [region leaf][kx]
+    // Es: [region leaf][kx]; after the products of a chunk it holds their sums,
+    // [target][kx] (padded rows of 17, 64 x 17)
+    __shared__ float2 Es[216 * 16];
     __shared__ float2 Gs[27 * 16];    // [offset][kx]
-    __shared__ float2 Ps[64 * 17];    // [target][kx] sums of one chunk (padded row)
     const int tid = threadIdx.x, lane = tid & 63;
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
@@ -229,8 +230,9 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
                     ai[s] = fmaf(g[oz].x, v.y, fmaf(g[oz].y, v.x, ai[s]));
                 }
         }
+        __syncthreads();   // every wave is done with Es before Ps overwrites it
 #pragma unroll
-        for (int s = 0; s < 4; ++s) Ps[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
+        for (int s = 0; s < 4; ++s) Es[tl[s] * 17 + f] = make_float2(ar[s], ai[s]);
         __syncthreads();
         // first inverse stage, over kx, at the 8 cells x of each target: this chunk holds all
         // 15 kx of one (ky, kz) = c, so U[leaf][c][x] = sum_kx P e^{+2 pi i kx x / 15}.  Wave
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) void near_products_kernel(const float2 *__rest
         // 4 results (n = 4 (lane / 16) + v) are x = 2 (lane / 16), + 1, re and im.
         {
             const int w = tid >> 6, t = 16 * w + n16;
-            const float *pt = (const float *)(Ps + t * 17);
+            const float *pt = (const float *)(Es + t * 17);
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks)
