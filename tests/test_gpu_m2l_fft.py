@@ -86,6 +86,10 @@ def test_fft_m2l_deep_tree_random_sources(K):
     assert rel_l2(a, ora) < 2e-6
     ref = odirect.fft_full(I, (L / n,) * 3, p_o2)
     assert rel_l2(a, ref) < 1e-4
+    # split-BF16 parent-pair products (levels 3 and 4): about 16 mantissa bits per operand
+    c = run(K, tree, ops, I, "bf16x3", True)
+    assert rel_l2(c, ora) < 1e-5
+    assert rel_l2(c, a) < 1e-5
 
 
 def test_fft_m2l_with_skipping_and_restriction(K):
