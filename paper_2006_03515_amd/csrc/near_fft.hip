@@ -91,45 +91,54 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
 #pragma unroll
         for (int y = 0; y < 8; ++y) v[y] = Wb[kz * 64 + x * 8 + y];
         wave_sync();   // Y overwrites Z
+        float2 s0 = make_float2(0.f, 0.f);   // ky = 0
 #pragma unroll
-        for (int ky = 0; ky < 15; ++ky) {
-            float re = 0.f, im = 0.f;
+        for (int y = 0; y < 8; ++y) s0 = make_float2(s0.x + v[y].x, s0.y + v[y].y);
+        Wb[x * NCOL + kz] = s0;
+        // ky and 15 - ky from the same four sums: with theta = 2 pi ky y / 15,
+        // out(ky) = sum v e^{-i theta}, out(15 - ky) = sum v e^{+i theta}
+#pragma unroll
+        for (int ky = 1; ky < 8; ++ky) {
+            float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
 #pragma unroll
             for (int y = 0; y < 8; ++y) {
-                const float c = kC15[(ky * y) % 15], sv = kS15[(ky * y) % 15];
-                re = fmaf(v[y].x, c, fmaf(v[y].y, sv, re));
-                im = fmaf(v[y].y, c, fmaf(-v[y].x, sv, im));
+                const float cv = kC15[(ky * y) % 15], sv = kS15[(ky * y) % 15];
+                a = fmaf(v[y].x, cv, a);
+                b = fmaf(v[y].y, sv, b);
+                c = fmaf(v[y].y, cv, c);
+                d = fmaf(v[y].x, sv, d);
             }
-            Wb[x * NCOL + ky * 8 + kz] = make_float2(re, im);
+            Wb[x * NCOL + ky * 8 + kz] = make_float2(a + b, c - d);
+            Wb[x * NCOL + (15 - ky) * 8 + kz] = make_float2(a - b, c + d);
         }
     }
     wave_sync();
-    // x: lane = (column of a group of 8, slot pair kp): the slots 2 kp, 2 kp + 1 of the
-    // column, so one store of the wave writes 8 whole columns (1 KB, contiguous)
+    // x: lane = (column of a group of 8, kp): the slots kp and 15 - kp of the column from the
+    // same four sums (kp = 0: kx = 0 and the zero slot 15); the wave's two stores cover 8
+    // whole columns (1 KB)
     const int kp = lane & 7;
-    float c0[8], s0[8], c1[8], s1[8];   // twiddles of kx = 2 kp and 2 kp + 1 (15: slot kept 0)
+    float cw[8], sw[8];   // twiddles of kx = kp
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
-        const int m0 = (2 * kp * x) % 15, m1 = ((2 * kp + 1) * x) % 15;
-        c0[x] = kCos15[m0];
-        s0[x] = kSin15[m0];
-        c1[x] = kp == 7 ? 0.f : kCos15[m1];
-        s1[x] = kp == 7 ? 0.f : kSin15[m1];
+        const int m = (kp * x) % 15;
+        cw[x] = kCos15[m];
+        sw[x] = kSin15[m];
     }
-    float4 *dst = (float4 *)(Q + leaf * NF) + lane;
+    float2 *dst = Q + leaf * NF + kp;
 #pragma unroll 3
     for (int g = 0; g < NCOL / 8; ++g) {
         const int r = 8 * g + (lane >> 3);   // column ky * 8 + kz
-        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
             const float2 v = Wb[x * NCOL + r];
-            o.x = fmaf(v.x, c0[x], fmaf(v.y, s0[x], o.x));
-            o.y = fmaf(v.y, c0[x], fmaf(-v.x, s0[x], o.y));
-            o.z = fmaf(v.x, c1[x], fmaf(v.y, s1[x], o.z));
-            o.w = fmaf(v.y, c1[x], fmaf(-v.x, s1[x], o.w));
+            a = fmaf(v.x, cw[x], a);
+            b = fmaf(v.y, sw[x], b);
+            c = fmaf(v.y, cw[x], c);
+            d = fmaf(v.x, sw[x], d);
         }
-        dst[64 * g] = o;
+        dst[r * 16] = make_float2(a + b, c - d);
+        dst[r * 16 + 15 - 2 * kp] = kp == 0 ? make_float2(0.f, 0.f) : make_float2(a - b, c + d);
     }
 }
 
@@ -268,14 +277,22 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
         float2 u[15];
 #pragma unroll
         for (int ky = 0; ky < 15; ++ky) u[ky] = U[leaf * NCOL * 8 + ky * 64 + lane];   // [ky * 8 + kz][x]
+        // ky and 15 - ky together: u(ky) e^{+i theta} + u(15 - ky) e^{-i theta}
+        //   = (u(ky) + u(15 - ky)) cos theta + i (u(ky) - u(15 - ky)) sin theta
+        float2 pk[8], mk[8];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            pk[k] = make_float2(u[k].x + u[15 - k].x, u[k].y + u[15 - k].y);
+            mk[k] = make_float2(u[k].x - u[15 - k].x, u[k].y - u[15 - k].y);
+        }
 #pragma unroll
         for (int y = 0; y < 8; ++y) {
-            float re = 0.f, im = 0.f;
+            float re = u[0].x, im = u[0].y;
 #pragma unroll
-            for (int ky = 0; ky < 15; ++ky) {
-                const float c = kC15[(ky * y) % 15], sv = kS15[(ky * y) % 15];
-                re = fmaf(u[ky].x, c, fmaf(-u[ky].y, sv, re));
-                im = fmaf(u[ky].y, c, fmaf(u[ky].x, sv, im));
+            for (int k = 1; k < 8; ++k) {
+                const float c = kC15[(k * y) % 15], sv = kS15[(k * y) % 15];
+                re = fmaf(pk[k].x, c, fmaf(-mk[k].y, sv, re));
+                im = fmaf(pk[k].y, c, fmaf(mk[k].x, sv, im));
             }
             Vb[(x * 8 + y) * 8 + kz] = make_float2(re, im);
         }
