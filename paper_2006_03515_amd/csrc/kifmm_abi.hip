@@ -796,7 +796,8 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             // The same matrices split into BF16 high and low parts (v = hi + lo, both rounded
             // to nearest even) as fragments of v_mfma_f32_16x16x32_bf16, K padded to 448:
             // [f][k-step (14)][lane][hi 8, lo 8], lane l holding (row l % 16, k = 32 k-step +
-            // 8 (l / 16) + 0..7).
+            // 8 (l / 16) + 0..7), source parents in the k order with 13 and 26 swapped (the
+            // last k-step is then zero and is not read).
             auto bf16_bits = [](float v) {
                 uint32_t u;
                 std::memcpy(&u, &v, 4);
@@ -813,12 +814,14 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             for (int ks = 0; ks < 14; ++ks)
                 for (int ln = 0; ln < 64; ++ln)
                     for (int j = 0; j < 8; ++j) {
-                        const int row = ln & 15, k = 32 * ks + 8 * (ln >> 4) + j;
-                        if (k >= 432) continue;
-                        const int t = offset_of(row, k);
+                        // position q = k / 16 holds source parent d = q with 13 and 26 swapped
+                        const int row = ln & 15, k = 32 * ks + 8 * (ln >> 4) + j, q = k / 16;
+                        if (q >= 27) continue;
+                        const int kd = 16 * (q == 13 ? 26 : (q == 26 ? 13 : q)) + k % 16;
+                        const int t = offset_of(row, kd);
                         if (t < 0) continue;
                         for (int f = 0; f < nf; ++f) {
-                            const double v = entry(t, f, row, k);
+                            const double v = entry(t, f, row, kd);
                             const uint16_t hi = bf16_bits((float)v), lo = bf16_bits((float)(v - (double)bf16_value(hi)));
                             const size_t at = (((size_t)f * 14 + ks) * 64 + ln) * 16 + j;
                             ab[at] = hi;

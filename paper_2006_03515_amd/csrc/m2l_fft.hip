@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     const float *Af = Am + (int64_t)(f0 + w) * 108 * 64 + lane;
     const float *Ew = Es + w * 16 * 216 + g * 216;
     for (int d = 0; d < 27; ++d) {   // source parent p + (dx, dy, dz), d = 9 (dx+1) + 3 (dy+1) + dz+1
+        if (d == 13) continue;   // the target's own parent: all its children are adjacent (zeros)
         const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
         float a4[4];
 #pragma unroll
@@ -219,8 +220,8 @@ __device__ __forceinline__ void split_bf16(float v, uint16_t &hi, uint16_t &lo) 
 // accumulation, about 16 mantissa bits) on v_mfma_f32_16x16x32_bf16: the same workgroup
 // shape as m2l_pair_mfma_kernel, spectra staged as BF16 pairs [f][region parent][c_s][re/im]
 // (16 values per parent, hi and lo planes), K = 432 padded to 448 (14 k-steps).  Lane group
-// g = lane / 16 of k-step ks reads the 8 values of source parent d = 2 ks + g / 2, children
-// 4 (g % 2) .. + 3.
+// g = lane / 16 of k-step ks reads the 8 values of the source parent at position 2 ks + g / 2
+// (13 and 26 swapped), children 4 (g % 2) .. + 3.
 __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__restrict__ E, const uint16_t *__restrict__ Ab,
                                                               int nl, int nfp, const uint8_t *__restrict__ out_need,
                                                               const uint8_t *__restrict__ in_nz,
@@ -281,8 +282,11 @@ __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__re
     const uint4 *Af = (const uint4 *)(Ab + ((int64_t)(f0 + w) * 14 * 64 + lane) * 16);
     const uint16_t *Ehw = Eh + w * 216 * 16 + 8 * (g & 1), *Elw = El + w * 216 * 16 + 8 * (g & 1);
 #pragma unroll 2
-    for (int ks = 0; ks < 14; ++ks) {
-        const int d = min(2 * ks + (g >> 1), 26);   // d = 27 (padding) has zero operator entries
+    // k order: position q = 2 ks + g / 2 holds source parent d = q with 13 and 26 swapped, so
+    // the last k-step (d = 13, the target's own parent, whose children are all adjacent, and
+    // the padding) is all zeros and is skipped
+    for (int ks = 0; ks < 13; ++ks) {
+        const int q = 2 * ks + (g >> 1), d = q == 13 ? 26 : (q == 26 ? 13 : q);
         const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
         const uint4 ah = Af[ks * 64 * 2], al = Af[ks * 64 * 2 + 1];
         bf16x8 a_hi, a_lo;
