@@ -190,8 +190,9 @@ struct kifmm_ops_s {
     // lattice (lat_w[l] = W_u, lrow x KU, rows past m0^3 zero) and lattice check potentials
     // -> downward coefficients (lat_u[l] = U_d^T, KD x lrow), lrow = m0^3 padded to 32,
     // mf = 2 nfp; lattice values of the finest level (lat_buf: boxes of level D x lrow) and
-    // its spectra (spec_e, spec_p: boxes of level D x mf), and the same for the coarser
-    // levels (the _c buffers, boxes of level D - 1), which run at the same time
+    // its spectra (spec_e, spec_p: boxes of level D x mf), and the same for each coarser
+    // level (the _c buffers: levels 2 .. D - 1 one after the other, (8^l - 64) / 7 boxes
+    // before level l), since levels run at the same time on different streams
     bool m2l_fft = false;
     int nfp = 0, mf = 0, lrow = 0;
     std::vector<float *> fft_g, lat_w, lat_u;
@@ -220,6 +221,8 @@ struct kifmm_ops_s {
     hipStream_t side = nullptr, fine = nullptr;
     rocblas_handle blas = nullptr;   // FP32 P2M and L2P over all leaves (plain GEMMs)
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
+    // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
+    std::vector<hipEvent_t> ev_up, ev_m2l;
     // per-pass timing (kifmm_profile_enable)
     bool prof = false;
     std::vector<hipEvent_t> ev;        // pool of events, recorded in pairs
@@ -305,6 +308,9 @@ static void free_ops(kifmm_ops o) {
     if (o->side) (void)hipStreamDestroy(o->side);
     if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
     if (o->join_fine) (void)hipEventDestroy(o->join_fine);
+    for (auto *v : {&o->ev_up, &o->ev_m2l})
+        for (hipEvent_t e : *v)
+            if (e) (void)hipEventDestroy(e);
     if (o->fine) (void)hipStreamDestroy(o->fine);
     if (o->blas) (void)rocblas_destroy_handle(o->blas);
     delete o;
@@ -844,9 +850,10 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
     KIFMM_TRY(dmalloc(&o->spec_p, nbx * mf));
     KIFMM_TRY(dmalloc(&o->lat_buf, nbx * o->lrow));
     if (D >= 3) {
-        KIFMM_TRY(dmalloc(&o->spec_e_c, nbx / 8 * mf));
-        KIFMM_TRY(dmalloc(&o->spec_p_c, nbx / 8 * mf));
-        KIFMM_TRY(dmalloc(&o->lat_buf_c, nbx / 8 * o->lrow));
+        const size_t ncoarse = (nbx / 8 * 8 - 64) / 7;   // boxes of levels 2 .. D - 1
+        KIFMM_TRY(dmalloc(&o->spec_e_c, ncoarse * mf));
+        KIFMM_TRY(dmalloc(&o->spec_p_c, ncoarse * mf));
+        KIFMM_TRY(dmalloc(&o->lat_buf_c, ncoarse * o->lrow));
     }
     o->m2l_fft = true;
     return KIFMM_OK;
@@ -963,6 +970,12 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(dmalloc(&o->amax_q, (size_t)o->n_amax));
     o->cu.assign(D + 1, nullptr);
     o->cd.assign(D + 1, nullptr);
+    o->ev_up.assign(D + 1, nullptr);
+    o->ev_m2l.assign(D + 1, nullptr);
+    for (int l = 3; l < D; ++l) {
+        KIFMM_HIP(hipEventCreateWithFlags(&o->ev_up[l], hipEventDisableTiming));
+        KIFMM_HIP(hipEventCreateWithFlags(&o->ev_m2l[l], hipEventDisableTiming));
+    }
     if (D < 2) {
         KIFMM_HIP(hipStreamSynchronize(st));
         return KIFMM_OK;
@@ -1191,8 +1204,9 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             const int64_t nbx = (int64_t)1 << (3 * l);
             const int lr = o->lrow;
             const bool fine = l == o->D;   // the coarser levels have buffers of their own
-            float *lat = fine ? o->lat_buf : o->lat_buf_c, *se = fine ? o->spec_e : o->spec_e_c,
-                  *sp = fine ? o->spec_p : o->spec_p_c;
+            const size_t off = fine ? 0 : (((size_t)1 << (3 * l)) - 64) / 7;   // boxes of levels 2 .. l - 1
+            float *lat = fine ? o->lat_buf : o->lat_buf_c + off * lr, *se = fine ? o->spec_e : o->spec_e_c + off * o->mf,
+                  *sp = fine ? o->spec_p : o->spec_p_c + off * o->mf;
             auto pf = tap<float, float>(o->lat_w[l], 0, lr, KU, (const float *)o->cu[l], KU, lat, lr, SRC_SAME, 0,
                                         o->t_single, 1, nbx, 0);
             pf.in_nz = nz_of(o, l);
@@ -1426,22 +1440,44 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         }
         KIFMM_HIP(hipEventRecord(o->join_fine, o->fine));
     }
+    // With the near field in Fourier space its stream is free early: the M2L of levels
+    // D - 1 .. 3 then runs there, each as soon as M2M has made that level's coefficients,
+    // into cd[l]; the main stream does level 2 and the L2L chain, each L2L adding to the M2L
+    // sum (the coarse chain of small launches is otherwise the step's longest path).
+    const bool coarse_side = fine_apart && D >= 4 && o->p2p_fft && nb >= 4;
     for (int l = D - 1; l >= 2; --l) {
-        const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
-        PassTimer pt(o, KIFMM_PASS_M2M, st);
-        auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
-                           o->t_m2m, 1, (int64_t)1 << (3 * l), 0);
-        p.in_nz = nz_of(o, l + 1);
-        if constexpr (sizeof(T) == 4) {
-            p.part = o->part;
-            p.part_capacity = o->part_capacity;
+        {
+            const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
+            PassTimer pt(o, KIFMM_PASS_M2M, st);
+            auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
+                               o->t_m2m, 1, (int64_t)1 << (3 * l), 0);
+            p.in_nz = nz_of(o, l + 1);
+            if constexpr (sizeof(T) == 4) {
+                p.part = o->part;
+                p.part_capacity = o->part_capacity;
+            }
+            KIFMM_TRY(run(p, st));
         }
-        KIFMM_TRY(run(p, st));
+        if (coarse_side && l >= 3) KIFMM_HIP(hipEventRecord(o->ev_up[l], st));
+    }
+    if (coarse_side) {   // the events waited for below are all recorded (enqueued) above
+        for (int l = D - 1; l >= 3; --l) {
+            KIFMM_HIP(hipStreamWaitEvent(o->side, o->ev_up[l], 0));
+            {
+                PassTimer pt(o, KIFMM_PASS_M2L, o->side);
+                KIFMM_TRY(m2l_level<T>(o, ops, l, precision, 0, o->side));
+            }
+            KIFMM_HIP(hipEventRecord(o->ev_m2l[l], o->side));
+        }
+        KIFMM_HIP(hipEventRecord(o->join, o->side));
     }
     for (int l = 2; l <= D; ++l) {
-        const bool m2l_done = fine_apart && l == D;   // cd[D] holds the M2L sum already
+        // cd[l] holds the M2L sum already: the finest level (own stream), the coarse levels
+        // 3 .. D - 1 (near-field stream)
+        const bool m2l_done = (fine_apart && l == D) || (coarse_side && l >= 3);
         if (l > 2) {
-            if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
+            if (fine_apart && l == D) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
+            else if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
             const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
