@@ -153,9 +153,11 @@ int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
  * float otherwise, in grid order; they must not overlap.  `ops` must come from
  * `tree` (else KIFMM_EMISMATCH).  Uses the work buffers owned by `ops`, so
  * calls sharing one ops object must be ordered on one stream.  The near field
- * runs on a second stream owned by `ops`, forked from and joined back into
- * `stream` with events; when the call returns, all its work is ordered on
- * `stream`. */
+ * (and, after it, the M2L of the coarse levels when both Fourier forms are on) runs
+ * on a second stream owned by `ops`, and the finest level's FFT-form M2L on a third;
+ * both are forked from and joined back into `stream` with events, so when the call
+ * returns, all its work is ordered on `stream`.  FP32 P2M and L2P call rocBLAS on
+ * `stream` (handle owned by `ops`). */
 int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor,
                void *S_dev, int32_t precision, void *stream);
 

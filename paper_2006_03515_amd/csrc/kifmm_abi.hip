@@ -216,8 +216,9 @@ struct kifmm_ops_s {
     int n_amax = 256;
     float *part = nullptr;             // tap-group partial sums of the M2L launches
     int64_t part_capacity = 0;         // floats
-    // the near field runs on a second stream, joined by events; with the FFT form of M2L
-    // the finest level's M2L runs on a third, beside the upward pass and the coarse levels
+    // the near field runs on a second stream (then, with both Fourier forms, the coarse
+    // levels' M2L), joined by events; with the FFT form of M2L the finest level's M2L runs
+    // on a third, beside the upward pass and the coarse levels
     hipStream_t side = nullptr, fine = nullptr;
     rocblas_handle blas = nullptr;   // FP32 P2M and L2P over all leaves (plain GEMMs)
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
