@@ -197,7 +197,7 @@ struct kifmm_ops_s {
     int nfp = 0, mf = 0, lrow = 0;
     std::vector<float *> fft_g, lat_w, lat_u;
     float *lat_buf = nullptr, *lat_buf_c = nullptr, *spec_e_c = nullptr, *spec_p_c = nullptr;
-    std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][108][64] MFMA fragments
+    std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][27][64][4] MFMA fragments
     std::vector<float *> fft_pair_bf;   // the same as split BF16 fragments [nfp][14][64][16] (KIFMM_BF16X3)
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
     // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
@@ -773,7 +773,8 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
             // Parent-pair form: per frequency the 16 x 432 real matrix taking the spectra of
             // the 8 children of each of the 27 neighbour parents (k = 16 d + 2 c_s + re/im) to
             // the 8 children of the target parent (row = 2 c_t + re/im), laid out as MFMA
-            // fragments [f][k-step][lane]: lane l holds (row l % 16, k = 4 k-step + l / 16).
+            // fragments [f][source parent d][lane][4 k-steps]: k-step 4 d + s of lane l holds
+            // (row l % 16, k = 4 (4 d + s) + l / 16), so a lane loads one parent's 4 in one go.
             std::vector<double> gh((size_t)n316 * 2 * nf);
             KIFMM_HIP(hipMemcpyAsync(gh.data(), tmp, gh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
             KIFMM_HIP(hipStreamSynchronize(st));
@@ -795,7 +796,8 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
                 for (int ln = 0; ln < 64; ++ln) {
                     const int row = ln & 15, k = 4 * ks + (ln >> 4), t = offset_of(row, k);
                     if (t < 0) continue;
-                    for (int f = 0; f < nf; ++f) am[((size_t)f * 108 + ks) * 64 + ln] = (float)entry(t, f, row, k);
+                    for (int f = 0; f < nf; ++f)   // [f][d = ks / 4][lane][ks % 4]
+                        am[(((size_t)f * 27 + ks / 4) * 64 + ln) * 4 + ks % 4] = (float)entry(t, f, row, k);
                 }
             KIFMM_TRY(dmalloc(&o->fft_pair[l], am.size()));
             KIFMM_HIP(hipMemcpyAsync(o->fft_pair[l], am.data(), am.size() * sizeof(float), hipMemcpyHostToDevice, st));

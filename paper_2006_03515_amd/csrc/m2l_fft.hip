@@ -26,7 +26,7 @@
 //                        [parent] so that 16 lanes reading 16 parents hit distinct banks.
 //                        Wave w takes frequency w: 4 column blocks of 16 parents on
 //                        v_mfma_f32_16x16x4f32, operator fragments read from a table laid out
-//                        per frequency as [108 k-steps][64 lanes].  Levels with at least 4
+//                        per frequency as [27 parents][64 lanes][4 k-steps].  Levels with at least 4
 //                        parents per axis.
 //   m2l_pair_bf16x3_kernel the same in split BF16 on v_mfma_f32_16x16x32_bf16 (precision
 //                        KIFMM_BF16X3).
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(512) void m2l_hadamard_kernel(const float2 *__restr
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int PF = 4;   // frequencies per workgroup of the MFMA kernel (one per wave)
 
-// Am[f][ks][lane]: lane l of k-step ks holds entry (row l % 16, k = 4 ks + l / 16) of the
-// 16 x 432 real matrix of frequency f; row = 2 c_t + (re/im), k = 16 d + 2 c_s + (re/im).
+// Am[f][d][lane][s]: lane l of k-step ks = 4 d + s holds entry (row l % 16, k = 4 ks + l / 16)
+// of the 16 x 432 real matrix of frequency f; row = 2 c_t + (re/im), k = 16 d + 2 c_s + (re/im).
 __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__restrict__ E, const float *__restrict__ Am,
                                                             int nl, int nfp, const uint8_t *__restrict__ out_need,
                                                             const uint8_t *__restrict__ in_nz,
@@ -169,14 +169,13 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     floatx4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float *Af = Am + (int64_t)(f0 + w) * 108 * 64 + lane;
+    const float4 *Af = (const float4 *)(Am + (int64_t)(f0 + w) * 108 * 64) + lane;
     const float *Ew = Es + w * 16 * 216 + g * 216;
     for (int d = 0; d < 27; ++d) {   // source parent p + (dx, dy, dz), d = 9 (dx+1) + 3 (dy+1) + dz+1
         if (d == 13) continue;   // the target's own parent: all its children are adjacent (zeros)
         const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
-        float a4[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) a4[s] = Af[(4 * d + s) * 64];
+        const float4 a = Af[d * 64];   // k-steps 4 d .. 4 d + 3
+        const float a4[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {   // k-step 4 d + s: c_s = 2 s + g / 2, re/im = g % 2
             const float *eb = Ew + s * 4 * 216 + dq;
