@@ -221,6 +221,7 @@ struct kifmm_ops_s {
     // on a third, beside the upward pass and the coarse levels
     hipStream_t side = nullptr, fine = nullptr;
     rocblas_handle blas = nullptr;   // FP32 P2M and L2P over all leaves (plain GEMMs)
+    void *blas_ws = nullptr;         // its workspace, sized at precompute (evaluations allocate nothing)
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
     // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
     std::vector<hipEvent_t> ev_up, ev_m2l;
@@ -290,7 +291,7 @@ static void free_ops(kifmm_ops o) {
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
-                    o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
+                    o->blas_ws, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -1514,6 +1515,30 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
 
 extern "C" {
 
+// rocBLAS's workspace for the FP32 P2M and L2P: the two calls are run in rocBLAS's size-query
+// mode (nothing executes), and a buffer of the largest size they ask for is handed to the
+// handle, so that evaluations allocate nothing
+static int blas_reserve(kifmm_ops o, hipStream_t st) {
+    if (!o->blas || o->D < 2 || !o->p2m32 || !o->l2p32) return KIFMM_OK;
+    const int64_t nleaf = (int64_t)o->nb * o->nb * o->nb;
+    if (nleaf > INT32_MAX) return KIFMM_OK;   // evaluations refuse this size anyway
+    const float one = 1.f, zero = 0.f;
+    size_t need = 0;
+    if (rocblas_set_stream(o->blas, st) != rocblas_status_success ||
+        rocblas_start_device_memory_size_query(o->blas) != rocblas_status_success)
+        return fail(KIFMM_EHIP, "rocBLAS workspace query failed to start");
+    (void)rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, o->KU, (int)nleaf, o->s, &one,
+                        o->p2m32, o->s, (const float *)o->q, o->s, &zero, (float *)o->cu[o->D], o->KU);
+    (void)rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, o->s, (int)nleaf, o->KD, &one,
+                        o->l2p32, o->KD, (const float *)o->cd[o->D], o->KD, &zero, (float *)o->Sp, o->s);
+    if (rocblas_stop_device_memory_size_query(o->blas, &need) != rocblas_status_success)
+        return fail(KIFMM_EHIP, "rocBLAS workspace query failed");
+    KIFMM_TRY(dmalloc((char **)&o->blas_ws, need > 256 ? need : 256));
+    if (rocblas_set_workspace(o->blas, o->blas_ws, need > 256 ? need : 256) != rocblas_status_success)
+        return fail(KIFMM_EHIP, "rocblas_set_workspace failed");
+    return KIFMM_OK;
+}
+
 int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, const kifmm_opts *opts,
                                void *stream, kifmm_ops *out) {
     if (!tree || !out) return fail(KIFMM_EINVAL, "tree and out must be non-NULL");
@@ -1541,6 +1566,7 @@ int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, cons
     ops->kern = *kernel;
     ops->opts = o;
     int rc = build_ops(tree, ops, (hipStream_t)stream);
+    if (rc == KIFMM_OK) rc = blas_reserve(ops, (hipStream_t)stream);
     if (rc != KIFMM_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         free_ops(ops);
