@@ -126,3 +126,9 @@ def test_benchmark_configuration_against_the_oracle(K, record_property):
     record_property("rel_l2_sampled", samp)
     print("benchmark configuration: full field %.2e, 4,096 cells %.2e" % (full, samp))
     assert full < 3e-5 and samp < 1e-4
+    # the mixed-precision form the bench reports beside it (split-BF16 M2L products):
+    # within 1e-5 of the FP32 evaluation, and the same bars against the exact field
+    Sx = K.eval(tree, ops, torch.from_numpy(I).cuda(), w.prefactor, precision="bf16x3").double().cpu().numpy()
+    record_property("rel_l2_bf16x3_vs_fp32", rel_l2(Sx, S))
+    assert rel_l2(Sx, S) < 1e-5
+    assert rel_l2(Sx, ref) < 3e-5 and rel_l2(Sx[tg], ref[tg]) < 1e-4
