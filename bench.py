@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--rcond", type=float, default=1e-5)
     ap.add_argument("--m0", type=int, default=5)
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--variants", default="bf16x3,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense,bf16x3/dense/near_dense,m2l_bf16x3/near_dense,m2l_fp16/near_dense,m2l_bf16/near_dense",
+    ap.add_argument("--variants", default="bf16x3,fp16,bf16,m2l_bf16x3,m2l_fp16,m2l_bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense,bf16x3/dense/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "
                          "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout), "
                          "'/near_fft' or '/near_dense' the near-field form")

@@ -113,9 +113,17 @@ typedef struct {
  *                     (about 16 significant bits per operand).
  *   KIFMM_BF16X3    : the near field (P2P) and M2L both in split bfloat16; the
  *                     near-range matrices, self cell included, are computed in
- *                     FP64 and then split.  Other passes FP32. */
+ *                     FP64 and then split.  Other passes FP32.
+ *   KIFMM_BF16      : every translation GEMM (P2M, M2M, M2L, L2L, L2P) with
+ *                     bfloat16 operands, FP32 accumulation: operators stored
+ *                     divided by their maxima, inputs divided by theirs; the
+ *                     near field and its self cell in FP32 (operators and
+ *                     pseudo-inverses built in FP64).
+ *   KIFMM_FP16      : the same with FP16 operands.
+ * With kifmm_ops_p2p_fft on, the near field of every single-precision mode other
+ * than a dense KIFMM_BF16X3 runs in Fourier space (FP32). */
 enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_M2L_BF16 = 2, KIFMM_M2L_FP16 = 3, KIFMM_M2L_BF16X3 = 4,
-       KIFMM_BF16X3 = 5 };
+       KIFMM_BF16X3 = 5, KIFMM_BF16 = 6, KIFMM_FP16 = 7 };
 
 typedef struct kifmm_tree_s *kifmm_tree;
 typedef struct kifmm_ops_s *kifmm_ops;
@@ -207,7 +215,7 @@ int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 
 /* Near field in Fourier space (eq. (nearfar), direct part, with the self cell).  On the
  * uniform grid the matrix between a leaf of 8^3 cells and a neighbour leaf is a block of a
- * convolution, so with enable != 0 the near field of FP32 and KIFMM_BF16X3 evaluations
+ * convolution, so with enable != 0 the near field of every single-precision evaluation
  * runs as: half spectra (15 x 15 x 8) of every leaf's sources zero-padded to 15^3,
  * 27 complex products per frequency against the kernel spectra of the 27 neighbour
  * offsets (built in FP64 with the operators), and the inverse transform at the 8^3 cells.

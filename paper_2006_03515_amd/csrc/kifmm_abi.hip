@@ -185,6 +185,12 @@ struct kifmm_ops_s {
     // 1 if some leaf below it is wanted (level D: the leaves); empty: every target is wanted
     std::vector<uint8_t *> want;
     _Float16 *m2lh = nullptr;
+    // KIFMM_BF16 / KIFMM_FP16: the surface operators (P2M, M2M per level, L2L per level, L2P)
+    // stored divided by their maxima in BF16 and FP16
+    __bf16 *p2mbf = nullptr, *m2mbf = nullptr, *l2lbf = nullptr, *l2pbf = nullptr;
+    _Float16 *p2mh = nullptr, *m2mh = nullptr, *l2lh = nullptr, *l2ph = nullptr;
+    float p2m_scale = 1.f, l2p_scale = 1.f;
+    std::vector<float> m2m_scale, l2l_scale;   // per level (M2M: target level, L2L: target level)
     // FFT form of M2L (layout LATTICE): per level l, the kernel spectra of the 316 offsets
     // (fft_g[l], 316 x nfp complex), upward coefficients -> equivalent densities on the
     // lattice (lat_w[l] = W_u, lrow x KU, rows past m0^3 zero) and lattice check potentials
@@ -289,6 +295,7 @@ static void free_ops(kifmm_ops o) {
     if (o->fine) (void)hipStreamSynchronize(o->fine);
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
+                    o->p2mbf, o->m2mbf, o->l2lbf, o->l2pbf, o->p2mh, o->m2mh, o->l2lh, o->l2ph,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
                     o->blas_ws, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
@@ -1131,6 +1138,47 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             KIFMM_TRY(store<_Float16>(tmp, kd, ku, n316, o->m2lh + so, KD, KU, 1.0 / mx, st));
         }
     }
+    // BF16 and FP16 copies of the surface operators, each divided by its maximum magnitude
+    {
+        auto lowp = [&](const double *src, int M, int K, int batch, __bf16 **bf, _Float16 **hh, float *scale) {
+            double mx;
+            KIFMM_TRY(max_abs_host(src, (size_t)M * K * batch, &mx, st));
+            if (!(mx > 0)) mx = 1.0;
+            *scale = (float)mx;
+            KIFMM_TRY(dmalloc(bf, (size_t)M * K * batch));
+            KIFMM_TRY(dmalloc(hh, (size_t)M * K * batch));
+            KIFMM_TRY(store<__bf16>(src, M, K, batch, *bf, M, K, 1.0 / mx, st));
+            return store<_Float16>(src, M, K, batch, *hh, M, K, 1.0 / mx, st);
+        };
+        KIFMM_TRY(lowp(o->p2m64, KU, s, 1, &o->p2mbf, &o->p2mh, &o->p2m_scale));
+        KIFMM_TRY(lowp(o->l2p64, s, KD, 1, &o->l2pbf, &o->l2ph, &o->l2p_scale));
+        o->m2m_scale.assign(D + 1, 1.0f);
+        o->l2l_scale.assign(D + 1, 1.0f);
+        if (D > 2) {
+            KIFMM_TRY(dmalloc(&o->m2mbf, (size_t)(D - 2) * 8 * KU * KU));
+            KIFMM_TRY(dmalloc(&o->m2mh, (size_t)(D - 2) * 8 * KU * KU));
+            KIFMM_TRY(dmalloc(&o->l2lbf, (size_t)(D - 2) * 8 * KD * KD));
+            KIFMM_TRY(dmalloc(&o->l2lh, (size_t)(D - 2) * 8 * KD * KD));
+        }
+        for (int l = 2; l <= D - 1; ++l) {   // M2M into level l: block l - 2
+            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
+            double mx;
+            KIFMM_TRY(max_abs_host(o->m2m64 + so, (size_t)8 * KU * KU, &mx, st));
+            if (!(mx > 0)) mx = 1.0;
+            o->m2m_scale[l] = (float)mx;
+            KIFMM_TRY(store<__bf16>(o->m2m64 + so, KU, KU, 8, o->m2mbf + so, KU, KU, 1.0 / mx, st));
+            KIFMM_TRY(store<_Float16>(o->m2m64 + so, KU, KU, 8, o->m2mh + so, KU, KU, 1.0 / mx, st));
+        }
+        for (int l = 3; l <= D; ++l) {   // L2L into level l: block l - 3
+            const size_t so = (size_t)(l - 3) * 8 * KD * KD;
+            double mx;
+            KIFMM_TRY(max_abs_host(o->l2l64 + so, (size_t)8 * KD * KD, &mx, st));
+            if (!(mx > 0)) mx = 1.0;
+            o->l2l_scale[l] = (float)mx;
+            KIFMM_TRY(store<__bf16>(o->l2l64 + so, KD, KD, 8, o->l2lbf + so, KD, KD, 1.0 / mx, st));
+            KIFMM_TRY(store<_Float16>(o->l2l64 + so, KD, KD, 8, o->l2lh + so, KD, KD, 1.0 / mx, st));
+        }
+    }
     if (o->opts.layout == KIFMM_LAYOUT_LATTICE) KIFMM_TRY(build_fft_m2l(db, o, Lside, h, m2lo, fu, fd, st));
     for (int l = 2; l <= D; ++l) {
         const size_t nbx = (size_t)1 << (3 * l);
@@ -1189,6 +1237,28 @@ int blas_gemm_tn(kifmm_ops o, int M, int64_t n, int K, const float *A, const flo
 }
 int run(const TapArgs<double, double, double> &p, hipStream_t st) { return run_tap_f64(p, st); }
 
+// A surface-operator pass (P2M, M2M, L2L, L2P) with BF16 or FP16 operands (KIFMM_BF16,
+// KIFMM_FP16): the input is divided by its maximum magnitude (device-side partial maxima) and
+// rounded while it is staged, the operator was stored divided by its own maximum, and the
+// products accumulate in FP32.
+template <typename TL>
+int lowp_pass(kifmm_ops o, const TL *A, int64_t a_stride, int M, int K, const float *in, int64_t n_in, int64_t in_ld,
+              float *out, int64_t out_ld, int mode, const TapList &tl, int nclass, int64_t nper, int acc, float scale,
+              const uint8_t *in_nz, const uint8_t *out_need, bool split, hipStream_t st) {
+    KIFMM_TRY(run_amax(in, n_in, o->amax, o->n_amax, st));
+    auto p = tap<TL, float>(A, a_stride, M, K, in, in_ld, out, out_ld, mode, 0, tl, nclass, nper, acc);
+    p.amax = o->amax;
+    p.n_amax = o->n_amax;
+    p.op_scale = scale;
+    p.in_nz = in_nz;
+    p.out_need = out_need;
+    if (split) {
+        p.part = o->part;
+        p.part_capacity = o->part_capacity;
+    }
+    return run_tap_lp<TL>(p, false, st);
+}
+
 template <typename T>
 struct OpSet {
     const T *p2m, *m2m, *m2l, *l2l, *l2p, *p2p;
@@ -1231,13 +1301,14 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             return run(pi, st);
         }
         if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16X3 ||
-            precision == KIFMM_BF16X3) {
+            precision == KIFMM_BF16X3 || precision == KIFMM_BF16 || precision == KIFMM_FP16) {
+            const bool fp16 = precision == KIFMM_M2L_FP16 || precision == KIFMM_FP16;
             const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
             KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
             const int64_t ldA = (int64_t)KD * KU;
             const bool x3 = precision == KIFMM_M2L_BF16X3 || precision == KIFMM_BF16X3;
             if (KD > 64) {   // staged kernel on the split coefficients
-                if (precision == KIFMM_M2L_FP16) {
+                if (fp16) {
                     _Float16 *hi = (_Float16 *)o->split_c;
                     KIFMM_TRY(run_split_lp<_Float16>((const float *)o->cu[l], ncu, o->amax, o->n_amax, hi, nullptr, st));
                     auto p = tap<_Float16, _Float16>(o->m2lh + so, ldA, KD, KU, hi, KU, (float *)o->cd[l], KD, SRC_NBR,
@@ -1262,7 +1333,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 p.pass = PASS_M2L;
                 return run_tap_lp_staged<__bf16>(p, x3, st);
             }
-            if (precision == KIFMM_M2L_FP16) {
+            if (fp16) {
                 auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
                                               (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
@@ -1301,7 +1372,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
     const int s = o->s, nb = o->nb;
     const int64_t nleaf = (int64_t)nb * nb * nb;
     if constexpr (sizeof(T) == 4) {
-        if (o->p2p_fft && nb >= 4 && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
+        if (o->p2p_fft && nb >= 4) {   // FP32 arithmetic in every single-precision mode
             for (int stage = 0; stage < 3; ++stage) {
                 PassTimer pt(o, stage == 1 ? KIFMM_PASS_NEAR_PRODUCTS : -1, st);
                 KIFMM_TRY(run_near_fft_stage(stage, (const float *)q, o->near_gh, nb, want_of(o, o->D), nz_of(o, o->D),
@@ -1421,7 +1492,14 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // far field: upward pass, downward pass, local expansion at the cells
     {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        if (sizeof(T) == 4 && !nz_of(o, D)) {   // every leaf: one plain GEMM
+        if (sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16)) {
+            if (precision == KIFMM_BF16)
+                KIFMM_TRY(lowp_pass<__bf16>(o, o->p2mbf, 0, KU, s, (const float *)q, nleaf * s, s, (float *)o->cu[D], KU,
+                                            SRC_SAME, o->t_single, 1, nleaf, 0, o->p2m_scale, nz_of(o, D), nullptr, false, st));
+            else
+                KIFMM_TRY(lowp_pass<_Float16>(o, o->p2mh, 0, KU, s, (const float *)q, nleaf * s, s, (float *)o->cu[D], KU,
+                                              SRC_SAME, o->t_single, 1, nleaf, 0, o->p2m_scale, nz_of(o, D), nullptr, false, st));
+        } else if (sizeof(T) == 4 && !nz_of(o, D)) {   // every leaf: one plain GEMM
             KIFMM_TRY(blas_gemm_tn(o, KU, nleaf, s, (const float *)ops.p2m, (const float *)q, (float *)o->cu[D], st));
         } else {
             auto p = tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
@@ -1449,8 +1527,21 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // into cd[l]; the main stream does level 2 and the L2L chain, each L2L adding to the M2L
     // sum (the coarse chain of small launches is otherwise the step's longest path).
     const bool coarse_side = fine_apart && D >= 4 && o->p2p_fft && nb >= 4;
+    const bool lowp = sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16);
     for (int l = D - 1; l >= 2; --l) {
-        {
+        if (lowp) {
+            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
+            const int64_t nin = ((int64_t)1 << (3 * (l + 1))) * KU;
+            PassTimer pt(o, KIFMM_PASS_M2M, st);
+            if (precision == KIFMM_BF16)
+                KIFMM_TRY(lowp_pass<__bf16>(o, o->m2mbf + so, (int64_t)KU * KU, KU, KU, (const float *)o->cu[l + 1], nin,
+                                            KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, (int64_t)1 << (3 * l), 0,
+                                            o->m2m_scale[l], nz_of(o, l + 1), nullptr, true, st));
+            else
+                KIFMM_TRY(lowp_pass<_Float16>(o, o->m2mh + so, (int64_t)KU * KU, KU, KU, (const float *)o->cu[l + 1], nin,
+                                              KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, (int64_t)1 << (3 * l), 0,
+                                              o->m2m_scale[l], nz_of(o, l + 1), nullptr, true, st));
+        } else {
             const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
             PassTimer pt(o, KIFMM_PASS_M2M, st);
             auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
@@ -1482,12 +1573,25 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         if (l > 2) {
             if (fine_apart && l == D) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
             else if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
-            const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
             PassTimer pt(o, KIFMM_PASS_L2L, st);
-            auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
-                               0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), m2l_done ? 1 : 0);
-            p.out_need = want_of(o, l);
-            KIFMM_TRY(run(p, st));
+            if (lowp) {
+                const size_t so = (size_t)(l - 3) * 8 * KD * KD;
+                const int64_t nin = ((int64_t)1 << (3 * (l - 1))) * KD, nper = (int64_t)1 << (3 * (l - 1));
+                if (precision == KIFMM_BF16)
+                    KIFMM_TRY(lowp_pass<__bf16>(o, o->l2lbf + so, (int64_t)KD * KD, KD, KD, (const float *)o->cd[l - 1], nin,
+                                                KD, (float *)o->cd[l], KD, SRC_PARENT, o->t_l2l, 8, nper, m2l_done ? 1 : 0,
+                                                o->l2l_scale[l], nullptr, want_of(o, l), false, st));
+                else
+                    KIFMM_TRY(lowp_pass<_Float16>(o, o->l2lh + so, (int64_t)KD * KD, KD, KD, (const float *)o->cd[l - 1], nin,
+                                                  KD, (float *)o->cd[l], KD, SRC_PARENT, o->t_l2l, 8, nper, m2l_done ? 1 : 0,
+                                                  o->l2l_scale[l], nullptr, want_of(o, l), false, st));
+            } else {
+                const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
+                auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
+                                   0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), m2l_done ? 1 : 0);
+                p.out_need = want_of(o, l);
+                KIFMM_TRY(run(p, st));
+            }
         }
         if (m2l_done) continue;
         PassTimer pt(o, KIFMM_PASS_M2L, st);
@@ -1498,7 +1602,17 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         // every leaf, also when targets are restricted: the wanted leaves then keep the
         // unrestricted values bit for bit (the others are written as zeros at the end; their
         // coefficients are finite, every level's coefficients being written in full)
-        if (sizeof(T) == 4) {
+        if (lowp) {
+            const int64_t nin = nleaf * KD;
+            if (precision == KIFMM_BF16)
+                KIFMM_TRY(lowp_pass<__bf16>(o, o->l2pbf, 0, s, KD, (const float *)o->cd[D], nin, KD, (float *)Sp, s,
+                                            SRC_SAME, o->t_single, 1, nleaf, 0, o->l2p_scale, nullptr, want_of(o, D),
+                                            false, st));
+            else
+                KIFMM_TRY(lowp_pass<_Float16>(o, o->l2ph, 0, s, KD, (const float *)o->cd[D], nin, KD, (float *)Sp, s,
+                                              SRC_SAME, o->t_single, 1, nleaf, 0, o->l2p_scale, nullptr, want_of(o, D),
+                                              false, st));
+        } else if (sizeof(T) == 4) {
             KIFMM_TRY(blas_gemm_tn(o, s, nleaf, KD, (const float *)ops.l2p, (const float *)o->cd[D], (float *)Sp, st));
         } else {
             auto p = tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
@@ -1705,7 +1819,7 @@ int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefact
     if (ops->tree_magic != tree->magic) return fail(KIFMM_EMISMATCH, "ops were built for another tree");
     if (!I_dev || !S_dev) return fail(KIFMM_EINVAL, "I_dev and S_dev must be non-NULL");
     if (!std::isfinite(prefactor)) return fail(KIFMM_EINVAL, "prefactor must be finite");
-    if (precision < KIFMM_FP64 || precision > KIFMM_BF16X3) return fail(KIFMM_EINVAL, "unknown precision");
+    if (precision < KIFMM_FP64 || precision > KIFMM_FP16) return fail(KIFMM_EINVAL, "unknown precision");
     const size_t esz = precision == KIFMM_FP64 ? 8 : 4;
     const char *ib = (const char *)I_dev, *sb = (const char *)S_dev;
     const size_t bytes = (size_t)tree->N * esz;

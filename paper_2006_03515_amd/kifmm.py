@@ -17,9 +17,9 @@ LIB_PATH = os.environ.get("KIFMM_LIB") or os.path.join(_HERE, "libkifmm.so")   #
 
 OK, EINVAL, EUNSUPPORTED, EMISMATCH, ENOMEM, EHIP = 0, -1, -2, -3, -4, -5
 LAYOUT_PAPER, LAYOUT_SINGLE, LAYOUT_NESTED, LAYOUT_LATTICE = 0, 1, 2, 3
-FP64, FP32, M2L_BF16, M2L_FP16, M2L_BF16X3, BF16X3 = 0, 1, 2, 3, 4, 5
+FP64, FP32, M2L_BF16, M2L_FP16, M2L_BF16X3, BF16X3, BF16, FP16 = 0, 1, 2, 3, 4, 5, 6, 7
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "m2l_bf16": M2L_BF16, "m2l_fp16": M2L_FP16,
-              "m2l_bf16x3": M2L_BF16X3, "bf16x3": BF16X3}
+              "m2l_bf16x3": M2L_BF16X3, "bf16x3": BF16X3, "bf16": BF16, "fp16": FP16}
 CHI_MIN, CHI_MAX = 0.035, 2.0
 
 EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "kifmm_tree_info",

@@ -53,7 +53,7 @@ def test_config3_256_streamer_all_precisions(K, p, record_property):
     # the benchmark configuration: 256^3, nested m0=5, rcond 1e-5, leaves 8^3, against
     # the exact full field (zero-padded FFT convolution of the FP64 oracle)
     w = workloads.streamer_channel(n=256, L=0.4, p=p)
-    precs = ["fp32", "m2l_fp16", "m2l_bf16x3", "bf16x3", "m2l_bf16"]
+    precs = ["fp32", "m2l_fp16", "m2l_bf16x3", "bf16x3", "m2l_bf16", "fp16", "bf16"]
     I, S = _run(K, w, K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), precs)
     ref = odirect.fft_full(I.reshape(256, 256, 256).astype(np.float64), (w.h,) * 3, w.p_o2,
                            prefactor=w.prefactor, workers=16).ravel()
@@ -71,6 +71,10 @@ def test_config3_256_streamer_all_precisions(K, p, record_property):
     assert errs["m2l_fp16"] < 5e-5
     assert abs(errs["bf16x3"] - errs["fp32"]) < 0.2 * errs["fp32"]
     assert errs["m2l_bf16"] < 1e-3
+    # every translation GEMM (P2M, M2M, M2L, L2L, L2P) with FP16 or BF16 operands: below the
+    # format's unit roundoff, 2^-11 (FP16) and 2^-8 (BF16), and no better than FP32
+    assert errs["fp32"] <= errs["fp16"] < 2.0 ** -11
+    assert errs["fp32"] <= errs["bf16"] < 2.0 ** -8
 
 
 def test_config3_256_accurate_layout_fp32_within_1e6(K):
