@@ -75,9 +75,12 @@ def test_fp32_is_fp64_up_to_rounding(K, g32):
 
 
 @pytest.mark.parametrize("precision,tol_direct,tol_fp32", [("m2l_bf16", 1e-3, 1e-3), ("m2l_fp16", 1e-4, 1e-4),
-                                                         ("m2l_bf16x3", 1e-5, 1e-5), ("bf16x3", 1e-5, 1e-5)])
+                                                         ("m2l_bf16x3", 1e-5, 1e-5), ("bf16x3", 1e-5, 1e-5),
+                                                         ("fp16", 2.0 ** -11, 2.0 ** -11),
+                                                         ("bf16", 2.0 ** -8, 2.0 ** -8)])
 def test_low_precision_m2l(K, g32, precision, tol_direct, tol_fp32, record_property):
-    # nested layout: truncation ~2e-7, so the error measured is the M2L rounding
+    # nested layout: truncation ~2e-7, so the error measured is the M2L rounding (fp16 / bf16:
+    # of every translation GEMM, bounded by the format's unit roundoff)
     I, L, refs = g32
     lo = fmm(K, I, L, 150.0, 64, layout="nested", rcond=1e-10, precision=precision)
     hi = fmm(K, I, L, 150.0, 64, layout="nested", rcond=1e-10, precision="fp32")
