@@ -162,10 +162,11 @@ def main():
     ap.add_argument("--rcond", type=float, default=1e-5)
     ap.add_argument("--m0", type=int, default=5)
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--variants", default="bf16x3,fp16,bf16,m2l_bf16x3,m2l_fp16,m2l_bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense,bf16x3/dense/near_dense",
+    ap.add_argument("--variants", default="fp32/graph,bf16x3/graph,bf16x3,fp16,bf16,m2l_bf16x3,m2l_fp16,m2l_bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense,bf16x3/dense/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "
                          "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout), "
-                         "'/near_fft' or '/near_dense' the near-field form")
+                         "'/near_fft' or '/near_dense' the near-field form, '/graph' times replays "
+                         "of one evaluation captured in a HIP graph")
     ap.add_argument("--check-targets", type=int, default=4096)
     ap.add_argument("--cpu-targets", type=int, default=2048,
                     help="targets of the oracle CPU baseline sample (0 = skip)")
@@ -232,6 +233,32 @@ def main():
         if profile:
             ops.profile(False)
         return ms, prof
+
+    def timed_graph(precision, steps, warmup):
+        # one evaluation captured in a HIP graph (its side streams join the capture through
+        # the library's fork/join events), then replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            K.eval(tree, ops, I, w.prefactor, out=S, precision=precision)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            K.eval(tree, ops, I, w.prefactor, out=S, precision=precision)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            g.replay()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        del g
+        return e0.elapsed_time(e1) / steps
 
     # accuracy sample: FP64 direct at seeded targets (computed once)
     tg = workloads.sample_targets(w.n ** 3, args.check_targets, seed=1009)
@@ -315,7 +342,10 @@ def main():
                 ops.m2l_fft(form == "fft")
             if form in ("near_fft", "near_dense"):
                 ops.p2p_fft(form == "near_fft")
-        vms, _ = timed(prec, args.steps, args.warmup, profile=False)
+        if "graph" in forms:
+            vms = timed_graph(prec, args.steps, args.warmup)
+        else:
+            vms, _ = timed(prec, args.steps, args.warmup, profile=False)
         variants[v] = {"value": N / (vms * 1e-3), "ms_per_step": round(vms, 4), "rel_l2": accuracy(),
                        "speedup_vs_headline": round(ms / vms, 3)}
         if args.layout == "lattice":

@@ -1,0 +1,56 @@
+"""One evaluation captured in a HIP graph (torch.cuda.CUDAGraph around kifmm_eval).
+
+kifmm_eval allocates nothing, never synchronises the host and forks its side streams from
+the calling stream (and joins them back) through events, so a capture on the calling
+stream records the whole evaluation.  Every replay, with eager evaluations of other data
+and synchronisations between the replays, must give the eager result bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as odirect
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2006_03515_amd import kifmm
+    return kifmm
+
+
+@pytest.mark.parametrize("prec,m2l_fft,near_fft", [("fp32", True, True), ("bf16x3", True, True),
+                                                   ("fp32", False, False)])
+def test_graph_replay_is_the_eager_evaluation(K, prec, m2l_fft, near_fft):
+    n, L, p_o2 = 64, 0.1, 150.0
+    I = np.random.default_rng(71).random((n, n, n)).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    ops.m2l_fft(m2l_fft)
+    ops.p2p_fft(near_fft)
+    It = torch.from_numpy(I.ravel()).cuda()
+    other = torch.flip(It, (0,)).contiguous()   # different data for the eager runs in between
+    ref = K.eval(tree, ops, It, 1.0, precision=prec)
+    torch.cuda.synchronize()
+    S, T = torch.zeros_like(It), torch.empty_like(It)
+    side = torch.cuda.Stream()   # warm-up off the capture, as torch asks
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        K.eval(tree, ops, It, 1.0, out=S, precision=prec)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        K.eval(tree, ops, It, 1.0, out=S, precision=prec)
+    torch.cuda.synchronize()
+    for r in range(3):
+        S.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(S, ref), "replay %d differs from the eager evaluation" % r
+        K.eval(tree, ops, other, 1.0, out=T, precision=prec)
+        torch.cuda.synchronize()
+    exact = odirect.fft_full(I.astype(np.float64), (L / n,) * 3, p_o2).ravel()
+    assert rel_l2(S.double().cpu().numpy(), exact) < 1e-4
+    del g
