@@ -30,6 +30,10 @@
  *   stream: a hipStream_t passed as void*; NULL means the legacy default stream.
  *   Work is enqueued on `stream`; kifmm_eval and direct_eval return before it
  *   finishes, never synchronise the device, and allocate no memory.
+ *   kifmm_eval forks its internal streams from `stream` and joins them back
+ *   through events, so a call may be captured in a HIP graph on `stream`
+ *   (replays repeat the evaluation on the same pointers; calls or replays that
+ *   overlap on one ops object race).
  *   Inputs are never modified.
  *
  * Errors
