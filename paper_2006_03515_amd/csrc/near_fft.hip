@@ -24,7 +24,7 @@
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
 //                         frequencies x 16 columns of 4 targets along z (the 12 taps of a
 //                         column at one (ox, oy) read 6 source spectra).
-//                         A workgroup takes 4 chunks of 16 frequencies in turn, the next
+//                         A workgroup takes 8 chunks of 16 frequencies in turn, the next
 //                         chunk's spectra in flight (registers) while one is multiplied;
 //                         XCD-contiguous order of the workgroups.
 //                         Each chunk ends with the first inverse stage (over kx, at the 8
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
     }
 }
 
-constexpr int NCH = 4;   // frequency chunks per products workgroup
+constexpr int NCH = 8;   // frequency chunks per products workgroup
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
