@@ -265,6 +265,15 @@ enum { KIFMM_PASS_PERMUTE_IN = 0, KIFMM_PASS_P2M = 1, KIFMM_PASS_M2M = 2, KIFMM_
 int kifmm_profile_enable(kifmm_ops ops, int32_t on);
 int kifmm_profile_read(kifmm_ops ops, double *ms, int64_t *calls, int32_t n);
 
+/* Serial schedule (measurement).  With enable != 0, every later kifmm_eval with `ops`
+ * runs all its passes on the calling stream, one after the other (near field first,
+ * then the upward pass, M2L level by level and the downward pass), instead of forking
+ * the near field and the M2L of the finest and coarse levels onto the library's own
+ * streams.  The results are bit for bit those of the concurrent schedule (the same
+ * kernels on the same data); only the overlap is lost, so each kernel's duration in a
+ * trace is its own.  Returns 0 or KIFMM_EINVAL (ops NULL). */
+int kifmm_ops_serial(kifmm_ops ops, int32_t enable);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate (not in the paper): kernels of a 3D convolutional network
  * that maps a coarse source field to S_ph, trained on pairs made by kifmm_eval
@@ -337,6 +346,12 @@ int kifmm_nn_upsample2(int32_t batch, int32_t n_coarse, const float *coarse, flo
 /* out[0] = ||scale * S[tgt] - ref|| / ||ref|| (one workgroup, fixed order) */
 int kifmm_nn_sampled_rel_err(int64_t n_tgt, const float *S, const int64_t *tgt, const double *ref,
                              double scale, double *out, void *stream);
+/* x[0:n] *= s (a prediction made for prefactor 1, rescaled) */
+int kifmm_nn_scale(int64_t n, float *x, float s, void *stream);
+/* out[0] = ||S[tgt] - R[tgt]|| / ||R[tgt]|| for two FP32 fields in grid order (one workgroup,
+ * FP64 sums in a fixed order): the serving check of a prediction S against a judge's field R */
+int kifmm_nn_sampled_rel_diff(int64_t n_tgt, const float *S, const float *R, const int64_t *tgt, double *out,
+                              void *stream);
 
 void kifmm_tree_destroy(kifmm_tree tree);  /* NULL is ignored */
 void kifmm_ops_destroy(kifmm_ops ops);     /* NULL is ignored */

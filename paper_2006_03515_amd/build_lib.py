@@ -45,7 +45,7 @@ def build(jobs=8, verbose=False):
             print(msg)
     objs = [o for o, _ in res]
     tmp = OUT + ".tmp"
-    subprocess.check_call(["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lrocblas"])
+    subprocess.check_call(["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs)
     os.replace(tmp, OUT)
     return OUT
 

@@ -7,8 +7,6 @@
 #include <cstring>
 #include <numeric>
 
-#include <rocblas/rocblas.h>
-
 #include "common.h"
 #include "tapgemm.h"
 
@@ -58,6 +56,11 @@ int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, 
                        float *, hipStream_t);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
+int launch_pack_fragments(const float *, int, int, int, float4 *, hipStream_t);
+bool leafgemm_fits(const Tree &, int, int);
+int run_p2m_permute_in(const Tree &, const float *, float, const float4 *, int, float *, float *, hipStream_t);
+int run_l2p_permute_out(const Tree &, const float *, int, const float4 *, const float *, float, const uint8_t *, float *,
+                        hipStream_t);
 
 static std::atomic<uint64_t> g_magic{0x6b69666d6d000001ull};
 
@@ -226,8 +229,10 @@ struct kifmm_ops_s {
     // levels' M2L), joined by events; with the FFT form of M2L the finest level's M2L runs
     // on a third, beside the upward pass and the coarse levels
     hipStream_t side = nullptr, fine = nullptr;
-    rocblas_handle blas = nullptr;   // FP32 P2M and L2P over all leaves (plain GEMMs)
-    void *blas_ws = nullptr;         // its workspace, sized at precompute (evaluations allocate nothing)
+    bool serial = false;             // kifmm_ops_serial: every pass on the calling stream, in order
+    // P2M and L2P as MFMA fragments for the kernels fused with the permutes (FP32, leaves of
+    // 8^3 cells): [KU / 32 tiles][64 chunks][64 lanes] and [16 tiles][KD / 8 chunks][64 lanes]
+    float4 *p2m_frag = nullptr, *l2p_frag = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
     // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
     std::vector<hipEvent_t> ev_up, ev_m2l;
@@ -298,7 +303,7 @@ static void free_ops(kifmm_ops o) {
                     o->p2mbf, o->m2mbf, o->l2lbf, o->l2pbf, o->p2mh, o->m2mh, o->l2lh, o->l2ph,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
-                    o->blas_ws, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
+                    o->p2m_frag, o->l2p_frag, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -321,7 +326,6 @@ static void free_ops(kifmm_ops o) {
         for (hipEvent_t e : *v)
             if (e) (void)hipEventDestroy(e);
     if (o->fine) (void)hipStreamDestroy(o->fine);
-    if (o->blas) (void)rocblas_destroy_handle(o->blas);
     delete o;
 }
 
@@ -971,10 +975,6 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
     KIFMM_HIP(hipStreamCreateWithFlags(&o->fine, hipStreamNonBlocking));
-    if (rocblas_create_handle(&o->blas) != rocblas_status_success) {
-        o->blas = nullptr;
-        return fail(KIFMM_EHIP, "rocblas_create_handle failed");
-    }
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
@@ -1060,6 +1060,13 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(dmalloc(&o->l2p32, (size_t)s * KD));
         KIFMM_TRY(dmalloc(&o->l2p64, (size_t)s * KD));
         KIFMM_TRY(store_both(tmp, s, o->kd[D], 1, o->l2p32, o->l2p64, s, KD, st));
+    }
+    // their MFMA fragments for the kernels fused with the permutes
+    if (leafgemm_fits(*tree, KU, KD)) {
+        KIFMM_TRY(dmalloc(&o->p2m_frag, (size_t)KU * s / 4));
+        KIFMM_TRY(dmalloc(&o->l2p_frag, (size_t)s * KD / 4));
+        KIFMM_TRY(launch_pack_fragments(o->p2m32, KU, s, s, o->p2m_frag, st));
+        KIFMM_TRY(launch_pack_fragments(o->l2p32, s, KD, KD, o->l2p_frag, st));
     }
     // child centre offsets at a level of half-width r: (2c - 1) r per axis
     auto child_shifts = [&](double r) {
@@ -1224,17 +1231,6 @@ TapArgs<TA, TI, TO> tap(const TA *A, int64_t a_stride, int M, int K, const TI *i
 
 int run(const TapArgs<float, float, float> &p, hipStream_t st) { return run_tap_f32(p, st); }
 
-// out[b][0:M] = A (M x K, row-major) . in[b][0:K] for the n boxes b, in FP32 through rocBLAS:
-// column-major C (M x n) = A^T^T B with A read as its K x M column-major transpose
-int blas_gemm_tn(kifmm_ops o, int M, int64_t n, int K, const float *A, const float *in, float *out, hipStream_t st) {
-    if (n > INT32_MAX) return fail(KIFMM_EINVAL, "P2M/L2P: too many leaves for one GEMM");
-    if (rocblas_set_stream(o->blas, st) != rocblas_status_success) return fail(KIFMM_EHIP, "rocblas_set_stream failed");
-    const float one = 1.f, zero = 0.f;
-    const rocblas_status r = rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, M, (int)n, K,
-                                           &one, A, K, in, K, &zero, out, M);
-    if (r != rocblas_status_success) return fail(KIFMM_EHIP, std::string("rocblas_sgemm failed: ") + rocblas_status_to_string(r));
-    return KIFMM_OK;
-}
 int run(const TapArgs<double, double, double> &p, hipStream_t st) { return run_tap_f64(p, st); }
 
 // A surface-operator pass (P2M, M2M, L2L, L2P) with BF16 or FP16 operands (KIFMM_BF16,
@@ -1454,6 +1450,26 @@ int mark_nonzero_sources(kifmm_ops o, const T *q, hipStream_t st) {
     return KIFMM_OK;
 }
 
+// Error path of an evaluation whose side streams were forked: the streams are joined back
+// into the calling stream before the error is returned, so that no later work on the calling
+// stream (the next evaluation's permute into q, a caller's read of S) overlaps kernels still
+// running on them, and a stream capture stays joined.
+struct ForkJoin {
+    kifmm_ops o;
+    hipStream_t st, side, fine;
+    bool side_forked = false, fine_forked = false;
+    ~ForkJoin() {
+        if (side_forked && side != st) {
+            (void)hipEventRecord(o->join, side);
+            (void)hipStreamWaitEvent(st, o->join, 0);
+        }
+        if (fine_forked && fine != st) {
+            (void)hipEventRecord(o->join_fine, fine);
+            (void)hipStreamWaitEvent(st, o->join_fine, 0);
+        }
+    }
+};
+
 template <typename T>
 int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, int precision,
                hipStream_t st) {
@@ -1466,7 +1482,17 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // the cell volume goes in with the sources (q = I h^3), the prefactor on the way out:
     // FP32 sums of G I alone reach 1e37 for fine cells and bright sources
     const T vol = (T)(t->h * t->h * t->h), scale = (T)prefactor;
-    {
+    // every translation GEMM with BF16 or FP16 operands
+    const bool lowp = sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16);
+    // P2M fused with the way into leaf order, L2P with the sum and the way out (FP32 GEMMs,
+    // leaves of 8^3 cells); with zero-source flags P2M keeps the tap GEMM, which skips them
+    const bool fused_in = sizeof(T) == 4 && D >= 2 && o->p2m_frag && !lowp && !o->skip_zero &&
+                          (uintptr_t)I % 16 == 0;
+    const bool fused_out = sizeof(T) == 4 && D >= 2 && o->l2p_frag && !lowp && (uintptr_t)S % 16 == 0;
+    if (fused_in) {
+        PassTimer pt(o, KIFMM_PASS_P2M, st);
+        KIFMM_TRY(run_p2m_permute_in(*t, (const float *)I, (float)vol, o->p2m_frag, KU, (float *)q, (float *)o->cu[D], st));
+    } else {
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, vol, q, st));
     }
@@ -1479,28 +1505,31 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
         return launch_permute_out<T>(*t, Sp, scale, want_of(o, D), S, st);
     }
+    // the side streams, or the calling stream itself when every pass is to run in order
+    // (kifmm_ops_serial: per-kernel timings without overlap)
+    hipStream_t side = o->serial ? st : o->side, fine = o->serial ? st : o->fine;
     // near field on the side stream, forked as early as possible: whatever runs beside it
     // waits for its long workgroups (forking it later, after the upward pass or before the
     // finest M2L level, measured slower)
     KIFMM_HIP(hipEventRecord(o->fork, st));
-    KIFMM_HIP(hipStreamWaitEvent(o->side, o->fork, 0));
+    KIFMM_HIP(hipStreamWaitEvent(side, o->fork, 0));
+    ForkJoin fj{o, st, side, fine};
+    fj.side_forked = true;
     {
-        PassTimer pt(o, KIFMM_PASS_P2P, o->side);
-        KIFMM_TRY(p2p_pass<T>(o, ops, q, SpN, precision, o->side));
+        PassTimer pt(o, KIFMM_PASS_P2P, side);
+        KIFMM_TRY(p2p_pass<T>(o, ops, q, SpN, precision, side));
     }
-    KIFMM_HIP(hipEventRecord(o->join, o->side));
+    KIFMM_HIP(hipEventRecord(o->join, side));
     // far field: upward pass, downward pass, local expansion at the cells
-    {
+    if (!fused_in) {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        if (sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16)) {
+        if (lowp) {
             if (precision == KIFMM_BF16)
                 KIFMM_TRY(lowp_pass<__bf16>(o, o->p2mbf, 0, KU, s, (const float *)q, nleaf * s, s, (float *)o->cu[D], KU,
                                             SRC_SAME, o->t_single, 1, nleaf, 0, o->p2m_scale, nz_of(o, D), nullptr, false, st));
             else
                 KIFMM_TRY(lowp_pass<_Float16>(o, o->p2mh, 0, KU, s, (const float *)q, nleaf * s, s, (float *)o->cu[D], KU,
                                               SRC_SAME, o->t_single, 1, nleaf, 0, o->p2m_scale, nz_of(o, D), nullptr, false, st));
-        } else if (sizeof(T) == 4 && !nz_of(o, D)) {   // every leaf: one plain GEMM
-            KIFMM_TRY(blas_gemm_tn(o, KU, nleaf, s, (const float *)ops.p2m, (const float *)q, (float *)o->cu[D], st));
         } else {
             auto p = tap<T, T>(ops.p2m, 0, KU, s, q, s, (T *)o->cu[D], KU, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
             p.in_nz = nz_of(o, D);
@@ -1515,19 +1544,19 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
                             (precision == KIFMM_FP32 || precision == KIFMM_BF16X3);
     if (fine_apart) {
         KIFMM_HIP(hipEventRecord(o->fork_fine, st));
-        KIFMM_HIP(hipStreamWaitEvent(o->fine, o->fork_fine, 0));
+        KIFMM_HIP(hipStreamWaitEvent(fine, o->fork_fine, 0));
+        fj.fine_forked = true;
         {
-            PassTimer pt(o, KIFMM_PASS_M2L, o->fine);
-            KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 0, o->fine));
+            PassTimer pt(o, KIFMM_PASS_M2L, fine);
+            KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 0, fine));
         }
-        KIFMM_HIP(hipEventRecord(o->join_fine, o->fine));
+        KIFMM_HIP(hipEventRecord(o->join_fine, fine));
     }
     // With the near field in Fourier space its stream is free early: the M2L of levels
     // D - 1 .. 3 then runs there, each as soon as M2M has made that level's coefficients,
     // into cd[l]; the main stream does level 2 and the L2L chain, each L2L adding to the M2L
     // sum (the coarse chain of small launches is otherwise the step's longest path).
     const bool coarse_side = fine_apart && D >= 4 && o->p2p_fft && nb >= 4;
-    const bool lowp = sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16);
     for (int l = D - 1; l >= 2; --l) {
         if (lowp) {
             const size_t so = (size_t)(l - 2) * 8 * KU * KU;
@@ -1557,14 +1586,14 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     }
     if (coarse_side) {   // the events waited for below are all recorded (enqueued) above
         for (int l = D - 1; l >= 3; --l) {
-            KIFMM_HIP(hipStreamWaitEvent(o->side, o->ev_up[l], 0));
+            KIFMM_HIP(hipStreamWaitEvent(side, o->ev_up[l], 0));
             {
-                PassTimer pt(o, KIFMM_PASS_M2L, o->side);
-                KIFMM_TRY(m2l_level<T>(o, ops, l, precision, 0, o->side));
+                PassTimer pt(o, KIFMM_PASS_M2L, side);
+                KIFMM_TRY(m2l_level<T>(o, ops, l, precision, 0, side));
             }
-            KIFMM_HIP(hipEventRecord(o->ev_m2l[l], o->side));
+            KIFMM_HIP(hipEventRecord(o->ev_m2l[l], side));
         }
-        KIFMM_HIP(hipEventRecord(o->join, o->side));
+        KIFMM_HIP(hipEventRecord(o->join, side));
     }
     for (int l = 2; l <= D; ++l) {
         // cd[l] holds the M2L sum already: the finest level (own stream), the coarse levels
@@ -1597,6 +1626,13 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_M2L, st);
         KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > 2 ? 1 : 0, st));
     }
+    if (fused_out) {   // the local expansions at the cells, plus the near field, in grid order
+        KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
+        fj.side_forked = fj.fine_forked = false;
+        PassTimer pt(o, KIFMM_PASS_L2P, st);
+        return run_l2p_permute_out(*t, (const float *)o->cd[D], KD, o->l2p_frag, (const float *)SpN, (float)scale,
+                                   want_of(o, D), (float *)S, st);
+    }
     {
         PassTimer pt(o, KIFMM_PASS_L2P, st);
         // every leaf, also when targets are restricted: the wanted leaves then keep the
@@ -1612,8 +1648,6 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
                 KIFMM_TRY(lowp_pass<_Float16>(o, o->l2ph, 0, s, KD, (const float *)o->cd[D], nin, KD, (float *)Sp, s,
                                               SRC_SAME, o->t_single, 1, nleaf, 0, o->l2p_scale, nullptr, want_of(o, D),
                                               false, st));
-        } else if (sizeof(T) == 4) {
-            KIFMM_TRY(blas_gemm_tn(o, s, nleaf, KD, (const float *)ops.l2p, (const float *)o->cd[D], (float *)Sp, st));
         } else {
             auto p = tap<T, T>(ops.l2p, 0, s, KD, (T *)o->cd[D], KD, Sp, s, SRC_SAME, 0, o->t_single, 1, nleaf, 0);
             p.out_need = want_of(o, D);
@@ -1621,6 +1655,7 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         }
     }
     KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
+    fj.side_forked = fj.fine_forked = false;   // both joined into st (the fine stream before L2L into level D)
     PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
     return launch_permute_out2<T>(*t, Sp, SpN, scale, want_of(o, D), S, st);
 }
@@ -1628,30 +1663,6 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
 }  // namespace
 
 extern "C" {
-
-// rocBLAS's workspace for the FP32 P2M and L2P: the two calls are run in rocBLAS's size-query
-// mode (nothing executes), and a buffer of the largest size they ask for is handed to the
-// handle, so that evaluations allocate nothing
-static int blas_reserve(kifmm_ops o, hipStream_t st) {
-    if (!o->blas || o->D < 2 || !o->p2m32 || !o->l2p32) return KIFMM_OK;
-    const int64_t nleaf = (int64_t)o->nb * o->nb * o->nb;
-    if (nleaf > INT32_MAX) return KIFMM_OK;   // evaluations refuse this size anyway
-    const float one = 1.f, zero = 0.f;
-    size_t need = 0;
-    if (rocblas_set_stream(o->blas, st) != rocblas_status_success ||
-        rocblas_start_device_memory_size_query(o->blas) != rocblas_status_success)
-        return fail(KIFMM_EHIP, "rocBLAS workspace query failed to start");
-    (void)rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, o->KU, (int)nleaf, o->s, &one,
-                        o->p2m32, o->s, (const float *)o->q, o->s, &zero, (float *)o->cu[o->D], o->KU);
-    (void)rocblas_sgemm(o->blas, rocblas_operation_transpose, rocblas_operation_none, o->s, (int)nleaf, o->KD, &one,
-                        o->l2p32, o->KD, (const float *)o->cd[o->D], o->KD, &zero, (float *)o->Sp, o->s);
-    if (rocblas_stop_device_memory_size_query(o->blas, &need) != rocblas_status_success)
-        return fail(KIFMM_EHIP, "rocBLAS workspace query failed");
-    KIFMM_TRY(dmalloc((char **)&o->blas_ws, need > 256 ? need : 256));
-    if (rocblas_set_workspace(o->blas, o->blas_ws, need > 256 ? need : 256) != rocblas_status_success)
-        return fail(KIFMM_EHIP, "rocblas_set_workspace failed");
-    return KIFMM_OK;
-}
 
 int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, const kifmm_opts *opts,
                                void *stream, kifmm_ops *out) {
@@ -1680,7 +1691,6 @@ int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, cons
     ops->kern = *kernel;
     ops->opts = o;
     int rc = build_ops(tree, ops, (hipStream_t)stream);
-    if (rc == KIFMM_OK) rc = blas_reserve(ops, (hipStream_t)stream);
     if (rc != KIFMM_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         free_ops(ops);
@@ -1761,6 +1771,12 @@ int kifmm_ops_p2p_fft(kifmm_ops ops, int32_t enable) {
         }
     }
     ops->p2p_fft = true;
+    return KIFMM_OK;
+}
+
+int kifmm_ops_serial(kifmm_ops ops, int32_t enable) {
+    if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
+    ops->serial = enable != 0;
     return KIFMM_OK;
 }
 

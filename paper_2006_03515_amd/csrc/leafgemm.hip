@@ -1,0 +1,248 @@
+// The two leaf-level translations fused with the permutes between grid order and
+// leaf order (FP32, leaves of 8^3 cells):
+//
+//   P2M (eq. (s2m) at the leaves) with the way in:
+//       q[leaf][cell] = h^3 I[grid cell]            (written: the near field reads it)
+//       c_u[leaf]     = A_p2m q[leaf]               A_p2m = U_u^T G(x^u, leaf cells), KU x 512
+//   L2P (algorithm outline step 4, far part) with the sum and the way out:
+//       S[grid cell]  = c (A_l2p c_d[leaf] + S_near[leaf][cell])   A_l2p = G(cells, y^d) V_d S^-1, 512 x KD
+//
+// Over all leaves each is one GEMM with a shared operator (K = 512 or KD), so a
+// workgroup takes 32 Morton-consecutive leaves (an aligned block of 2 x 4 x 4 leaves
+// along x, y, z) as the 32 columns of v_mfma_f32_32x32x2f32 tiles: the sources or the
+// coefficients of the block are staged once in LDS, and each wave streams the operator
+// rows of its 32-row tiles from L2 in MFMA fragment order (one contiguous 1 KB read per
+// wave and 8-wide reduction chunk; the fragments are packed once at precompute).  The
+// values cross HBM once: I in and q, c_u out for the way in; c_d, S_near in and S out
+// for the way out.
+//
+// Fragment order of an operator A (rows x cols, row-major) for tile t (rows 32t ..
+// 32t + 31) and chunk c (columns 8c .. 8c + 7): lane l = 32 h + r holds the float4
+// A[32t + r][8c + 4h .. 8c + 4h + 3].  Its j-th component is the A operand of the j-th
+// of four MFMA steps, whose B operand is component j of the float4 B[8c + 4h ..][col],
+// so the four steps sum the chunk's 8 products (in a permuted order of the reduction
+// index, the same for A and B).
+#include "common.h"
+
+namespace kifmm {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kLeafBlock = 32;    // leaves per workgroup
+constexpr int kQRow = 129;        // LDS row of a leaf's sources: 128 float4 + 1 pad
+
+__device__ inline float4 scaled(float4 v, float s) { return make_float4(v.x * s, v.y * s, v.z * s, v.w * s); }
+
+// Morton offset (0..31) inside the block of leaf (dx, dy, dz), dx < 2, dy < 4, dz < 4: the
+// block's codes differ in their five lowest bits, z0 y0 x0 z1 y1 from the least significant
+__device__ inline int block_code(int dx, int dy, int dz) {
+    return (dz & 1) | ((dy & 1) << 1) | (dx << 2) | ((dz >> 1) << 3) | ((dy >> 1) << 4);
+}
+__device__ inline void block_leaf(int m, int &dx, int &dy, int &dz) {
+    dz = (m & 1) | (((m >> 3) & 1) << 1);
+    dy = ((m >> 1) & 1) | (((m >> 4) & 1) << 1);
+    dx = (m >> 2) & 1;
+}
+
+__device__ inline floatx16 mfma4(const float4 &a, const float4 &b, floatx16 acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+    return acc;
+}
+
+// fragments[(t * nchunk + c) * 64 + l] = A[32t + l % 32][8c + 4(l / 32) .. + 3]; rows and
+// columns past the operator's size are zero
+__global__ void pack_fragments_kernel(const float *__restrict__ A, int rows, int cols, int lda, int ntile,
+                                      int nchunk, float4 *__restrict__ frag) {
+    const int64_t total = (int64_t)ntile * nchunk * 64;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(e & 63);
+        const int64_t tc = e >> 6;
+        const int c = (int)(tc % nchunk), t = (int)(tc / nchunk);
+        const int r = 32 * t + (l & 31), k0 = 8 * c + 4 * (l >> 5);
+        float v[4];
+        for (int j = 0; j < 4; ++j) v[j] = (r < rows && k0 + j < cols) ? A[(int64_t)r * lda + k0 + j] : 0.f;
+        frag[e] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// Way in + P2M.  Grid: one workgroup per block of 32 leaves (nleaf / 32 workgroups).
+// n % 32 == 0, ntile = KU / 32 row tiles of A (fragments of 64 chunks of 8 columns).
+__global__ __launch_bounds__(256, 2) void p2m_permute_in_kernel(const float *__restrict__ I, int n, float vol,
+                                                                const float4 *__restrict__ Af, int ntile, int KU,
+                                                                float *__restrict__ q, float *__restrict__ cu) {
+    __shared__ float4 Qs[kLeafBlock * kQRow];
+    const uint32_t g = blockIdx.x;
+    int bx, by, bz;
+    morton_decode(g << 5, bx, by, bz);
+    const int tid = threadIdx.x;
+    // the block's cells: 16 x 32 grid rows (i, j) of 32 cells along k (4 leaves' lines);
+    // one thread reads a row's 128 contiguous bytes
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        const int r = tid + 256 * rr;
+        const int ii = r >> 5, jj = r & 31;
+        const float4 *src = (const float4 *)(I + ((int64_t)((bx << 3) + ii) * n + (by << 3) + jj) * n + (bz << 3));
+        const int local = ((ii & 7) * 8 + (jj & 7)) * 8;   // first cell of the line in its leaf
+        float4 v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = scaled(src[c], vol);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int m = block_code(ii >> 3, jj >> 3, c);
+            float4 *dq = (float4 *)(q + ((int64_t)((g << 5) + m) << 9) + local);
+            dq[0] = v[2 * c];
+            dq[1] = v[2 * c + 1];
+            Qs[m * kQRow + (local >> 2)] = v[2 * c];
+            Qs[m * kQRow + (local >> 2) + 1] = v[2 * c + 1];
+        }
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
+    const float4 *bq = Qs + col * kQRow + h;
+    for (int t = wave; t < ntile; t += 4) {
+        const float4 *af = Af + (int64_t)t * 64 * 64 + lane;
+        floatx16 acc;
+        double tot[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { acc[v] = 0.f; tot[v] = 0.0; }
+        // 64 chunks in 8 groups of 8; the next group's operator fragments are loaded while
+        // one group is multiplied.  FP32 MFMA partials are folded into FP64 every 16 chunks
+        // (128 products per FP32 chain).
+        float4 a[8], an[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[c] = af[c * 64];
+#pragma unroll 1
+        for (int grp = 0; grp < 8; ++grp) {
+            if (grp < 7) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) an[c] = af[((grp + 1) * 8 + c) * 64];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc = mfma4(a[c], bq[2 * (grp * 8 + c)], acc);
+            if (grp & 1) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) { tot[v] += (double)acc[v]; acc[v] = 0.f; }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[c] = an[c];
+        }
+        // D layout of 32x32x2: lane holds column lane % 32 and, in registers 4g .. 4g + 3,
+        // rows 8g + 4 (lane / 32) + 0..3
+        float *o = cu + (int64_t)((g << 5) + col) * KU + 32 * t + 4 * h;
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg)
+            *(float4 *)(o + 8 * gg) = make_float4((float)tot[4 * gg], (float)tot[4 * gg + 1], (float)tot[4 * gg + 2],
+                                                  (float)tot[4 * gg + 3]);
+    }
+}
+
+// L2P + sum with the near field + way out.  Grid: one workgroup per block of 32 leaves.
+// KD % 8 == 0, KD <= 256; the operator has 512 rows (16 tiles), wave w takes the cells
+// 128 w .. 128 w + 127 of every leaf of the block (tiles 4w .. 4w + 3).
+__global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__restrict__ cd, int KD,
+                                                                 const float4 *__restrict__ Lf,
+                                                                 const float *__restrict__ Snear, int n, float scale,
+                                                                 const uint8_t *__restrict__ want, float *__restrict__ S) {
+    __shared__ float4 Cs[kLeafBlock * 65];
+    const int crow = KD / 4 + 1;
+    const uint32_t g = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nchunk = KD / 8;
+    for (int e = tid; e < kLeafBlock * (KD / 4); e += 256) {
+        const int m = e / (KD / 4), k4 = e % (KD / 4);
+        Cs[m * crow + k4] = ((const float4 *)(cd + (int64_t)((g << 5) + m) * KD))[k4];
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
+    const float4 *bc = Cs + col * crow + h;
+    floatx16 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+    const float4 *lf = Lf + (int64_t)(4 * wave) * nchunk * 64 + lane;
+    // the next chunk's operator fragments are loaded while one chunk is multiplied
+    float4 a[4], an[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = lf[(int64_t)i * nchunk * 64];
+    for (int c = 0; c < nchunk; ++c) {
+        if (c + 1 < nchunk) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) an[i] = lf[((int64_t)i * nchunk + c + 1) * 64];
+        }
+        const float4 b = bc[2 * c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = mfma4(a[i], b, acc[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = an[i];
+    }
+    // column col of the tiles is leaf 32 g + col
+    const int leaf = (int)(g << 5) + col;
+    int bx, by, bz, dx, dy, dz;
+    morton_decode(g << 5, bx, by, bz);
+    block_leaf(col, dx, dy, dz);
+    const bool keep = !want || want[leaf];
+    const float *sn = Snear + ((int64_t)leaf << 9);
+    float *base = S + ((int64_t)((bx + dx) << 3) * n + ((by + dy) << 3)) * n + ((bz + dz) << 3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+            // cells c .. c + 3 of the leaf (C order x, y, z inside it): one half z-line
+            const int c = 128 * wave + 32 * i + 8 * gg + 4 * h;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (keep) {
+                const float4 s = *(const float4 *)(sn + c);
+                v = make_float4((acc[i][4 * gg] + s.x) * scale, (acc[i][4 * gg + 1] + s.y) * scale,
+                                (acc[i][4 * gg + 2] + s.z) * scale, (acc[i][4 * gg + 3] + s.w) * scale);
+            }
+            *(float4 *)(base + ((int64_t)(c >> 6) * n + ((c >> 3) & 7)) * n + (c & 7)) = v;
+        }
+}
+
+}  // namespace
+
+// Operator fragments for the fused kernels: rows x cols (row-major, leading dimension
+// lda) into ceil(rows / 32) tiles of ceil(cols / 8) chunks.
+int launch_pack_fragments(const float *A, int rows, int cols, int lda, float4 *frag, hipStream_t st) {
+    const int ntile = (rows + 31) / 32, nchunk = (cols + 7) / 8;
+    const int64_t total = (int64_t)ntile * nchunk * 64;
+    hipLaunchKernelGGL(pack_fragments_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, rows, cols,
+                       lda, ntile, nchunk, frag);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+// The fused kernels apply to FP32 evaluations on leaves of 8^3 cells with at least 4 leaves
+// per axis (n % 32 == 0), 16-byte aligned fields, KU % 32 == 0 and KD % 8 == 0, KD <= 256.
+bool leafgemm_fits(const Tree &t, int KU, int KD) {
+    return t.ell == 8 && t.n % 32 == 0 && t.nb >= 4 && KU % 32 == 0 && KU > 0 && KD % 8 == 0 && KD > 0 &&
+           KD <= 256;
+}
+
+int run_p2m_permute_in(const Tree &t, const float *I, float vol, const float4 *Af, int KU, float *q, float *cu,
+                       hipStream_t st) {
+    if ((uintptr_t)I % 16 || (uintptr_t)q % 16 || (uintptr_t)cu % 16) return fail(KIFMM_EINVAL, "fused P2M: misaligned buffer");
+    const int64_t nblk = (int64_t)t.nb * t.nb * t.nb / kLeafBlock;
+    hipLaunchKernelGGL(p2m_permute_in_kernel, dim3((unsigned)nblk), dim3(256), 0, st, I, t.n, vol, Af, KU / 32, KU, q,
+                       cu);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int run_l2p_permute_out(const Tree &t, const float *cd, int KD, const float4 *Lf, const float *Snear, float scale,
+                        const uint8_t *want, float *S, hipStream_t st) {
+    if ((uintptr_t)S % 16 || (uintptr_t)cd % 16 || (uintptr_t)Snear % 16) return fail(KIFMM_EINVAL, "fused L2P: misaligned buffer");
+    const int64_t nblk = (int64_t)t.nb * t.nb * t.nb / kLeafBlock;
+    hipLaunchKernelGGL(l2p_permute_out_kernel, dim3((unsigned)nblk), dim3(256), 0, st, cd, KD, Lf, Snear, t.n, scale,
+                       want, S);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+}  // namespace kifmm

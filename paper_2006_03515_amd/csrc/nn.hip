@@ -290,6 +290,28 @@ __global__ void sampled_err_kernel(int64_t nt, const float *__restrict__ S, cons
     if (threadIdx.x == 0) out[0] = c > 0 ? sqrt(a / c) : 0.0;
 }
 
+// x *= s
+__global__ void scale_kernel(int64_t n, float *__restrict__ x, float s) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] *= s;
+}
+
+// out[0] = ||S[tgt] - R[tgt]|| / ||R[tgt]|| (two FP32 fields compared at the targets)
+__global__ void sampled_diff_kernel(int64_t nt, const float *__restrict__ S, const float *__restrict__ R,
+                                    const int64_t *__restrict__ tgt, double *__restrict__ out) {
+    __shared__ double sh[4];
+    double a = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < nt; i += blockDim.x) {
+        const double r = (double)R[tgt[i]];
+        const double d = (double)S[tgt[i]] - r;
+        a += d * d;
+        c += r * r;
+    }
+    a = block_sum_d(a, sh);
+    c = block_sum_d(c, sh);
+    if (threadIdx.x == 0) out[0] = c > 0 ? sqrt(a / c) : 0.0;
+}
+
 int pack(int x, int y, int z) { return ((x + 16) << 10) | ((y + 16) << 5) | (z + 16); }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -550,6 +572,22 @@ int kifmm_nn_sampled_rel_err(int64_t n_tgt, const float *S, const int64_t *tgt, 
                              double *out, void *stream) {
     if (n_tgt < 1 || !S || !tgt || !ref || !out) return fail(KIFMM_EINVAL, "bad argument");
     hipLaunchKernelGGL(sampled_err_kernel, dim3(1), dim3(kT), 0, (hipStream_t)stream, n_tgt, S, tgt, ref, scale, out);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int kifmm_nn_scale(int64_t n, float *x, float s, void *stream) {
+    if (n < 0 || (n > 0 && !x)) return fail(KIFMM_EINVAL, "bad argument");
+    if (n == 0) return KIFMM_OK;
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks(n)), dim3(kT), 0, (hipStream_t)stream, n, x, s);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int kifmm_nn_sampled_rel_diff(int64_t n_tgt, const float *S, const float *R, const int64_t *tgt, double *out,
+                              void *stream) {
+    if (n_tgt < 1 || !S || !R || !tgt || !out) return fail(KIFMM_EINVAL, "bad argument");
+    hipLaunchKernelGGL(sampled_diff_kernel, dim3(1), dim3(kT), 0, (hipStream_t)stream, n_tgt, S, R, tgt, out);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }

@@ -26,11 +26,12 @@ EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "
            "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_tree_destroy",
            "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read",
            "kifmm_ops_skip_zero_sources", "kifmm_ops_restrict_targets", "kifmm_ops_m2l_fft",
-           "kifmm_ops_p2p_fft",
+           "kifmm_ops_p2p_fft", "kifmm_ops_serial",
            "kifmm_nn_layer_forward", "kifmm_nn_layer_backward_data", "kifmm_nn_layer_backward_weight",
            "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
            "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
-           "kifmm_nn_max_abs", "kifmm_nn_coarsen2", "kifmm_nn_upsample2", "kifmm_nn_sampled_rel_err")
+           "kifmm_nn_max_abs", "kifmm_nn_coarsen2", "kifmm_nn_upsample2", "kifmm_nn_sampled_rel_err",
+           "kifmm_nn_sampled_rel_diff", "kifmm_nn_scale")
 NN_CONV3, NN_DOWN2, NN_UP2, NN_POINT = 0, 1, 2, 3
 NN_TAPS = {NN_CONV3: 27, NN_DOWN2: 8, NN_UP2: 8, NN_POINT: 1}
 PASSES = ("permute_in", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "permute_out", "near_products")
@@ -82,6 +83,7 @@ def load_library(path=LIB_PATH):
     lib.kifmm_ops_restrict_targets.argtypes = [P, P]
     lib.kifmm_ops_m2l_fft.argtypes = [P, ctypes.c_int32]
     lib.kifmm_ops_p2p_fft.argtypes = [P, ctypes.c_int32]
+    lib.kifmm_ops_serial.argtypes = [P, ctypes.c_int32]
     I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     nn = {
         "kifmm_nn_layer_forward": [I32, I32, I32, P, I32, P, I32, P, I32, I32, P, I64, P],
@@ -98,6 +100,8 @@ def load_library(path=LIB_PATH):
         "kifmm_nn_coarsen2": [I32, I32, P, P, P],
         "kifmm_nn_upsample2": [I32, I32, P, P, P],
         "kifmm_nn_sampled_rel_err": [I64, P, P, P, F64, P, P],
+        "kifmm_nn_sampled_rel_diff": [I64, P, P, P, P, P],
+        "kifmm_nn_scale": [I64, P, F32, P],
     }
     for f, a in nn.items():
         getattr(lib, f).argtypes = a
@@ -206,6 +210,11 @@ class Ops:
     def p2p_fft(self, enable=True):
         """Near field in Fourier space (leaves of 8^3) or the dense near field."""
         _check(_lib.kifmm_ops_p2p_fft(self.handle, 1 if enable else 0))
+
+    def serial(self, enable=True):
+        """Run every pass of eval() on the calling stream in order (per-kernel timings
+        without overlap; the same results bit for bit)."""
+        _check(_lib.kifmm_ops_serial(self.handle, 1 if enable else 0))
 
     def restrict_targets(self, leaf_mask=None):
         """Evaluate only at the leaves marked in leaf_mask (array of nb^3 values, C order

@@ -44,8 +44,9 @@ def test_config2_128_two_heads(K, p, record_property):
     e32, e64 = _err(S["fp32"], ref, tg), _err(S["fp64"], ref, tg)
     record_property("rel_l2_fp32", e32)
     print("config 2, %g Torr, nested m0=8: fp32 %.3e fp64 %.3e" % (p, e32, e64))
-    assert e64 < 5e-6
-    assert e32 < 5e-6
+    # the benchmark spec's FP32 bar (measured 2.8e-7 / 5.3e-7 at 760 / 100 Torr)
+    assert e64 < 1e-6
+    assert e32 < 1e-6
 
 
 @pytest.mark.parametrize("p", [760.0, 100.0, 10.0])

@@ -20,10 +20,13 @@ def K():
     return kifmm
 
 
-@pytest.mark.parametrize("prec,m2l_fft,near_fft", [("fp32", True, True), ("bf16x3", True, True),
-                                                   ("fp32", False, False)])
-def test_graph_replay_is_the_eager_evaluation(K, prec, m2l_fft, near_fft):
-    n, L, p_o2 = 64, 0.1, 150.0
+@pytest.mark.parametrize("n,prec,m2l_fft,near_fft", [(64, "fp32", True, True), (64, "bf16x3", True, True),
+                                                     (64, "fp32", False, False),
+                                                     # depth 4: the coarse levels' M2L on the near
+                                                     # field's stream, gated by per-level events
+                                                     (128, "fp32", True, True), (128, "bf16x3", True, True)])
+def test_graph_replay_is_the_eager_evaluation(K, n, prec, m2l_fft, near_fft):
+    L, p_o2 = 0.1 * n / 64, 150.0
     I = np.random.default_rng(71).random((n, n, n)).astype(np.float32)
     tree = K.build_tree(K.Grid.cube(n, L), 512)
     ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
@@ -54,3 +57,23 @@ def test_graph_replay_is_the_eager_evaluation(K, prec, m2l_fft, near_fft):
     exact = odirect.fft_full(I.astype(np.float64), (L / n,) * 3, p_o2).ravel()
     assert rel_l2(S.double().cpu().numpy(), exact) < 1e-4
     del g
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_serial_schedule_is_the_concurrent_evaluation(K, prec):
+    # every pass on the calling stream in order (the measurement schedule) runs the same
+    # kernels on the same data: the same field bit for bit
+    n, L, p_o2 = 128, 0.2, 150.0
+    I = np.random.default_rng(72).random((n, n, n))
+    tree = K.build_tree(K.Grid.cube(n, L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    ops.p2p_fft(prec != "fp64")
+    It = torch.from_numpy(I.ravel()).cuda()
+    It = It if prec == "fp64" else It.float()
+    a = K.eval(tree, ops, It, 1.0, precision=prec)
+    ops.serial(True)
+    b = K.eval(tree, ops, It, 1.0, precision=prec)
+    ops.serial(False)
+    c = K.eval(tree, ops, It, 1.0, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)

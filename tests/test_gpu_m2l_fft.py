@@ -57,10 +57,14 @@ def test_fft_m2l_is_the_dense_m2l(K, g32, p_o2):
     ora = kifmm_ref.evaluate(I, L, p_o2, ell=4, layout="lattice", m0=5, rcond=1e-7)
     a = run(K, tree, ops, I, "fp32", True)
     b = run(K, tree, ops, I, "fp32", False)
-    assert rel_l2(a, b) < 2e-6
-    assert rel_l2(a, ora) < 2e-6
+    # FP32 FFT form against the oracle's FMM of the same layout: the benchmark spec's 1e-6
+    # (measured 1.0e-7 at 150 Torr, 1.7e-7 at 1.974 Torr; the dense form 1.0-1.1e-7)
+    assert rel_l2(a, b) < 1e-6
+    assert rel_l2(a, ora) < 1e-6
+    assert rel_l2(b, ora) < 1e-6
+    # split BF16 products (about 16 mantissa bits per operand): measured 0.9-1.1e-6
     c = run(K, tree, ops, I, "bf16x3", True)
-    assert rel_l2(c, ora) < 1e-5
+    assert rel_l2(c, ora) < 5e-6
 
 
 @pytest.mark.parametrize("m0", [3, 4, 6, 7, 8])
@@ -83,13 +87,14 @@ def test_fft_m2l_deep_tree_random_sources(K):
     tree, ops = setup(K, n, L, p_o2, 512, rcond=1e-5)
     ora = kifmm_ref.evaluate(I, L, p_o2, ell=8, layout="lattice", m0=5, rcond=1e-5)
     a = run(K, tree, ops, I, "fp32", True)
-    assert rel_l2(a, ora) < 2e-6
+    assert rel_l2(a, ora) < 1e-6          # measured 1.3e-7
     ref = odirect.fft_full(I, (L / n,) * 3, p_o2)
     assert rel_l2(a, ref) < 1e-4
     # split-BF16 parent-pair products (levels 3 and 4): about 16 mantissa bits per operand
+    # (measured 3.6e-7 from the oracle's FMM)
     c = run(K, tree, ops, I, "bf16x3", True)
-    assert rel_l2(c, ora) < 1e-5
-    assert rel_l2(c, a) < 1e-5
+    assert rel_l2(c, ora) < 2e-6
+    assert rel_l2(c, a) < 2e-6
 
 
 def test_fft_m2l_with_skipping_and_restriction(K):

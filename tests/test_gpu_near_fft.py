@@ -5,6 +5,7 @@ import pytest
 import torch
 
 from oracle import direct as odirect
+from oracle import metrics
 from paper_2006_03515_amd import embedding, workloads
 from tests.gpu_common import rel_l2
 
@@ -102,16 +103,20 @@ def test_bright_sources_on_fine_cells_stay_finite(K):
     assert rel_l2(b, ref) < 1e-4
 
 
-def test_benchmark_configuration_against_the_oracle(K, record_property):
-    # exactly what bench.py times: 256^3 channel at 760 Torr, lattice layout R = 1.0, M2L in
-    # its FFT form, near field in Fourier space, FP32; against the oracle's exact field (its
-    # FFT form, checked at sampled cells against its one-target-at-a-time direct sum), over
-    # the whole field and at bench.py's 4,096 cells (seed 1009).  A rel-L2 over few random
-    # cells weighs the dim background, where the method's relative error is largest.
-    w = workloads.streamer_channel(n=256, L=0.4, p=760.0)
+@pytest.mark.parametrize("p,R", [(760.0, 1.2), (100.0, 1.2), (10.0, 1.2), (760.0, 1.0)])
+def test_benchmark_configuration_against_the_oracle(K, p, R, record_property):
+    # exactly what bench.py times: the 256^3 channel, lattice layout (R = 1.2, the library
+    # default, at each of the three pressures; R = 1.0 at 760 Torr), M2L in its FFT form,
+    # near field in Fourier space, FP32; against the oracle's exact field (its FFT form,
+    # checked at sampled cells against its one-target-at-a-time direct sum).  Bounds: the
+    # whole field, bench.py's 4,096 cells (seed 1009), every leaf's own rel-L2 (an error
+    # confined to a few dim leaves would hide in the whole-field norm: the worst leaves are
+    # the background at the domain's faces, 0.7-3e-3 measured) and E_delta of eq.
+    # (relativefun) within 5 sigma of the head.
+    w = workloads.streamer_channel(n=256, L=0.4, p=p)
     I = np.ascontiguousarray(w.I.astype(np.float32).ravel())
     tree = K.build_tree(K.Grid.cube(256, w.L), 512)
-    ops = K.precompute_operators(tree, K.Kernel(w.p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    ops = K.precompute_operators(tree, K.Kernel(w.p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, R))
     ops.m2l_fft(True)
     ops.p2p_fft(True)
     S = K.eval(tree, ops, torch.from_numpy(I).cuda(), w.prefactor).double().cpu().numpy()
@@ -121,14 +126,30 @@ def test_benchmark_configuration_against_the_oracle(K, record_property):
     d = odirect.direct_targets(I3, (w.h,) * 3, w.p_o2, t64, prefactor=w.prefactor)
     assert np.max(np.abs(ref[t64] / d - 1)) < 1e-10
     tg = workloads.sample_targets(256 ** 3, 4096, seed=1009)
-    full, samp = rel_l2(S, ref), rel_l2(S[tg], ref[tg])
-    record_property("rel_l2_full", full)
-    record_property("rel_l2_sampled", samp)
-    print("benchmark configuration: full field %.2e, 4,096 cells %.2e" % (full, samp))
-    assert full < 3e-5 and samp < 1e-4
+
+    def bounds(X):
+        dS = (X - ref).reshape(32, 8, 32, 8, 32, 8)
+        rS = ref.reshape(32, 8, 32, 8, 32, 8)
+        leaf = np.sqrt((dS ** 2).sum(axis=(1, 3, 5)) / (rS ** 2).sum(axis=(1, 3, 5)))
+        c = (np.arange(256) + 0.5) * w.h
+        x0, delta = (0.2, 0.2, 0.35), 5 * 0.008          # the head (sigma 0.008 cm)
+        sub = tuple(slice(int(np.nonzero(np.abs(c - x0[a]) <= delta)[0][0]),
+                          int(np.nonzero(np.abs(c - x0[a]) <= delta)[0][-1]) + 1) for a in range(3))
+        cen = np.stack(np.meshgrid(*[c[s] for s in sub], indexing="ij"), -1)
+        ed = metrics.e_delta(X.reshape(256, 256, 256)[sub], ref.reshape(256, 256, 256)[sub], cen, x0, delta)
+        return rel_l2(X, ref), rel_l2(X[tg], ref[tg]), float(leaf.max()), ed
+
+    full, samp, leaf, ed = bounds(S)
+    for k, v in (("rel_l2_full", full), ("rel_l2_sampled", samp), ("max_leaf_rel_l2", leaf), ("E_delta_head", ed)):
+        record_property(k, v)
+    print("benchmark configuration %g Torr R %.1f: full field %.2e, 4,096 cells %.2e, worst leaf %.2e, "
+          "E_delta(head) %.2e" % (p, R, full, samp, leaf, ed))
+    assert full < 6e-5 and samp < 1e-4
+    assert leaf < 5e-3 and ed < 2e-4
     # the mixed-precision form the bench reports beside it (split-BF16 M2L products):
     # within 1e-5 of the FP32 evaluation, and the same bars against the exact field
     Sx = K.eval(tree, ops, torch.from_numpy(I).cuda(), w.prefactor, precision="bf16x3").double().cpu().numpy()
     record_property("rel_l2_bf16x3_vs_fp32", rel_l2(Sx, S))
     assert rel_l2(Sx, S) < 1e-5
-    assert rel_l2(Sx, ref) < 3e-5 and rel_l2(Sx[tg], ref[tg]) < 1e-4
+    fx, sx, lx, ex = bounds(Sx)
+    assert fx < 6e-5 and sx < 1e-4 and lx < 5e-3 and ex < 2e-4

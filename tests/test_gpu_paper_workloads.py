@@ -1,11 +1,12 @@
-"""The paper's Section 4.1 workload at full size (320 x 320 x 160 cells, 16.4 M points),
-evaluated inside a 512^3 cube, against the oracle's exact sum in FFT form: the global and
-local relative errors E_V and E_delta of eq. (relativefun)."""
+"""The paper's Section 4.1 (cases 1 and 2) and Section 4.3 workloads at full size (320 x 320
+x 160 cells, 16.4 M points), evaluated inside a 512^3 cube, against the oracle's exact sum in
+FFT form: the global and local relative errors E_V and E_delta of eq. (relativefun)."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import direct as odirect
+from oracle import metrics
 from paper_2006_03515_amd import embedding, workloads
 
 pytestmark = pytest.mark.gpu
@@ -18,14 +19,18 @@ def K():
 
 
 def paper_errors(num, ref, w):
-    """E_V (over all cells) and E_delta(x0) (mean relative error over the cells within
-    delta of x0), both as fractions."""
-    ev = float(np.linalg.norm(num - ref) / np.linalg.norm(ref))
-    cx, cy, cz = [(np.arange(m) + 0.5) * w.h for m in w.shape]
-    d2 = ((cx[:, None, None] - w.x0[0]) ** 2 + (cy[None, :, None] - w.x0[1]) ** 2
-          + (cz[None, None, :] - w.x0[2]) ** 2)
-    ball = d2 <= w.delta ** 2
-    ed = float(np.mean(np.abs(num[ball] - ref[ball]) / ref[ball]))
+    """E_V over all cells and E_delta(x0) of eq. (relativefun) (oracle.metrics), as
+    fractions.  E_delta is taken over the block of cells whose centres lie within delta
+    of x0 along every axis, which holds every cell of the ball."""
+    ev = metrics.rel_l2(num, ref)
+    sl, cs = [], []
+    for a, m in enumerate(w.shape):
+        c = (np.arange(m) + 0.5) * w.h
+        idx = np.nonzero(np.abs(c - w.x0[a]) <= w.delta)[0]
+        sl.append(slice(idx[0], idx[-1] + 1))
+        cs.append(c[sl[-1]])
+    cen = np.stack(np.meshgrid(*cs, indexing="ij"), -1)
+    ed = metrics.e_delta(num[tuple(sl)], ref[tuple(sl)], cen, w.x0, w.delta)
     return ev, ed
 
 
@@ -46,24 +51,47 @@ def test_embedding_in_a_cube_is_exact(K):
     np.testing.assert_allclose(got, ref, rtol=1e-12)
 
 
-def test_section41_gaussian_full_size(K, record_property):
-    w = workloads.paper_gaussian(1)
+# (workload, paper layout bars, nested layout bars), each bar (E_V, E_delta).  The paper's
+# own figures at m0 = 6 (Tables 3, 4, 7): E_V 0.21 / 0.22 / 0.69 %, E_delta 1.30 / 0.53 /
+# 0.82 %; its layout here (radii not given in the text) lands at the same order.
+PAPER_CASES = [
+    ("section41_case1", (2e-2, 3e-2), (1e-4, 2e-4)),
+    ("section41_case2", (2e-2, 3e-2), (1e-4, 2e-4)),
+    ("section43_multipeak", (3e-2, 3e-2), (1e-4, 2e-4)),
+]
+
+
+def _paper_workload(name):
+    if name == "section43_multipeak":
+        return workloads.paper_multipeak()
+    return workloads.paper_gaussian(1 if name.endswith("1") else 2)
+
+
+@pytest.mark.parametrize("name,paper_bars,nested_bars", PAPER_CASES)
+def test_section4_workloads_full_size(K, name, paper_bars, nested_bars, record_property):
+    # Section 4.1 cases 1 and 2 (Tables 3, 4) and Section 4.3 (Table 7): 320 x 320 x 160
+    # cells inside a 512^3 cube, the padding's sources skipped and the targets restricted
+    # to the box's leaves (neither changes a value at the box's cells)
+    w = _paper_workload(name)
+    print("case %s" % name, flush=True)
     ref = odirect.fft_full(w.S_i.astype(np.float64), (w.h,) * 3, w.p_o2, prefactor=w.prefactor, workers=16)
     n = embedding.cube_side(w.shape)
     tree = K.build_tree(K.Grid.cube(n, n * w.h), 512)
     I = embedding.embed(torch.from_numpy(w.S_i).cuda(), w.shape)
     kern = K.Kernel(w.p_o2)
-    # the paper's own layout (one surface each, m0 = 6) and this build's nested layout
-    cases = (("paper_m0_6", K.Opts(K.LAYOUT_PAPER, 6, 10, 1e-7), 1e-2),
-             ("nested_m0_5", K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), 1e-4))
-    for name, opts, bar in cases:
+    cases = (("paper_m0_6", K.Opts(K.LAYOUT_PAPER, 6, 10, 1e-7), paper_bars),
+             ("nested_m0_5", K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), nested_bars))
+    for lname, opts, (bar_v, bar_d) in cases:
         ops = K.precompute_operators(tree, kern, opts)
+        ops.skip_zero_sources(True)
+        ops.restrict_targets(embedding.leaf_mask(w.shape, n, tree.leaf_side))
         S = K.eval(tree, ops, I, w.prefactor, precision=K.FP32)
         num = embedding.extract(S, w.shape).double().cpu().numpy()
         ev, ed = paper_errors(num, ref, w)
-        record_property(name, {"E_V": ev, "E_delta": ed})
-        print("%s: E_V %.3e  E_delta %.3e" % (name, ev, ed), flush=True)
-        assert ev < bar
+        record_property(lname, {"E_V": ev, "E_delta": ed})
+        print("%s %s: E_V %.3e  E_delta %.3e" % (name, lname, ev, ed), flush=True)
+        assert ev < bar_v, (lname, ev)
+        assert ed < bar_d, (lname, ed)
         del ops
 
 
