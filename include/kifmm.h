@@ -338,6 +338,20 @@ int kifmm_nn_unpack_output(int32_t batch, int32_t n, const float *y, int32_t ld,
 /* out[s] = max |x_s| over per_sample values, or its reciprocal (1 for a zero field) */
 int kifmm_nn_max_abs(int32_t batch, int64_t per_sample, const float *x, float *out, int32_t reciprocal,
                      float *work, int64_t work_floats, void *stream);
+/* kifmm_nn_max_abs for callers that cannot allocate device memory (code under stream
+ * capture, serving loops that must not call hipMalloc): the same result, with the
+ * per-block partial maxima kept in a static device array of KIFMM_NN_MAX_ABS_SCRATCH
+ * floats (1 MiB) instead of a caller's workspace.  Each GPU the library runs on holds its
+ * own copy of that array until the process ends; its address on a device is looked up
+ * (hipGetSymbolAddress) on the first call made with that device current.  Nothing is
+ * allocated.  batch * min(256, ceil(per_sample / 256)) must not exceed
+ * KIFMM_NN_MAX_ABS_SCRATCH, else KIFMM_EINVAL before any device work.  All calls on one GPU
+ * share the array and leave their partial maxima in it: calls that overlap on one GPU
+ * (other streams, other host threads) race and must be ordered by the caller.  Returns 0,
+ * KIFMM_EINVAL or KIFMM_EHIP. */
+#define KIFMM_NN_MAX_ABS_SCRATCH 262144
+int kifmm_nn_max_abs_noalloc(int32_t batch, int64_t per_sample, const float *x, float *out, int32_t reciprocal,
+                             void *stream);
 /* 2x2x2 block means of a (2 n_coarse)^3 grid-ordered field */
 int kifmm_nn_coarsen2(int32_t batch, int32_t n_coarse, const float *fine, float *coarse, void *stream);
 /* trilinear interpolation from cell centres of an n_coarse^3 field to those of the

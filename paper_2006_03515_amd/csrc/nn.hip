@@ -13,6 +13,7 @@
 // weights (CONV3 with negated offsets, DOWN2 <-> UP2).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -546,6 +547,57 @@ int kifmm_nn_max_abs(int32_t batch, int64_t per_sample, const float *x, float *o
     hipLaunchKernelGGL(max_abs_partial_kernel, dim3(nblk, batch), dim3(kT), 0, st, per_sample, x, nblk, work);
     KIFMM_HIP(hipGetLastError());
     hipLaunchKernelGGL(max_abs_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, batch, nblk, work, out,
+                       reciprocal);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ max |x| without a workspace --
+// The partial maxima of kifmm_nn_max_abs_noalloc go to this file-scope device array
+// instead of a caller's workspace.  Each GPU holds its own copy; host code reaches it only
+// through the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float scratch[KIFMM_NN_MAX_ABS_SCRATCH];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<float *> g_scratch_ptr;   // per device ordinal, null until looked up
+
+// device address of `scratch` on the current device, looked up once per device
+int scratch_ptr(float **out) {
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= (int)g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        float *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KIFMM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int kifmm_nn_max_abs_noalloc(int32_t batch, int64_t per_sample, const float *x, float *out, int32_t reciprocal,
+                             void *stream) {
+    if (batch < 1 || per_sample < 1 || !x || !out) return fail(KIFMM_EINVAL, "bad argument");
+    const int nblk = (int)std::min<int64_t>(256, (per_sample + 255) / 256);
+    if ((int64_t)batch * nblk > KIFMM_NN_MAX_ABS_SCRATCH)
+        return fail(KIFMM_EINVAL, "batch * blocks exceeds the static scratch (" +
+                                      std::to_string(KIFMM_NN_MAX_ABS_SCRATCH) + " floats)");
+    float *part = nullptr;
+    KIFMM_TRY_(scratch_ptr(&part));
+    hipStream_t st = (hipStream_t)stream;
+    // every entry read by the final kernel is written by the partial kernel first: nothing
+    // of a previous call's contents is read
+    hipLaunchKernelGGL(max_abs_partial_kernel, dim3(nblk, batch), dim3(kT), 0, st, per_sample, x, nblk, part);
+    KIFMM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(max_abs_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, batch, nblk, part, out,
                        reciprocal);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;

@@ -31,7 +31,8 @@ EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "
            "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
            "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
            "kifmm_nn_max_abs", "kifmm_nn_coarsen2", "kifmm_nn_upsample2", "kifmm_nn_sampled_rel_err",
-           "kifmm_nn_sampled_rel_diff", "kifmm_nn_scale")
+           "kifmm_nn_sampled_rel_diff", "kifmm_nn_scale",
+           "kifmm_nn_max_abs_noalloc")
 NN_CONV3, NN_DOWN2, NN_UP2, NN_POINT = 0, 1, 2, 3
 NN_TAPS = {NN_CONV3: 27, NN_DOWN2: 8, NN_UP2: 8, NN_POINT: 1}
 PASSES = ("permute_in", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "permute_out", "near_products")
@@ -102,6 +103,7 @@ def load_library(path=LIB_PATH):
         "kifmm_nn_sampled_rel_err": [I64, P, P, P, F64, P, P],
         "kifmm_nn_sampled_rel_diff": [I64, P, P, P, P, P],
         "kifmm_nn_scale": [I64, P, F32, P],
+        "kifmm_nn_max_abs_noalloc": [I32, I64, P, P, I32, P],
     }
     for f, a in nn.items():
         getattr(lib, f).argtypes = a
