@@ -274,6 +274,9 @@ def main():
     ap.add_argument("--rcond", type=float, default=1e-5)
     ap.add_argument("--m0", type=int, default=5)
     ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "serial"],
+                    help="serial: every pass of the headline on the calling stream (per-kernel profiles "
+                         "without overlap; the headline value is then the serial step)")
     ap.add_argument("--variants", default="fp32/graph,bf16x3/graph,bf16x3,fp16,bf16,m2l_bf16x3,m2l_fp16,m2l_bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "
                          "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout), "
@@ -310,6 +313,8 @@ def main():
 
     case = channel_case(args.p)
     tree, ops, w = case.tree, case.ops, case.w
+    serial_default = args.schedule == "serial"
+    ops.serial(serial_default)
     ranks = {l: ops.rank(l) for l in range(2, tree.depth + 1)}
     log("tree depth %d, leaf %d^3, precompute %.2f s, ranks %s" % (tree.depth, tree.leaf_side, case.t_pre, ranks))
 
@@ -321,7 +326,7 @@ def main():
     _, _, prof = case.timed(args.precision, args.steps, 1, profile=True)
     ops.serial(True)
     ms_serial, _, prof_serial = case.timed(args.precision, args.steps, 1, profile=True)
-    ops.serial(False)
+    ops.serial(serial_default)
     log("%s: %.3f ms/step (median %.3f, serial %.3f), rel-L2 %.3e" % (args.precision, ms, med, ms_serial, err))
 
     N = case.N
@@ -490,7 +495,7 @@ def main():
                    "rcond": args.rcond, "max_leaf": args.max_leaf, "leaf_side": tree.leaf_side,
                    "depth": tree.depth, "precision": args.precision, "m2l": case.m2l, "p2p": case.p2p,
                    "lattice_radius": (args.lattice_radius or 1.2) if args.layout == "lattice" else None,
-                   "parallelism": "none"},
+                   "schedule": args.schedule, "parallelism": "none"},
         "rel_l2_sampled": err,
         "accuracy_ok": err <= BAR,
         "pair_interactions_per_s_dense_equivalent": near_pairs(nb, s) / (ms * 1e-3),

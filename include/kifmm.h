@@ -166,10 +166,15 @@ int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
  * `tree` (else KIFMM_EMISMATCH).  Uses the work buffers owned by `ops`, so
  * calls sharing one ops object must be ordered on one stream.  The near field
  * (and, after it, the M2L of the coarse levels when both Fourier forms are on) runs
- * on a second stream owned by `ops`, and the finest level's FFT-form M2L on a third;
- * both are forked from and joined back into `stream` with events, so when the call
- * returns, all its work is ordered on `stream`.  FP32 P2M and L2P call rocBLAS on
- * `stream` (handle owned by `ops`). */
+ * on a second stream, and the finest level's FFT-form M2L on a third; the library
+ * creates these two once per device and shares them between all operator objects
+ * (kept until the process ends), and both are forked from and joined back into
+ * `stream` with events, so when the call returns, all its work is ordered on `stream`
+ * (also when it returns an error).  Evaluations of different ops objects may be
+ * issued on different streams; their side work then shares the two streams.  With
+ * leaves of 8^3 cells and FP32 arithmetic, P2M runs fused with the permute of I into
+ * leaf order and L2P fused with the sum of far and near field and the permute back
+ * (16-byte aligned I_dev and S_dev; otherwise separate permutes and tap GEMMs). */
 int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefactor,
                void *S_dev, int32_t precision, void *stream);
 

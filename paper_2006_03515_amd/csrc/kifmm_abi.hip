@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
@@ -293,6 +294,26 @@ struct PassTimer {
     }
 };
 
+// The near-field and finest-level streams of the evaluations, one pair per device, shared
+// by every operator object and kept until the process ends.  HIP spreads streams over a few
+// hardware queues (4 by default); a pair per live object would put the passes of several
+// objects, and the calling stream, on shared queues and serialise what should overlap.
+static std::mutex g_stream_mu;
+static std::vector<std::pair<hipStream_t, hipStream_t>> g_streams;
+
+static int shared_streams(hipStream_t *side, hipStream_t *fine) {
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    if (dev >= (int)g_streams.size()) g_streams.resize(dev + 1, {nullptr, nullptr});
+    auto &p = g_streams[dev];
+    if (!p.first) KIFMM_HIP(hipStreamCreateWithFlags(&p.first, hipStreamNonBlocking));
+    if (!p.second) KIFMM_HIP(hipStreamCreateWithFlags(&p.second, hipStreamNonBlocking));
+    *side = p.first;
+    *fine = p.second;
+    return KIFMM_OK;
+}
+
 static void free_ops(kifmm_ops o) {
     if (!o) return;
     clear_profile(o);
@@ -319,13 +340,11 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     if (o->fork) (void)hipEventDestroy(o->fork);
     if (o->join) (void)hipEventDestroy(o->join);
-    if (o->side) (void)hipStreamDestroy(o->side);
     if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
     if (o->join_fine) (void)hipEventDestroy(o->join_fine);
     for (auto *v : {&o->ev_up, &o->ev_m2l})
         for (hipEvent_t e : *v)
             if (e) (void)hipEventDestroy(e);
-    if (o->fine) (void)hipStreamDestroy(o->fine);
     delete o;
 }
 
@@ -971,10 +990,9 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(dmalloc(&o->q, (size_t)tree->N));
     KIFMM_TRY(dmalloc(&o->Sp, (size_t)tree->N));
     KIFMM_TRY(dmalloc(&o->SpN, (size_t)tree->N));
-    KIFMM_HIP(hipStreamCreateWithFlags(&o->side, hipStreamNonBlocking));
+    KIFMM_TRY(shared_streams(&o->side, &o->fine));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
-    KIFMM_HIP(hipStreamCreateWithFlags(&o->fine, hipStreamNonBlocking));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
