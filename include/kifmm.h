@@ -132,15 +132,23 @@ enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_M2L_BF16 = 2, KIFMM_M2L_FP16 = 3, K
 typedef struct kifmm_tree_s *kifmm_tree;
 typedef struct kifmm_ops_s *kifmm_ops;
 
-/* Tree construction (Section 3, step 1 of the algorithm outline).
- * Builds the complete octree of a cubic grid with n = 2^p cells per axis whose
- * leaves are cubes of ell^3 cells, ell^3 <= max_leaf (the paper's m) with ell
- * the largest power of two that fits; computes the Morton leaf order on the
- * device.  Requires nx == ny == nz, hx == hy == hz (else KIFMM_EUNSUPPORTED),
- * max_leaf >= 1.  A box-shaped grid of cubic cells is evaluated exactly inside
- * the smallest such cube with zero sources outside the box (caller-side:
- * paper_2006_03515_amd/embedding.py).  Allocates device memory owned by the tree; *out is set only
- * on success.  Synchronises `stream` before returning. */
+/* Tree construction (Section 3, step 1 of the algorithm outline; its closing remark on
+ * non-uniform meshes for cells with hz != hx).
+ * Cubic grid of cubic cells (nx == ny == nz = 2^p, hx == hy == hz): the complete octree
+ * whose leaves are cubes of ell^3 cells, ell^3 <= max_leaf (the paper's m) with ell the
+ * largest power of two that fits.
+ * Box nx == ny = 2^p, nz, with hx == hy and any hz: leaves of ell x ell x ellz cells,
+ * ellz the power of two closest to ell hx / hz (leaves nearly cubic in space), ell the
+ * largest power of two with ell^2 ellz <= max_leaf; the leaves form a column of R root
+ * cubes of (nx / ell)^3 leaves along z, each a complete octree (nz must equal
+ * R ellz nx / ell, R <= 64), and the near and far fields cross from one cube into the next
+ * (at level 0 the roots two or more apart interact through M2L).
+ * The leaf order (Morton within a root, root after root) is computed on the device.
+ * Requires ell >= 4; otherwise KIFMM_EUNSUPPORTED; KIFMM_EINVAL for bad sizes or
+ * max_leaf < 1.  Other box shapes of cubic cells are evaluated exactly inside the smallest
+ * cube with zero sources outside the box (caller-side: paper_2006_03515_amd/embedding.py).
+ * Allocates device memory owned by the tree; *out is set only on success.  Synchronises
+ * `stream` before returning. */
 int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kifmm_tree *out);
 
 /* Operator precompute for one tree and one pressure (Section 3, eq. (s2m),
@@ -153,12 +161,16 @@ int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kif
 int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel,
                                const kifmm_opts *opts, void *stream, kifmm_ops *out);
 
-/* Retained SVD ranks of level `level` (2 <= level <= depth); returns 0 and
+/* Retained SVD ranks of level `level` (lmin <= level <= depth; lmin = 2 on a cube, 1 on a column of
+ * two cubes, 0 on a column of three or more); returns 0 and
  * writes k_up/k_down, or a negative code. depth is returned by kifmm_tree_info. */
 int kifmm_ops_rank(kifmm_ops ops, int32_t level, int32_t *k_up, int32_t *k_down);
 
-/* Tree shape: depth D (levels 0..D), leaf side ell in cells. */
+/* Tree shape: depth D (levels 0..D below each root), leaf side ell in cells (along x, y). */
 int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side);
+/* Leaf cells along x and y (ell) and along z (ellz), and the number R of root cubes along z
+ * (1 for a cubic grid).  Any output pointer may be NULL. */
+int kifmm_tree_shape(kifmm_tree tree, int32_t *leaf_xy, int32_t *leaf_z, int32_t *roots);
 
 /* FMM evaluation: S_dev[i] ~= prefactor * sum_j G(x_i,y_j) I_dev[j] hx hy hz for
  * every cell i.  I_dev and S_dev hold nx*ny*nz values, double for KIFMM_FP64 and
@@ -193,10 +205,11 @@ int kifmm_eval(kifmm_tree tree, kifmm_ops ops, const void *I_dev, double prefact
 int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable);
 
 /* Target restriction: evaluation on a part of the domain only (Section 5.1, closing
- * remark: S_ph is often needed on a sub-region).  leaf_mask is a host array of nb^3
- * bytes, nb = n / ell leaves per axis (ell from kifmm_tree_info), in C order
- * [nb][nb][nb] over leaf coordinates (leaf (a, b, c) holds the cells a*ell .. a*ell+ell-1
- * along x, and so on); nonzero marks a wanted leaf.  It is copied (the caller keeps
+ * remark: S_ph is often needed on a sub-region).  leaf_mask is a host array of
+ * nb * nb * (R nb) bytes, nb = n / ell leaves per axis of a root cube (ell, R from
+ * kifmm_tree_shape), in C order [nb][nb][R nb] over leaf coordinates (leaf (a, b, c) holds
+ * the cells a*ell .. a*ell+ell-1 along x, and c*ellz .. along z); nonzero marks a wanted
+ * leaf.  It is copied (the caller keeps
  * ownership).  Every later kifmm_eval with these ops returns, at each cell of a wanted
  * leaf, exactly what it returns without the restriction (bit for bit: the sum and its
  * order are unchanged), and 0 at every other cell.  M2L, L2L, L2P and the near field

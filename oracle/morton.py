@@ -41,3 +41,23 @@ def leaf_order(n, ell):
     local = ((i % ell) * ell + (j % ell)) * ell + (k % ell)
     order = np.lexsort((local, leaf_key))   # sort by leaf key, then local index
     return order.astype(np.int64)
+
+
+def column_leaf_order(n, nz, ell, ellz):
+    """Leaf order of a box of n x n x nz cells cut into leaves of ell x ell x ellz cells,
+    the leaves forming a column of R = nz / (ellz * n / ell) cubes of (n / ell)^3 leaves
+    stacked along z, each cube a complete octree visited in pre-order (Morton order of the
+    leaf coordinates inside the cube), cube after cube from z = 0 upwards; inside a leaf
+    the cells follow C order.  Returns perm of length n * n * nz (position p of the
+    leaf-ordered array holds the cell perm[p] of the C-order grid)."""
+    nb = n // ell
+    assert nb * ell == n and nz % (ellz * nb) == 0
+    bits = int(np.log2(nb)) if nb > 1 else 0
+    i, j, k = np.meshgrid(np.arange(n), np.arange(n), np.arange(nz), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    lz = k // ellz                      # leaf z in the column
+    root = lz // nb
+    key = interleave(i // ell, j // ell, lz % nb, bits)
+    local = ((i % ell) * ell + (j % ell)) * ellz + (k % ellz)
+    order = np.lexsort((local, key, root))   # by cube, then Morton key, then local index
+    return order.astype(np.int64)

@@ -58,15 +58,24 @@ __host__ __device__ inline void morton_decode(uint32_t key, int &x, int &y, int 
 }
 
 // ------------------------------------------------------------ structures ----
+// The tree over the grid: R cubes ("roots") of 2^D x 2^D x 2^D leaves stacked along z, each
+// a complete octree.  A leaf holds ell x ell x ellz cells (x, y, z).  A cubic grid of cubic
+// cells has R = 1 and ellz = ell; a box nx = ny = ell 2^D, nz = R ellz 2^D with cells of
+// hx = hy != hz takes R > 1 and ellz chosen so that leaves are nearly cubic in space.  Boxes
+// of level l are numbered root * 8^l + morton(x, y, z - root 2^l), leaves (l = D) likewise,
+// so children of box b are 8 b .. 8 b + 7 and its parent b >> 3 as in a single octree.
 struct Tree {
     uint64_t magic;       // identifies the tree for ops/tree matching
-    int n;                // cells per axis
-    int ell;              // leaf side in cells
-    int nb;               // leaves per axis
+    int n;                // cells along x and y
+    int nz;               // cells along z (n for a cube)
+    int ell;              // leaf side in cells along x and y
+    int ellz;             // leaf side in cells along z
+    int nb;               // leaves per axis of one root cube (2^D)
+    int R;                // root cubes along z
     int depth;            // D: levels 0..D, leaves at D
-    int s;                // points per leaf = ell^3
-    int64_t N;            // n^3
-    double h, x0, y0, z0;
+    int s;                // points per leaf = ell^2 ellz
+    int64_t N;            // n^2 nz
+    double h, hz, x0, y0, z0;   // h = hx = hy
     int32_t *perm;        // device: perm[p] = grid index of leaf-ordered slot p
 };
 

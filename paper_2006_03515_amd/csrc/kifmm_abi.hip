@@ -34,7 +34,7 @@ template <typename T> int launch_permute_out(const Tree &, const T *, T, const u
 int launch_perm_i64(const Tree &, int64_t *, hipStream_t);
 int launch_kmat(const double *, int, const double *, int, const double *, const double *, int, int,
                 const kifmm_kernel &, double, double *, hipStream_t);
-int launch_near(int, double, const int *, int, const kifmm_kernel &, double *, hipStream_t);
+int launch_near(int, int, double, double, const int *, int, const kifmm_kernel &, double *, hipStream_t);
 int launch_jacobi_round(double *, double *, const int *, const int *, int, int, int, int64_t,
                         int64_t, int, int, double, unsigned long long *, hipStream_t);
 int launch_colnorm(const double *, const int *, const int *, int, int64_t, int, int, double *,
@@ -163,6 +163,13 @@ using namespace kifmm;
 struct kifmm_ops_s {
     uint64_t tree_magic = 0;
     int D = 0, ell = 0, s = 0, nb = 0;
+    int ellz = 0, R = 1;               // leaf cells along z, root cubes along z
+    int lmin = 2;                      // coarsest level with expansions: 2 on a cube, 1 on a column of 2, else 0
+    // M2L of level 0 on a column of R > 2 cubes: the roots two or more apart, offsets
+    // (0, 0, dz), 2 <= |dz| <= R - 1 (n0 operators)
+    int n0 = 0;
+    float *m2l0_32 = nullptr;
+    double *m2l0_64 = nullptr;
     int KU = 0, KD = 0;
     std::vector<int> ku, kd;           // retained ranks per level
     kifmm_kernel kern{};
@@ -218,7 +225,7 @@ struct kifmm_ops_s {
     float *spec_e = nullptr, *spec_p = nullptr;
     std::vector<float> m2l_scale;      // per level: max |M2L| (low precision storage divisor)
     int *taps = nullptr;               // all tap tables
-    TapList t_single{}, t_m2m{}, t_l2l{}, t_m2l{}, t_p2p{};
+    TapList t_single{}, t_m2m{}, t_l2l{}, t_m2l{}, t_p2p{}, t_m2l0{};
     // work buffers (sized for FP64)
     double *q = nullptr, *Sp = nullptr, *SpN = nullptr;   // leaf-ordered sources, far / near field
     std::vector<double *> cu, cd;
@@ -248,7 +255,7 @@ struct kifmm_ops_s {
 
 // flags of the boxes at level l, or null when zero-source skipping is off
 static const uint8_t *nz_of(kifmm_ops o, int l) {
-    return o->skip_zero && l >= 2 && l < (int)o->nz.size() ? o->nz[l] : nullptr;
+    return o->skip_zero && l >= o->lmin && l < (int)o->nz.size() ? o->nz[l] : nullptr;
 }
 
 // wanted-target flags of the boxes at level l, or null when every target is wanted
@@ -324,7 +331,7 @@ static void free_ops(kifmm_ops o) {
                     o->p2mbf, o->m2mbf, o->l2lbf, o->l2pbf, o->p2mh, o->m2mh, o->l2lh, o->l2ph,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
-                    o->p2m_frag, o->l2p_frag, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
+                    o->p2m_frag, o->l2p_frag, o->m2l0_32, o->m2l0_64, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -391,28 +398,49 @@ int kifmm_build_tree(const kifmm_grid *grid, int32_t max_leaf, void *stream, kif
     if (!out) return fail(KIFMM_EINVAL, "out is NULL");
     KIFMM_TRY(check_grid(grid));
     if (max_leaf < 1) return fail(KIFMM_EINVAL, "max_leaf must be >= 1");
-    if (grid->nx != grid->ny || grid->nx != grid->nz)
-        return fail(KIFMM_EUNSUPPORTED, "only cubic grids (nx == ny == nz) are supported");
-    if (grid->hx != grid->hy || grid->hx != grid->hz)
-        return fail(KIFMM_EUNSUPPORTED, "only cubic cells (hx == hy == hz) are supported");
-    const int n = grid->nx;
+    if (grid->nx != grid->ny)
+        return fail(KIFMM_EUNSUPPORTED, "nx must equal ny (a cube, or a column of cubes along z)");
+    if (grid->hx != grid->hy) return fail(KIFMM_EUNSUPPORTED, "hx must equal hy");
+    const int n = grid->nx, nz = grid->nz;
     if (n & (n - 1)) return fail(KIFMM_EUNSUPPORTED, "n must be a power of two");
     if (n > 1024) return fail(KIFMM_EUNSUPPORTED, "n must be <= 1024");
-    int ell = 1;
-    while (2 * ell <= n && (int64_t)(2 * ell) * (2 * ell) * (2 * ell) <= max_leaf) ell *= 2;
+    const bool cube = nz == n && grid->hz == grid->hx;
+    // leaves: ell x ell x ellz cells, ell the largest power of two that fits max_leaf; on a
+    // cube ellz = ell, else the power of two closest (in ratio) to ell hx / hz, so that the
+    // leaves are nearly cubic in space
+    auto ellz_for = [&](int e) {
+        if (cube) return e;
+        const double want = e * grid->hx / grid->hz;
+        int ez = 1;
+        while (ez * 2 <= nz && std::fabs(std::log2(ez * 2.0 / want)) < std::fabs(std::log2(ez / want))) ez *= 2;
+        return ez;
+    };
+    int ell = 0;
+    for (int e = 1; e <= n; e *= 2)
+        if ((int64_t)e * e * ellz_for(e) <= max_leaf) ell = e;
     if (ell < 4)
-        return fail(KIFMM_EUNSUPPORTED, "leaves must hold at least 4^3 cells (n >= 4, max_leaf >= 64)");
+        return fail(KIFMM_EUNSUPPORTED, "leaves must hold at least 4 x 4 cells across (n >= 4, max_leaf large enough)");
+    const int ellz = ellz_for(ell), nb = n / ell;
+    if (nz % ((int64_t)ellz * nb) != 0)
+        return fail(KIFMM_EUNSUPPORTED, "nz must be a multiple of ellz * nx / ell (a column of whole cubes of leaves)");
+    const int R = nz / (ellz * nb);
+    if (R > 64) return fail(KIFMM_EUNSUPPORTED, "at most 64 root cubes along z");
+    if ((int64_t)n * n * nz > INT32_MAX) return fail(KIFMM_EUNSUPPORTED, "at most 2^31 - 1 cells");
     kifmm_tree t = new (std::nothrow) kifmm_tree_s();
     if (!t) return fail(KIFMM_ENOMEM, "host allocation failed");
     t->magic = g_magic.fetch_add(1);
     t->n = n;
+    t->nz = nz;
     t->ell = ell;
-    t->nb = n / ell;
+    t->ellz = ellz;
+    t->nb = nb;
+    t->R = R;
     t->depth = 0;
     while ((1 << t->depth) < t->nb) ++t->depth;
-    t->s = ell * ell * ell;
-    t->N = (int64_t)n * n * n;
+    t->s = ell * ell * ellz;
+    t->N = (int64_t)n * n * nz;
     t->h = grid->hx;
+    t->hz = grid->hz;
     t->x0 = grid->x0;
     t->y0 = grid->y0;
     t->z0 = grid->z0;
@@ -439,6 +467,14 @@ int kifmm_tree_info(kifmm_tree tree, int32_t *depth, int32_t *leaf_side) {
     return KIFMM_OK;
 }
 
+int kifmm_tree_shape(kifmm_tree tree, int32_t *leaf_xy, int32_t *leaf_z, int32_t *roots) {
+    if (!tree) return fail(KIFMM_EINVAL, "tree is NULL");
+    if (leaf_xy) *leaf_xy = tree->ell;
+    if (leaf_z) *leaf_z = tree->ellz;
+    if (roots) *roots = tree->R;
+    return KIFMM_OK;
+}
+
 int kifmm_tree_permutation(kifmm_tree tree, int64_t *perm_dev, void *stream) {
     if (!tree || !perm_dev) return fail(KIFMM_EINVAL, "tree and perm_dev must be non-NULL");
     return launch_perm_i64(*tree, perm_dev, (hipStream_t)stream);
@@ -454,7 +490,7 @@ void kifmm_ops_destroy(kifmm_ops ops) { free_ops(ops); }
 
 int kifmm_ops_rank(kifmm_ops ops, int32_t level, int32_t *k_up, int32_t *k_down) {
     if (!ops) return fail(KIFMM_EINVAL, "ops is NULL");
-    if (level < 2 || level > ops->D) return fail(KIFMM_EINVAL, "level out of range");
+    if (level < ops->lmin || level > ops->D) return fail(KIFMM_EINVAL, "level out of range");
     if (k_up) *k_up = ops->ku[level];
     if (k_down) *k_down = ops->kd[level];
     return KIFMM_OK;
@@ -895,9 +931,13 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
 
 int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     DevBuf db;
-    const int D = o->D, s = o->s, ell = o->ell;
-    const double h = tree->h, Lside = tree->h * tree->n;
+    const int D = o->D, s = o->s, ell = o->ell, ellz = o->ellz, R = o->R, lmin = o->lmin;
+    const bool cube = R == 1 && ellz == ell && tree->hz == tree->h;
+    // a root cube's sides (x = y, z): box half-widths at level l are these over 2^(l+1)
+    const double h = tree->h, hz = tree->hz, Lside = tree->h * tree->n, Lz = hz * ellz * o->nb;
     const kifmm_kernel &kern = o->kern;
+    auto rx_of = [&](int l) { return Lside / std::ldexp(1.0, l + 1); };
+    auto rz_of = [&](int l) { return Lz / std::ldexp(1.0, l + 1); };
     o->ku.assign(D + 1, 0);
     o->kd.assign(D + 1, 0);
 
@@ -914,11 +954,11 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(upload(db, nbr, &nbrd, st));
     double *p2p;
     KIFMM_TRY(db.get(&p2p, (size_t)27 * s * s));
-    KIFMM_TRY(launch_near(ell, h, nbrd, 27, kern, p2p, st));
+    KIFMM_TRY(launch_near(ell, ellz, h, hz, nbrd, 27, kern, p2p, st));
     KIFMM_TRY(dmalloc(&o->p2p32, (size_t)27 * s * s));
     KIFMM_TRY(dmalloc(&o->p2p64, (size_t)27 * s * s));
     KIFMM_TRY(store_both(p2p, s, s, 27, o->p2p32, o->p2p64, s, s, st));
-    if (ell == 8) KIFMM_TRY(build_near_spectra(db, o, h, st));
+    if (ell == 8 && cube) KIFMM_TRY(build_near_spectra(db, o, h, st));
     {
         double mx;
         KIFMM_TRY(max_abs_host(p2p, (size_t)27 * s * s, &mx, st));
@@ -979,9 +1019,20 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         }
         add_list(o->t_m2l, 8, ntaps, op, off);
     }
+    if (R > 2) {   // level 0 of a column of cubes: every root two or more apart
+        std::vector<int> op, off;
+        for (int dz = -(R - 1); dz <= R - 1; ++dz) {
+            if (std::abs(dz) < 2) continue;
+            op.push_back((int)op.size());
+            off.push_back(pack_off(0, 0, dz));
+        }
+        o->n0 = (int)op.size();
+        add_list(o->t_m2l0, 1, o->n0, op, off);
+    }
     KIFMM_TRY(dmalloc(&o->taps, taps.size()));
     KIFMM_HIP(hipMemcpyAsync(o->taps, taps.data(), taps.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    for (TapList *tl : {&o->t_p2p, &o->t_single, &o->t_m2m, &o->t_l2l, &o->t_m2l}) {
+    for (TapList *tl : {&o->t_p2p, &o->t_single, &o->t_m2m, &o->t_l2l, &o->t_m2l, &o->t_m2l0}) {
+        if (tl->ntaps == 0) continue;
         tl->op_dev = o->taps + (size_t)tl->op_dev;
         tl->off_dev = o->taps + (size_t)tl->off_dev;
     }
@@ -1001,11 +1052,11 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     o->cd.assign(D + 1, nullptr);
     o->ev_up.assign(D + 1, nullptr);
     o->ev_m2l.assign(D + 1, nullptr);
-    for (int l = 3; l < D; ++l) {
+    for (int l = 3; l < D && cube; ++l) {
         KIFMM_HIP(hipEventCreateWithFlags(&o->ev_up[l], hipEventDisableTiming));
         KIFMM_HIP(hipEventCreateWithFlags(&o->ev_m2l[l], hipEventDisableTiming));
     }
-    if (D < 2) {
+    if (D < lmin) {
         KIFMM_HIP(hipStreamSynchronize(st));
         return KIFMM_OK;
     }
@@ -1013,48 +1064,51 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     // point sets per level, relative to the box centre
     std::vector<PointSets> ps(D + 1);
     std::vector<double *> yu(D + 1), xu(D + 1), yd(D + 1), xd(D + 1);
-    for (int l = 2; l <= D; ++l) {
-        const double r = Lside / std::ldexp(1.0, l + 1);
-        ps[l] = make_point_sets(o->opts, r);
+    for (int l = lmin; l <= D; ++l) {
+        // the unit point sets, stretched to the box (half-widths rx, rx, rz)
+        ps[l] = make_point_sets(o->opts, 1.0);
+        const double sc[3] = {rx_of(l), rx_of(l), rz_of(l)};
+        for (auto *v : {&ps[l].yu, &ps[l].xu, &ps[l].yd, &ps[l].xd})
+            for (size_t i = 0; i < v->size(); ++i) (*v)[i] *= sc[i % 3];
         KIFMM_TRY(upload(db, ps[l].yu, &yu[l], st));
         KIFMM_TRY(upload(db, ps[l].xu, &xu[l], st));
         KIFMM_TRY(upload(db, ps[l].yd, &yd[l], st));
         KIFMM_TRY(upload(db, ps[l].xd, &xd[l], st));
     }
-    const int nyu = (int)ps[2].yu.size() / 3, nxu = (int)ps[2].xu.size() / 3;
-    const int nyd = (int)ps[2].yd.size() / 3, nxd = (int)ps[2].xd.size() / 3;
+    const int nyu = (int)ps[lmin].yu.size() / 3, nxu = (int)ps[lmin].xu.size() / 3;
+    const int nyd = (int)ps[lmin].yd.size() / 3, nxd = (int)ps[lmin].xd.size() / 3;
 
     // truncated SVDs of the check-to-equivalent matrices, every level
     std::vector<const double *> X, Y;
-    for (int l = 2; l <= D; ++l) { X.push_back(xu[l]); Y.push_back(yu[l]); }
+    for (int l = lmin; l <= D; ++l) { X.push_back(xu[l]); Y.push_back(yu[l]); }
     std::vector<Factor> fu, fd;
     KIFMM_TRY(batched_tsvd(db, X, Y, nxu, nyu, kern, h, o->opts.rcond, fu, st));
     X.clear(); Y.clear();
-    for (int l = 2; l <= D; ++l) { X.push_back(xd[l]); Y.push_back(yd[l]); }
+    for (int l = lmin; l <= D; ++l) { X.push_back(xd[l]); Y.push_back(yd[l]); }
     KIFMM_TRY(batched_tsvd(db, X, Y, nxd, nyd, kern, h, o->opts.rcond, fd, st));
     int kumax = 0, kdmax = 0;
-    for (int l = 2; l <= D; ++l) {
-        o->ku[l] = fu[l - 2].k;
-        o->kd[l] = fd[l - 2].k;
+    for (int l = lmin; l <= D; ++l) {
+        o->ku[l] = fu[l - lmin].k;
+        o->kd[l] = fd[l - lmin].k;
         kumax = std::max(kumax, o->ku[l]);
         kdmax = std::max(kdmax, o->kd[l]);
     }
     const int KU = pad_to(kumax, 32), KD = pad_to(kdmax, 32);
     o->KU = KU;
     o->KD = KD;
-    auto UTu = [&](int l) { return fu[l - 2].UT; };
-    auto Wu = [&](int l) { return fu[l - 2].W; };
-    auto UTd = [&](int l) { return fd[l - 2].UT; };
-    auto Wd = [&](int l) { return fd[l - 2].W; };
+    auto UTu = [&](int l) { return fu[l - lmin].UT; };
+    auto Wu = [&](int l) { return fu[l - lmin].W; };
+    auto UTd = [&](int l) { return fd[l - lmin].UT; };
+    auto Wd = [&](int l) { return fd[l - lmin].W; };
 
     // leaf cell centres relative to the leaf centre, C order
     std::vector<double> P;
     for (int i = 0; i < ell; ++i)
         for (int j = 0; j < ell; ++j)
-            for (int k = 0; k < ell; ++k) {
+            for (int k = 0; k < ellz; ++k) {
                 P.push_back((i + 0.5) * h - 0.5 * ell * h);
                 P.push_back((j + 0.5) * h - 0.5 * ell * h);
-                P.push_back((k + 0.5) * h - 0.5 * ell * h);
+                P.push_back((k + 0.5) * hz - 0.5 * ellz * hz);
             }
     double *Pd;
     KIFMM_TRY(upload(db, P, &Pd, st));
@@ -1086,52 +1140,52 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(launch_pack_fragments(o->p2m32, KU, s, s, o->p2m_frag, st));
         KIFMM_TRY(launch_pack_fragments(o->l2p32, s, KD, KD, o->l2p_frag, st));
     }
-    // child centre offsets at a level of half-width r: (2c - 1) r per axis
-    auto child_shifts = [&](double r) {
+    // child centre offsets at a level of half-widths (r, r, rz): (2c - 1) r per axis
+    auto child_shifts = [&](double r, double rz) {
         std::vector<double> v;
         for (int c = 0; c < 8; ++c) {
             v.push_back((2 * ((c >> 2) & 1) - 1) * r);
             v.push_back((2 * ((c >> 1) & 1) - 1) * r);
-            v.push_back((2 * (c & 1) - 1) * r);
+            v.push_back((2 * (c & 1) - 1) * rz);
         }
         return v;
     };
-    // M2M (eq. (m2m)), levels 2..D-1: U_u^T(l) G(x^u(l), y^u(l+1) + child) W_u(l+1)
-    if (D >= 3) {
-        KIFMM_TRY(dmalloc(&o->m2m32, (size_t)(D - 2) * 8 * KU * KU));
-        KIFMM_TRY(dmalloc(&o->m2m64, (size_t)(D - 2) * 8 * KU * KU));
-        KIFMM_TRY(dmalloc(&o->l2l32, (size_t)(D - 2) * 8 * KD * KD));
-        KIFMM_TRY(dmalloc(&o->l2l64, (size_t)(D - 2) * 8 * KD * KD));
-        for (int l = 2; l <= D - 1; ++l) {
-            const double rc = Lside / std::ldexp(1.0, l + 2);
+    // M2M (eq. (m2m)), levels lmin..D-1 (block l - lmin): U_u^T(l) G(x^u(l), y^u(l+1) + child) W_u(l+1)
+    if (D > lmin) {
+        KIFMM_TRY(dmalloc(&o->m2m32, (size_t)(D - lmin) * 8 * KU * KU));
+        KIFMM_TRY(dmalloc(&o->m2m64, (size_t)(D - lmin) * 8 * KU * KU));
+        KIFMM_TRY(dmalloc(&o->l2l32, (size_t)(D - lmin) * 8 * KD * KD));
+        KIFMM_TRY(dmalloc(&o->l2l64, (size_t)(D - lmin) * 8 * KD * KD));
+        for (int l = lmin; l <= D - 1; ++l) {
             double *sh, *tmp;
-            KIFMM_TRY(upload(db, child_shifts(rc), &sh, st));
+            KIFMM_TRY(upload(db, child_shifts(rx_of(l + 1), rz_of(l + 1)), &sh, st));
             KIFMM_TRY(db.get(&tmp, (size_t)8 * o->ku[l] * o->ku[l + 1]));
             KIFMM_TRY(fused_ops(db, UTu(l), o->ku[l], xu[l], nxu, yu[l + 1], nyu, Wu(l + 1),
                                 o->ku[l + 1], nullptr, sh, 8, kern, h, tmp, st));
-            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
+            const size_t so = (size_t)(l - lmin) * 8 * KU * KU;
             KIFMM_TRY(store_both(tmp, o->ku[l], o->ku[l + 1], 8, o->m2m32 + so, o->m2m64 + so, KU, KU, st));
         }
-        // L2L (eq. (l2l)), levels 3..D: U_d^T(l) G(x^d(l) + child, y^d(l-1)) W_d(l-1)
-        for (int l = 3; l <= D; ++l) {
-            const double r = Lside / std::ldexp(1.0, l + 1);
+        // L2L (eq. (l2l)), levels lmin+1..D (block l - lmin - 1): U_d^T(l) G(x^d(l) + child, y^d(l-1)) W_d(l-1)
+        for (int l = lmin + 1; l <= D; ++l) {
             double *sh, *tmp;
-            KIFMM_TRY(upload(db, child_shifts(r), &sh, st));
+            KIFMM_TRY(upload(db, child_shifts(rx_of(l), rz_of(l)), &sh, st));
             KIFMM_TRY(db.get(&tmp, (size_t)8 * o->kd[l] * o->kd[l - 1]));
             KIFMM_TRY(fused_ops(db, UTd(l), o->kd[l], xd[l], nxd, yd[l - 1], nyd, Wd(l - 1),
                                 o->kd[l - 1], sh, nullptr, 8, kern, h, tmp, st));
-            const size_t so = (size_t)(l - 3) * 8 * KD * KD;
+            const size_t so = (size_t)(l - lmin - 1) * 8 * KD * KD;
             KIFMM_TRY(store_both(tmp, o->kd[l], o->kd[l - 1], 8, o->l2l32 + so, o->l2l64 + so, KD, KD, st));
         }
     }
-    // M2L (eq. (m2l)), levels 2..D, 316 offsets: U_d^T G(x^d, y^u + 2 r o) W_u
+    // M2L (eq. (m2l)), levels lmin..D (block l - lmin; level 0 of a column of cubes has its
+    // own list), 316 offsets: U_d^T G(x^d, y^u + 2 r o) W_u
     {
         const size_t per = (size_t)n316 * KD * KU;
-        KIFMM_TRY(dmalloc(&o->m2l32, (size_t)(D - 1) * per));
-        KIFMM_TRY(dmalloc(&o->m2l64, (size_t)(D - 1) * per));
-        KIFMM_TRY(dmalloc(&o->m2lbf, (size_t)(D - 1) * per));
-        KIFMM_TRY(dmalloc(&o->m2lbf_lo, (size_t)(D - 1) * per));
-        KIFMM_TRY(dmalloc(&o->m2lh, (size_t)(D - 1) * per));
+        const size_t nlev = (size_t)(D - lmin + 1);
+        KIFMM_TRY(dmalloc(&o->m2l32, nlev * per));
+        KIFMM_TRY(dmalloc(&o->m2l64, nlev * per));
+        KIFMM_TRY(dmalloc(&o->m2lbf, nlev * per));
+        KIFMM_TRY(dmalloc(&o->m2lbf_lo, nlev * per));
+        KIFMM_TRY(dmalloc(&o->m2lh, nlev * per));
         o->m2l_scale.assign(D + 1, 1.0f);
         double *G, *T1, *tmp, *sh;
         const size_t maxk = (size_t)std::max(kumax, kdmax);
@@ -1139,10 +1193,9 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(db.get(&T1, (size_t)n316 * maxk * nyu));
         KIFMM_TRY(db.get(&tmp, (size_t)n316 * maxk * maxk));
         KIFMM_TRY(db.get(&sh, (size_t)3 * n316));
-        for (int l = 2; l <= D; ++l) {
-            const double r = Lside / std::ldexp(1.0, l + 1);
+        for (int l = std::max(lmin, 1); l <= D; ++l) {
             std::vector<double> shifts(3 * n316);
-            for (int i = 0; i < 3 * n316; ++i) shifts[i] = 2.0 * r * m2lo[i];
+            for (int i = 0; i < 3 * n316; ++i) shifts[i] = 2.0 * (i % 3 == 2 ? rz_of(l) : rx_of(l)) * m2lo[i];
             KIFMM_HIP(hipMemcpyAsync(sh, shifts.data(), shifts.size() * sizeof(double),
                                      hipMemcpyHostToDevice, st));
             const int kd = o->kd[l], ku = o->ku[l];
@@ -1151,7 +1204,7 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
                                       nyu, (int64_t)kd * nyu, n316, st));
             KIFMM_TRY(launch_gemm_f64(kd, ku, nyu, T1, nyu, (int64_t)kd * nyu, Wu(l), ku, 0, tmp, ku,
                                       (int64_t)kd * ku, n316, st));
-            const size_t so = (size_t)(l - 2) * per;
+            const size_t so = (size_t)(l - lmin) * per;
             KIFMM_TRY(store_both(tmp, kd, ku, n316, o->m2l32 + so, o->m2l64 + so, KD, KU, st));
             double mx;
             KIFMM_TRY(max_abs_host(tmp, (size_t)n316 * kd * ku, &mx, st));
@@ -1161,6 +1214,25 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             KIFMM_TRY(launch_cast_pad_lo(tmp, kd, ku, (int64_t)kd * ku, o->m2lbf_lo + so, KD, KU,
                                          (int64_t)KD * KU, n316, 1.0 / mx, st));
             KIFMM_TRY(store<_Float16>(tmp, kd, ku, n316, o->m2lh + so, KD, KU, 1.0 / mx, st));
+        }
+        if (o->n0 > 0) {   // level 0 of a column of cubes: roots (0, 0, dz) apart, |dz| >= 2
+            std::vector<double> shifts;
+            for (int dz = -(R - 1); dz <= R - 1; ++dz)
+                if (std::abs(dz) >= 2) {
+                    shifts.push_back(0.0);
+                    shifts.push_back(0.0);
+                    shifts.push_back(2.0 * rz_of(0) * dz);
+                }
+            const int n0 = o->n0, kd = o->kd[0], ku = o->ku[0];
+            KIFMM_HIP(hipMemcpyAsync(sh, shifts.data(), shifts.size() * sizeof(double), hipMemcpyHostToDevice, st));
+            KIFMM_TRY(launch_kmat(xd[0], nxd, yu[0], nyu, nullptr, sh, n0, 0, kern, h, G, st));
+            KIFMM_TRY(launch_gemm_f64(kd, nyu, nxd, UTd(0), nxd, 0, G, nyu, (int64_t)nxd * nyu, T1,
+                                      nyu, (int64_t)kd * nyu, n0, st));
+            KIFMM_TRY(launch_gemm_f64(kd, ku, nyu, T1, nyu, (int64_t)kd * nyu, Wu(0), ku, 0, tmp, ku,
+                                      (int64_t)kd * ku, n0, st));
+            KIFMM_TRY(dmalloc(&o->m2l0_32, (size_t)n0 * KD * KU));
+            KIFMM_TRY(dmalloc(&o->m2l0_64, (size_t)n0 * KD * KU));
+            KIFMM_TRY(store_both(tmp, kd, ku, n0, o->m2l0_32, o->m2l0_64, KD, KU, st));
         }
     }
     // BF16 and FP16 copies of the surface operators, each divided by its maximum magnitude
@@ -1179,14 +1251,14 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(lowp(o->l2p64, s, KD, 1, &o->l2pbf, &o->l2ph, &o->l2p_scale));
         o->m2m_scale.assign(D + 1, 1.0f);
         o->l2l_scale.assign(D + 1, 1.0f);
-        if (D > 2) {
-            KIFMM_TRY(dmalloc(&o->m2mbf, (size_t)(D - 2) * 8 * KU * KU));
-            KIFMM_TRY(dmalloc(&o->m2mh, (size_t)(D - 2) * 8 * KU * KU));
-            KIFMM_TRY(dmalloc(&o->l2lbf, (size_t)(D - 2) * 8 * KD * KD));
-            KIFMM_TRY(dmalloc(&o->l2lh, (size_t)(D - 2) * 8 * KD * KD));
+        if (D > lmin) {
+            KIFMM_TRY(dmalloc(&o->m2mbf, (size_t)(D - lmin) * 8 * KU * KU));
+            KIFMM_TRY(dmalloc(&o->m2mh, (size_t)(D - lmin) * 8 * KU * KU));
+            KIFMM_TRY(dmalloc(&o->l2lbf, (size_t)(D - lmin) * 8 * KD * KD));
+            KIFMM_TRY(dmalloc(&o->l2lh, (size_t)(D - lmin) * 8 * KD * KD));
         }
-        for (int l = 2; l <= D - 1; ++l) {   // M2M into level l: block l - 2
-            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
+        for (int l = lmin; l <= D - 1; ++l) {   // M2M into level l: block l - lmin
+            const size_t so = (size_t)(l - lmin) * 8 * KU * KU;
             double mx;
             KIFMM_TRY(max_abs_host(o->m2m64 + so, (size_t)8 * KU * KU, &mx, st));
             if (!(mx > 0)) mx = 1.0;
@@ -1194,8 +1266,8 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             KIFMM_TRY(store<__bf16>(o->m2m64 + so, KU, KU, 8, o->m2mbf + so, KU, KU, 1.0 / mx, st));
             KIFMM_TRY(store<_Float16>(o->m2m64 + so, KU, KU, 8, o->m2mh + so, KU, KU, 1.0 / mx, st));
         }
-        for (int l = 3; l <= D; ++l) {   // L2L into level l: block l - 3
-            const size_t so = (size_t)(l - 3) * 8 * KD * KD;
+        for (int l = lmin + 1; l <= D; ++l) {   // L2L into level l: block l - lmin - 1
+            const size_t so = (size_t)(l - lmin - 1) * 8 * KD * KD;
             double mx;
             KIFMM_TRY(max_abs_host(o->l2l64 + so, (size_t)8 * KD * KD, &mx, st));
             if (!(mx > 0)) mx = 1.0;
@@ -1204,22 +1276,22 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
             KIFMM_TRY(store<_Float16>(o->l2l64 + so, KD, KD, 8, o->l2lh + so, KD, KD, 1.0 / mx, st));
         }
     }
-    if (o->opts.layout == KIFMM_LAYOUT_LATTICE) KIFMM_TRY(build_fft_m2l(db, o, Lside, h, m2lo, fu, fd, st));
-    for (int l = 2; l <= D; ++l) {
-        const size_t nbx = (size_t)1 << (3 * l);
+    if (o->opts.layout == KIFMM_LAYOUT_LATTICE && cube) KIFMM_TRY(build_fft_m2l(db, o, Lside, h, m2lo, fu, fd, st));
+    for (int l = lmin; l <= D; ++l) {
+        const size_t nbx = (size_t)R << (3 * l);
         KIFMM_TRY(dmalloc(&o->cu[l], nbx * KU));
         KIFMM_TRY(dmalloc(&o->cd[l], nbx * KD));
     }
-    o->split_c_n = ((int64_t)1 << (3 * D)) * KU;
+    o->split_c_n = ((int64_t)R << (3 * D)) * KU;
     KIFMM_TRY(dmalloc(&o->split_c, (size_t)(2 * o->split_c_n)));
     o->split_q_n = tree->N;
     KIFMM_TRY(dmalloc(&o->split_q, (size_t)(2 * o->split_q_n)));
     // scratch for the tap-group split of the M2L launches: up to 64 M floats
     // (the launcher uses fewer groups when a split would not fit)
     int64_t need = 0;
-    for (int l = 2; l <= D; ++l) {
-        const int64_t nbx = (int64_t)1 << (3 * l);
-        const int64_t base = ((nbx / 8 + 63) / 64) * ((KD + 127) / 128) * 8;
+    for (int l = lmin; l <= D; ++l) {
+        const int64_t nbx = (int64_t)R << (3 * l);
+        const int64_t base = std::max<int64_t>(1, ((nbx / 8 + 63) / 64) * ((KD + 127) / 128) * 8);
         int64_t g = std::min<int64_t>(o->t_m2l.ntaps, (2048 + base - 1) / base);
         need = std::max(need, g * nbx * KD);
     }
@@ -1233,11 +1305,11 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
 template <typename TA, typename TI, typename TO>
 TapArgs<TA, TI, TO> tap(const TA *A, int64_t a_stride, int M, int K, const TI *in, int64_t in_ld, TO *out,
                         int64_t out_ld, int mode, int nl, const TapList &tl, int cls_stride,
-                        int64_t n_per_class, int accumulate) {
+                        int64_t n_per_class, int accumulate, int zroots = 1) {
     TapArgs<TA, TI, TO> p{};
     p.A = A; p.A2 = nullptr; p.a_stride = a_stride; p.M = M; p.K = K;
     p.in = in; p.in2 = nullptr; p.in_ld = in_ld; p.out = out; p.out_ld = out_ld;
-    p.mode = mode; p.nl = nl; p.nclass = tl.nclass; p.cls_stride = cls_stride;
+    p.mode = mode; p.nl = nl; p.zroots = zroots; p.nclass = tl.nclass; p.cls_stride = cls_stride;
     p.n_per_class = n_per_class; p.n_boxes = n_per_class * tl.nclass;
     p.tap_op = tl.op_dev; p.tap_off = tl.off_dev; p.ntaps = tl.ntaps;
     p.accumulate = accumulate;
@@ -1282,9 +1354,20 @@ struct OpSet {
 template <typename T>
 int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, hipStream_t st) {
     const int KU = o->KU, KD = o->KD;
-    const int64_t nper = (int64_t)1 << (3 * (l - 1));
+    const int64_t nper = (int64_t)o->R << (3 * (l - 1));   // boxes per parity class
     const size_t per = (size_t)316 * KD * KU;
-    const size_t so = (size_t)(l - 2) * per;
+    const size_t so = (size_t)(l - o->lmin) * per;
+    const int zr = o->R;
+    if (l == 0) {   // a column of cubes: the roots two or more apart (FP32 or FP64 operators)
+        if (o->n0 == 0) return KIFMM_OK;
+        const T *A0 = sizeof(T) == 8 ? (const T *)o->m2l0_64 : (const T *)o->m2l0_32;
+        auto p = tap<T, T>(A0, (int64_t)KD * KU, KD, KU, (T *)o->cu[0], KU, (T *)o->cd[0], KD, SRC_NBR, 1,
+                           o->t_m2l0, 1, o->R, acc, zr);
+        p.in_nz = nz_of(o, 0);
+        p.out_need = want_of(o, 0);
+        p.pass = PASS_M2L;
+        return run(p, st);
+    }
     if constexpr (sizeof(T) == 4) {
         if (o->m2l_fft && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
             // FFT form: equivalent densities on the lattice, their spectra, pointwise
@@ -1317,7 +1400,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
         if (precision == KIFMM_M2L_BF16 || precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16X3 ||
             precision == KIFMM_BF16X3 || precision == KIFMM_BF16 || precision == KIFMM_FP16) {
             const bool fp16 = precision == KIFMM_M2L_FP16 || precision == KIFMM_FP16;
-            const int64_t ncu = ((int64_t)1 << (3 * l)) * KU;
+            const int64_t ncu = ((int64_t)o->R << (3 * l)) * KU;
             KIFMM_TRY(run_amax((const float *)o->cu[l], ncu, o->amax, o->n_amax, st));
             const int64_t ldA = (int64_t)KD * KU;
             const bool x3 = precision == KIFMM_M2L_BF16X3 || precision == KIFMM_BF16X3;
@@ -1326,7 +1409,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                     _Float16 *hi = (_Float16 *)o->split_c;
                     KIFMM_TRY(run_split_lp<_Float16>((const float *)o->cu[l], ncu, o->amax, o->n_amax, hi, nullptr, st));
                     auto p = tap<_Float16, _Float16>(o->m2lh + so, ldA, KD, KU, hi, KU, (float *)o->cd[l], KD, SRC_NBR,
-                                                     1 << l, o->t_m2l, 8, nper, acc);
+                                                     1 << l, o->t_m2l, 8, nper, acc, zr);
                     p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                     p.part = o->part; p.part_capacity = o->part_capacity;
                     p.in_nz = nz_of(o, l);
@@ -1337,7 +1420,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 __bf16 *hi = (__bf16 *)o->split_c, *lo = hi + o->split_c_n;
                 KIFMM_TRY(run_split_lp<__bf16>((const float *)o->cu[l], ncu, o->amax, o->n_amax, hi, x3 ? lo : nullptr, st));
                 auto p = tap<__bf16, __bf16>(o->m2lbf + so, ldA, KD, KU, hi, KU, (float *)o->cd[l], KD, SRC_NBR, 1 << l,
-                                             o->t_m2l, 8, nper, acc);
+                                             o->t_m2l, 8, nper, acc, zr);
                 p.A2 = o->m2lbf_lo + so;
                 p.in2 = lo;
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
@@ -1349,7 +1432,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             }
             if (fp16) {
                 auto p = tap<_Float16, float>(o->m2lh + so, ldA, KD, KU, (float *)o->cu[l], KU,
-                                              (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
+                                              (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc, zr);
                 p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
                 p.part = o->part; p.part_capacity = o->part_capacity;
                 p.in_nz = nz_of(o, l);
@@ -1358,7 +1441,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 return run_tap_lp<_Float16>(p, false, st);
             }
             auto p = tap<__bf16, float>(o->m2lbf + so, ldA, KD, KU, (float *)o->cu[l], KU,
-                                        (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc);
+                                        (float *)o->cd[l], KD, SRC_NBR, 1 << l, o->t_m2l, 8, nper, acc, zr);
             p.A2 = o->m2lbf_lo + so;
             p.amax = o->amax; p.n_amax = o->n_amax; p.op_scale = o->m2l_scale[l];
             p.part = o->part; p.part_capacity = o->part_capacity;
@@ -1369,7 +1452,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
         }
     }
     auto p = tap<T, T>(ops.m2l + so, (int64_t)KD * KU, KD, KU, (T *)o->cu[l], KU, (T *)o->cd[l], KD, SRC_NBR,
-                       1 << l, o->t_m2l, 8, nper, acc);
+                       1 << l, o->t_m2l, 8, nper, acc, zr);
     if constexpr (sizeof(T) == 4) {
         p.part = o->part;
         p.part_capacity = o->part_capacity;
@@ -1384,7 +1467,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
 template <typename T>
 int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision, hipStream_t st) {
     const int s = o->s, nb = o->nb;
-    const int64_t nleaf = (int64_t)nb * nb * nb;
+    const int64_t nleaf = (int64_t)o->R * nb * nb * nb;
     if constexpr (sizeof(T) == 4) {
         if (o->p2p_fft && nb >= 4) {   // FP32 arithmetic in every single-precision mode
             for (int stage = 0; stage < 3; ++stage) {
@@ -1400,7 +1483,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
                 __bf16 *hi = (__bf16 *)o->split_q, *lo = hi + o->split_q_n;
                 KIFMM_TRY(run_split_lp<__bf16>((const float *)q, nleaf * s, o->amax_q, o->n_amax, hi, lo, st));
                 auto p = tap<__bf16, __bf16>(o->p2pbf, (int64_t)s * s, s, s, hi, s, (float *)out, s, SRC_NBR, nb,
-                                             o->t_p2p, 1, nleaf, 0);
+                                             o->t_p2p, 1, nleaf, 0, o->R);
                 p.A2 = o->p2pbf_lo;
                 p.in2 = lo;
                 p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
@@ -1410,7 +1493,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
                 return run_tap_lp_staged<__bf16>(p, true, st);
             }
             auto p = tap<__bf16, float>(o->p2pbf, (int64_t)s * s, s, s, (const float *)q, s, (float *)out, s,
-                                        SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
+                                        SRC_NBR, nb, o->t_p2p, 1, nleaf, 0, o->R);
             p.A2 = o->p2pbf_lo;
             p.amax = o->amax_q; p.n_amax = o->n_amax; p.op_scale = o->p2p_scale;
             p.in_nz = nz_of(o, o->D);
@@ -1419,7 +1502,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
             return run_tap_lp<__bf16>(p, true, st);
         }
     }
-    auto p = tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, out, s, SRC_NBR, nb, o->t_p2p, 1, nleaf, 0);
+    auto p = tap<T, T>(ops.p2p, (int64_t)s * s, s, s, q, s, out, s, SRC_NBR, nb, o->t_p2p, 1, nleaf, 0, o->R);
     p.in_nz = nz_of(o, o->D);
     p.out_need = want_of(o, o->D);
     p.pass = PASS_P2P;
@@ -1454,13 +1537,13 @@ __global__ void parent_nonzero_kernel(const uint8_t *__restrict__ child, int64_t
 
 template <typename T>
 int mark_nonzero_sources(kifmm_ops o, const T *q, hipStream_t st) {
-    const int64_t nleaf = (int64_t)o->nb * o->nb * o->nb;
+    const int64_t nleaf = (int64_t)o->R * o->nb * o->nb * o->nb;
     int64_t blocks = (nleaf * 64 + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(leaf_nonzero_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, q, nleaf, o->s, o->nz[o->D]);
     KIFMM_HIP(hipGetLastError());
-    for (int l = o->D - 1; l >= 2; --l) {
-        const int64_t n = (int64_t)1 << (3 * l);
+    for (int l = o->D - 1; l >= o->lmin; --l) {
+        const int64_t n = (int64_t)o->R << (3 * l);
         hipLaunchKernelGGL(parent_nonzero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, o->nz[l + 1], n,
                            o->nz[l]);
         KIFMM_HIP(hipGetLastError());
@@ -1495,11 +1578,11 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     if constexpr (sizeof(T) == 8) ops = {o->p2m64, o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64};
     else ops = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32};
     T *q = (T *)o->q, *Sp = (T *)o->Sp, *SpN = (T *)o->SpN;
-    const int D = o->D, s = o->s, nb = o->nb, KU = o->KU, KD = o->KD;
-    const int64_t nleaf = (int64_t)nb * nb * nb;
+    const int D = o->D, s = o->s, nb = o->nb, KU = o->KU, KD = o->KD, R = o->R, lmin = o->lmin;
+    const int64_t nleaf = (int64_t)R * nb * nb * nb;
     // the cell volume goes in with the sources (q = I h^3), the prefactor on the way out:
     // FP32 sums of G I alone reach 1e37 for fine cells and bright sources
-    const T vol = (T)(t->h * t->h * t->h), scale = (T)prefactor;
+    const T vol = (T)(t->h * t->h * t->hz), scale = (T)prefactor;
     // every translation GEMM with BF16 or FP16 operands
     const bool lowp = sizeof(T) == 4 && (precision == KIFMM_BF16 || precision == KIFMM_FP16);
     // P2M fused with the way into leaf order, L2P with the sum and the way out (FP32 GEMMs,
@@ -1514,8 +1597,8 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, vol, q, st));
     }
-    if (o->skip_zero && D >= 2) KIFMM_TRY(mark_nonzero_sources<T>(o, q, st));
-    if (D < 2) {   // every leaf is in every other leaf's near range
+    if (o->skip_zero && D >= lmin) KIFMM_TRY(mark_nonzero_sources<T>(o, q, st));
+    if (D < lmin) {   // one cube of at most 2^3 leaves: every leaf is in every other leaf's near range
         {
             PassTimer pt(o, KIFMM_PASS_P2P, st);
             KIFMM_TRY(p2p_pass<T>(o, ops, q, Sp, precision, st));
@@ -1575,24 +1658,25 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // into cd[l]; the main stream does level 2 and the L2L chain, each L2L adding to the M2L
     // sum (the coarse chain of small launches is otherwise the step's longest path).
     const bool coarse_side = fine_apart && D >= 4 && o->p2p_fft && nb >= 4;
-    for (int l = D - 1; l >= 2; --l) {
+    for (int l = D - 1; l >= lmin; --l) {
+        const int64_t nbl = (int64_t)R << (3 * l);   // boxes of level l
         if (lowp) {
-            const size_t so = (size_t)(l - 2) * 8 * KU * KU;
-            const int64_t nin = ((int64_t)1 << (3 * (l + 1))) * KU;
+            const size_t so = (size_t)(l - lmin) * 8 * KU * KU;
+            const int64_t nin = 8 * nbl * KU;
             PassTimer pt(o, KIFMM_PASS_M2M, st);
             if (precision == KIFMM_BF16)
                 KIFMM_TRY(lowp_pass<__bf16>(o, o->m2mbf + so, (int64_t)KU * KU, KU, KU, (const float *)o->cu[l + 1], nin,
-                                            KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, (int64_t)1 << (3 * l), 0,
+                                            KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, nbl, 0,
                                             o->m2m_scale[l], nz_of(o, l + 1), nullptr, true, st));
             else
                 KIFMM_TRY(lowp_pass<_Float16>(o, o->m2mh + so, (int64_t)KU * KU, KU, KU, (const float *)o->cu[l + 1], nin,
-                                              KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, (int64_t)1 << (3 * l), 0,
+                                              KU, (float *)o->cu[l], KU, SRC_CHILD, o->t_m2m, 1, nbl, 0,
                                               o->m2m_scale[l], nz_of(o, l + 1), nullptr, true, st));
         } else {
-            const T *A = ops.m2m + (size_t)(l - 2) * 8 * KU * KU;
+            const T *A = ops.m2m + (size_t)(l - lmin) * 8 * KU * KU;
             PassTimer pt(o, KIFMM_PASS_M2M, st);
             auto p = tap<T, T>(A, (int64_t)KU * KU, KU, KU, (T *)o->cu[l + 1], KU, (T *)o->cu[l], KU, SRC_CHILD, 0,
-                               o->t_m2m, 1, (int64_t)1 << (3 * l), 0);
+                               o->t_m2m, 1, nbl, 0);
             p.in_nz = nz_of(o, l + 1);
             if constexpr (sizeof(T) == 4) {
                 p.part = o->part;
@@ -1613,17 +1697,18 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         }
         KIFMM_HIP(hipEventRecord(o->join, side));
     }
-    for (int l = 2; l <= D; ++l) {
+    for (int l = lmin; l <= D; ++l) {
         // cd[l] holds the M2L sum already: the finest level (own stream), the coarse levels
         // 3 .. D - 1 (near-field stream)
         const bool m2l_done = (fine_apart && l == D) || (coarse_side && l >= 3);
-        if (l > 2) {
+        const int64_t npar = (int64_t)R << (3 * (l - 1));   // boxes of level l - 1 (l > lmin)
+        if (l > lmin) {
             if (fine_apart && l == D) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
             else if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             if (lowp) {
-                const size_t so = (size_t)(l - 3) * 8 * KD * KD;
-                const int64_t nin = ((int64_t)1 << (3 * (l - 1))) * KD, nper = (int64_t)1 << (3 * (l - 1));
+                const size_t so = (size_t)(l - lmin - 1) * 8 * KD * KD;
+                const int64_t nin = npar * KD, nper = npar;
                 if (precision == KIFMM_BF16)
                     KIFMM_TRY(lowp_pass<__bf16>(o, o->l2lbf + so, (int64_t)KD * KD, KD, KD, (const float *)o->cd[l - 1], nin,
                                                 KD, (float *)o->cd[l], KD, SRC_PARENT, o->t_l2l, 8, nper, m2l_done ? 1 : 0,
@@ -1633,16 +1718,16 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
                                                   KD, (float *)o->cd[l], KD, SRC_PARENT, o->t_l2l, 8, nper, m2l_done ? 1 : 0,
                                                   o->l2l_scale[l], nullptr, want_of(o, l), false, st));
             } else {
-                const T *A = ops.l2l + (size_t)(l - 3) * 8 * KD * KD;
+                const T *A = ops.l2l + (size_t)(l - lmin - 1) * 8 * KD * KD;
                 auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
-                                   0, o->t_l2l, 8, (int64_t)1 << (3 * (l - 1)), m2l_done ? 1 : 0);
+                                   0, o->t_l2l, 8, npar, m2l_done ? 1 : 0);
                 p.out_need = want_of(o, l);
                 KIFMM_TRY(run(p, st));
             }
         }
         if (m2l_done) continue;
         PassTimer pt(o, KIFMM_PASS_M2L, st);
-        KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > 2 ? 1 : 0, st));
+        KIFMM_TRY(m2l_level<T>(o, ops, l, precision, l > lmin ? 1 : 0, st));
     }
     if (fused_out) {   // the local expansions at the cells, plus the near field, in grid order
         KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
@@ -1706,6 +1791,12 @@ int kifmm_precompute_operators(kifmm_tree tree, const kifmm_kernel *kernel, cons
     ops->ell = tree->ell;
     ops->s = tree->s;
     ops->nb = tree->nb;
+    ops->ellz = tree->ellz;
+    ops->R = tree->R;
+    // coarsest level with expansions: a cube's levels 0 and 1 have no interaction lists; on a
+    // column of two cubes level 0 has none (the two roots are adjacent), from three on the
+    // roots two or more apart interact at level 0
+    ops->lmin = tree->R > 2 ? 0 : (tree->R == 2 ? 1 : 2);
     ops->kern = *kernel;
     ops->opts = o;
     int rc = build_ops(tree, ops, (hipStream_t)stream);
@@ -1754,10 +1845,10 @@ int kifmm_ops_skip_zero_sources(kifmm_ops ops, int32_t enable) {
         ops->skip_zero = false;
         return KIFMM_OK;
     }
-    if (ops->D >= 2 && ops->nz.empty()) {
+    if (ops->D >= ops->lmin && ops->nz.empty()) {
         ops->nz.assign(ops->D + 1, nullptr);
-        for (int l = 2; l <= ops->D; ++l) {
-            const int rc = dmalloc(&ops->nz[l], (size_t)1 << (3 * l));
+        for (int l = ops->lmin; l <= ops->D; ++l) {
+            const int rc = dmalloc(&ops->nz[l], (size_t)ops->R << (3 * l));
             if (rc != KIFMM_OK) {
                 for (uint8_t *p : ops->nz)
                     if (p) (void)hipFree(p);
@@ -1817,16 +1908,19 @@ int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask) {
         ops->want.clear();
         return KIFMM_OK;
     }
-    const int D = ops->D, nb = ops->nb;
-    // host flags per level: leaves by Morton code, then each parent the OR of its 8 children
+    const int D = ops->D, nb = ops->nb, R = ops->R;
+    // host flags per level: leaves by root and Morton code, then each parent the OR of its 8
+    // children
     std::vector<std::vector<uint8_t>> h(D + 1);
-    h[D].assign((size_t)nb * nb * nb, 0);
+    const size_t nbz = (size_t)R * nb;
+    h[D].assign((size_t)R * nb * nb * nb, 0);
     for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b)
-            for (int c = 0; c < nb; ++c)
-                h[D][morton_encode(a, b, c)] = leaf_mask[((size_t)a * nb + b) * nb + c] != 0;
+            for (size_t c = 0; c < nbz; ++c)
+                h[D][((c / nb) << (3 * D)) + morton_encode(a, b, (uint32_t)(c % nb))] =
+                    leaf_mask[((size_t)a * nb + b) * nbz + c] != 0;
     for (int l = D - 1; l >= 0; --l) {
-        h[l].assign((size_t)1 << (3 * l), 0);
+        h[l].assign((size_t)R << (3 * l), 0);
         for (size_t i = 0; i < h[l].size(); ++i)
             for (int k = 0; k < 8; ++k) h[l][i] |= h[l + 1][8 * i + k];
     }

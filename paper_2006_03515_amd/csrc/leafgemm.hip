@@ -221,7 +221,7 @@ int launch_pack_fragments(const float *A, int rows, int cols, int lda, float4 *f
 // The fused kernels apply to FP32 evaluations on leaves of 8^3 cells with at least 4 leaves
 // per axis (n % 32 == 0), 16-byte aligned fields, KU % 32 == 0 and KD % 8 == 0, KD <= 256.
 bool leafgemm_fits(const Tree &t, int KU, int KD) {
-    return t.ell == 8 && t.n % 32 == 0 && t.nb >= 4 && KU % 32 == 0 && KU > 0 && KD % 8 == 0 && KD > 0 &&
+    return t.ell == 8 && t.ellz == 8 && t.R == 1 && t.n % 32 == 0 && t.nb >= 4 && KU % 32 == 0 && KU > 0 && KD % 8 == 0 && KD > 0 &&
            KD <= 256;
 }
 

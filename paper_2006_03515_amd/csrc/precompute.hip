@@ -48,22 +48,23 @@ __global__ void kmat_kernel(const double *__restrict__ X, int nX, const double *
 }
 
 // Near-range matrix of tap t (neighbour offset o_t in leaves): row = target cell
-// li (C order in the leaf), column = source cell lj of the neighbour leaf.
-// Cell offset d = li - lj - ell * o_t (integers), R = h |d|.
-__global__ void near_kernel(int ell, double h, const int *__restrict__ offs, KParams p,
+// li (C order in the leaf of ell x ell x ellz cells), column = source cell lj of the
+// neighbour leaf.  Cell offset d = li - lj - (ell, ell, ellz) * o_t (integers),
+// R = |(h dx, h dy, hz dz)|.
+__global__ void near_kernel(int ell, int ellz, double h, double hz, const int *__restrict__ offs, KParams p,
                             double *__restrict__ out) {
     const int t = blockIdx.y;
-    const int s = ell * ell * ell;
+    const int s = ell * ell * ellz;
     const int64_t total = (int64_t)s * s;
     const int ox = offs[3 * t], oy = offs[3 * t + 1], oz = offs[3 * t + 2];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int li = (int)(e / s), lj = (int)(e % s);
-        const int ix = li / (ell * ell), iy = (li / ell) % ell, iz = li % ell;
-        const int jx = lj / (ell * ell), jy = (lj / ell) % ell, jz = lj % ell;
+        const int ix = li / (ell * ellz), iy = (li / ellz) % ell, iz = li % ellz;
+        const int jx = lj / (ell * ellz), jy = (lj / ellz) % ell, jz = lj % ellz;
         const double dx = (double)(ix - jx - ell * ox) * h;
         const double dy = (double)(iy - jy - ell * oy) * h;
-        const double dz = (double)(iz - jz - ell * oz) * h;
+        const double dz = (double)(iz - jz - ellz * oz) * hz;
         out[(int64_t)t * total + e] = kval(dx * dx + dy * dy + dz * dz, p);
     }
 }
@@ -245,14 +246,16 @@ unsigned blocks_for(int64_t total) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers ----
-KParams make_params(const kifmm_kernel &k, double h) {
+// kernel parameters; the self-cell value of the discrete kernel (after eq. (summation)) for
+// cells of h x h x hz
+KParams make_params(const kifmm_kernel &k, double h, double hz) {
     const double ln = std::log(k.chi_max / k.chi_min);
     const double a = k.chi_min * k.p_o2, b = k.chi_max * k.p_o2;
     KParams p;
     p.a = a;
     p.bma = b - a;
     p.c = 1.0 / (4.0 * M_PI * ln);
-    const double s2 = 3.0 * h * h;
+    const double s2 = 2.0 * h * h + hz * hz;
     const double rho = std::sqrt(s2 / 12.0);
     const double grho = -std::exp(-a * rho) * std::expm1(-(b - a) * rho) / (rho * ln);
     p.self = 3.0 * grho / (M_PI * s2);
@@ -262,18 +265,18 @@ KParams make_params(const kifmm_kernel &k, double h) {
 int launch_kmat(const double *X, int nX, const double *Y, int nY, const double *sx,
                 const double *sy, int batch, int transpose, const kifmm_kernel &k, double h,
                 double *out, hipStream_t st) {
-    KParams p = make_params(k, h);
+    KParams p = make_params(k, h, h);
     hipLaunchKernelGGL(kmat_kernel, dim3(blocks_for((int64_t)nX * nY), batch), dim3(256), 0, st,
                        X, nX, Y, nY, sx, sy, transpose, p, out);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
-int launch_near(int ell, double h, const int *offs_dev, int ntaps, const kifmm_kernel &k,
+int launch_near(int ell, int ellz, double h, double hz, const int *offs_dev, int ntaps, const kifmm_kernel &k,
                 double *out, hipStream_t st) {
-    KParams p = make_params(k, h);
-    const int64_t s = (int64_t)ell * ell * ell;
-    hipLaunchKernelGGL(near_kernel, dim3(blocks_for(s * s), ntaps), dim3(256), 0, st, ell, h,
+    KParams p = make_params(k, h, hz);
+    const int64_t s = (int64_t)ell * ell * ellz;
+    hipLaunchKernelGGL(near_kernel, dim3(blocks_for(s * s), ntaps), dim3(256), 0, st, ell, ellz, h, hz,
                        offs_dev, p, out);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;

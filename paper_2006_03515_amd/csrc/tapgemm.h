@@ -22,6 +22,7 @@ struct TapArgs {
     int64_t out_ld;
     int mode;             // SrcMode
     int nl;               // boxes per axis of the source level (SRC_NBR)
+    int zroots;           // SRC_NBR: cubes of nl^3 boxes stacked along z (0 or 1: independent samples)
     int nclass;           // number of output classes
     int cls_stride;       // output box = cls_stride * j + class
     int64_t n_per_class;

@@ -63,23 +63,31 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-__device__ inline int64_t source_box(int mode, int64_t b, int off, int nl) {
+// zr <= 1: b = sample * nl^3 + morton(x, y, z), neighbours stay inside the sample (the
+// surrogate's batches, or the single cube of the tree).  zr > 1: the level is a column of
+// zr cubes of nl^3 boxes stacked along z (a tree over a box of zr cubes), b = root *
+// nl^3 + morton(x, y, z - root nl), and neighbours cross from one cube into the next.
+__device__ inline int64_t source_box(int mode, int64_t b, int off, int nl, int zr = 1) {
     switch (mode) {
         case SRC_SAME: return b;
         case SRC_CHILD: return 8 * b + off;
         case SRC_PARENT: return b >> 3;
         default: {
-            // b = sample * nl^3 + morton(x, y, z); neighbours stay inside the sample
             int lg = 0;
             while ((1 << lg) < nl) ++lg;
-            const int64_t base = (b >> (3 * lg)) << (3 * lg);
+            const int64_t root = b >> (3 * lg);
             int x, y, z;
-            morton_decode((uint32_t)(b - base), x, y, z);
+            morton_decode((uint32_t)(b - (root << (3 * lg))), x, y, z);
             x += ((off >> 10) & 31) - 16;
             y += ((off >> 5) & 31) - 16;
             z += (off & 31) - 16;
-            if (x < 0 || y < 0 || z < 0 || x >= nl || y >= nl || z >= nl) return -1;
-            return base + (int64_t)morton_encode(x, y, z);
+            if (zr <= 1) {
+                if (x < 0 || y < 0 || z < 0 || x >= nl || y >= nl || z >= nl) return -1;
+                return (root << (3 * lg)) + (int64_t)morton_encode(x, y, z);
+            }
+            const int64_t zg = root * nl + z;   // z in the column
+            if (x < 0 || y < 0 || zg < 0 || x >= nl || y >= nl || zg >= (int64_t)zr * nl) return -1;
+            return ((zg >> lg) << (3 * lg)) + (int64_t)morton_encode(x, y, (uint32_t)(zg & (nl - 1)));
         }
     }
 }
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(256) void tapgemm_f32_small(TapArgs<float, float, f
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int64_t j = j0 + r * 32 + lrow;
-                lsrc[r] = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+                lsrc[r] = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
             }
         }
         const int k = kc * BK + lk;
@@ -307,7 +315,7 @@ __device__ inline int active_taps(const TapArgs<TA, TI, TO> &p, int cls, int t0,
     for (int t = t0 + wave; t < t1; t += 4) {   // one wave per tap, one lane per box
         const int off = tap_op_of(p.tap_off, p.inl_off, cls * p.ntaps + t);
         const int64_t j = j0 + lane;
-        const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+        const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
         const bool live = src >= 0 && p.in_nz[src] != 0;
         const uint64_t any = __ballot(live);
         if (lane == 0) flags[t - t0] = any != 0;
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(256) void tapgemm_f32_staged(TapArgs<float, float, 
 #pragma unroll
             for (int r = 0; r < BR; ++r) {
                 const int64_t j = j0 + (r * 4 + wave) * 8 + (lane >> 3);
-                const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+                const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
                 bsrc[r] = src >= 0 ? p.in + src * p.in_ld : nullptr;
             }
         }
@@ -612,7 +620,7 @@ __global__ __launch_bounds__(256) void tapgemm_lp(TapArgs<TL, float, float> p) {
             Ahi = p.A + (int64_t)op * p.a_stride;
             if (X3) Alo = p.A2 + (int64_t)op * p.a_stride;
             const int64_t j = j0 + lrow;
-            lsrc = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+            lsrc = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
         }
         const int k = kc * LBK + lk;
 #pragma unroll
@@ -734,7 +742,7 @@ __global__ __launch_bounds__(256) void tapgemm_valu(TapArgs<T, T, T> p) {
         __syncthreads();
         if (tid < VN) {
             const int64_t j = j0 + tid;
-            srcs[tid] = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+            srcs[tid] = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
         }
         __syncthreads();
         const T *Aop = p.A + (int64_t)op * p.a_stride;
@@ -1040,7 +1048,7 @@ __global__ __launch_bounds__(256) void tapgemm_lp_staged(TapArgs<TL, TL, float> 
             Ahi = p.A + (int64_t)op * p.a_stride;
             if (NP == 3) Alo = p.A2 + (int64_t)op * p.a_stride;
             const int64_t j = j0 + bbox;
-            const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl) : -1;
+            const int64_t src = j < p.n_per_class ? source_box(p.mode, (int64_t)p.cls_stride * j + cls, off, p.nl, p.zroots) : -1;
             bsrc = src >= 0 ? src * p.in_ld + b_kq * 8 : -1;
         }
         const int k = kc * 32;

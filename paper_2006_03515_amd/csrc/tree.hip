@@ -1,8 +1,10 @@
-// Octree over a uniform n^3 grid (Section 3, tree construction step).
+// Octree over a uniform grid (Section 3, tree construction step).
 //
-// The complete octree with ell^3-cell leaves is visited in pre-order by the
-// Morton order of the leaves.  Every cell gets the key
-//     key = morton(leaf coordinates) * ell^3 + (C-order index inside the leaf)
+// The complete octree with ell x ell x ellz-cell leaves (one per root cube; a box grid
+// is a column of R root cubes along z) is visited in pre-order by the Morton order of
+// the leaves, root after root.  Every cell gets the key
+//     key = (root * nb^3 + morton(leaf coordinates in its root)) * s
+//           + (C-order index inside the leaf),   s = ell^2 ellz
 // Keys are distinct and cover [0, N) exactly, so sorting the cells by key is a
 // single scatter perm[key] = cell (a counting sort whose buckets hold one cell
 // each).  perm is kept for callers; the evaluation's permutes recompute
@@ -13,64 +15,84 @@ namespace kifmm {
 
 namespace {
 
-__global__ void morton_scatter_kernel(int n, int ell, int lg_ell, int64_t N, int32_t *perm) {
+// Shape of the leaf order (all sides powers of two): lg of ell, ellz, nb; n, nz
+struct Shape {
+    int n, nz, lg_ell, lg_ellz, lg_nb;
+};
+
+Shape shape_of(const Tree &t) {
+    auto lg = [](int v) { int l = 0; while ((1 << l) < v) ++l; return l; };
+    return Shape{t.n, t.nz, lg(t.ell), lg(t.ellz), lg(t.nb)};
+}
+
+// leaf-ordered slot of grid cell (i, j, k)
+__device__ inline int64_t slot_of_cell(int i, int j, int k, const Shape &sh) {
+    const int lz_all = k >> sh.lg_ellz;                       // leaf z in the column
+    const int root = lz_all >> sh.lg_nb, lz = lz_all & ((1 << sh.lg_nb) - 1);
+    const int64_t leaf = ((int64_t)root << (3 * sh.lg_nb)) + morton_encode(i >> sh.lg_ell, j >> sh.lg_ell, lz);
+    const int mx = (1 << sh.lg_ell) - 1, mz = (1 << sh.lg_ellz) - 1;
+    const int64_t local = ((int64_t)(i & mx) << (sh.lg_ell + sh.lg_ellz)) + ((j & mx) << sh.lg_ellz) + (k & mz);
+    return (leaf << (2 * sh.lg_ell + sh.lg_ellz)) + local;
+}
+
+__global__ void morton_scatter_kernel(Shape sh, int64_t N, int32_t *perm) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < N;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(g / ((int64_t)n * n));
-        const int j = (int)((g / n) % n);
-        const int k = (int)(g % n);
-        const uint32_t leaf = morton_encode(i >> lg_ell, j >> lg_ell, k >> lg_ell);
-        const int mask = ell - 1;
-        const int64_t local = (((int64_t)(i & mask) * ell) + (j & mask)) * ell + (k & mask);
-        const int64_t key = (int64_t)leaf * ((int64_t)ell * ell * ell) + local;
-        perm[key] = (int32_t)g;
+        const int i = (int)(g / ((int64_t)sh.n * sh.nz));
+        const int j = (int)((g / sh.nz) % sh.n);
+        const int k = (int)(g % sh.nz);
+        perm[slot_of_cell(i, j, k, sh)] = (int32_t)g;
     }
 }
 
-// Grid index of leaf-ordered slot p (the inverse of the key above): p = leaf * ell^3 +
-// local, leaf a Morton code of leaf coordinates, local the C-order index inside it.
-__device__ inline int64_t cell_of_slot(int64_t p, int n, int lg_ell) {
-    const int lg_s = 3 * lg_ell, mask = (1 << lg_ell) - 1;
-    const uint32_t leaf = (uint32_t)(p >> lg_s);
+// Grid index of leaf-ordered slot p (the inverse of slot_of_cell): p = leaf * s + local,
+// leaf = root * nb^3 + a Morton code of leaf coordinates in the root, local the C-order
+// index inside the leaf.
+__device__ inline int64_t cell_of_slot(int64_t p, const Shape &sh) {
+    const int lg_s = 2 * sh.lg_ell + sh.lg_ellz;
+    const int64_t leaf = p >> lg_s;
     const int local = (int)(p & ((1 << lg_s) - 1));
+    const int64_t root = leaf >> (3 * sh.lg_nb);
     int lx, ly, lz;
-    morton_decode(leaf, lx, ly, lz);
-    const int i = (lx << lg_ell) | (local >> (2 * lg_ell));
-    const int j = (ly << lg_ell) | ((local >> lg_ell) & mask);
-    const int k = (lz << lg_ell) | (local & mask);
-    return ((int64_t)i * n + j) * n + k;
+    morton_decode((uint32_t)(leaf & ((1ll << (3 * sh.lg_nb)) - 1)), lx, ly, lz);
+    const int i = (lx << sh.lg_ell) | (local >> (sh.lg_ell + sh.lg_ellz));
+    const int j = (ly << sh.lg_ell) | ((local >> sh.lg_ellz) & ((1 << sh.lg_ell) - 1));
+    const int64_t k = (((root << sh.lg_nb) + lz) << sh.lg_ellz) | (local & ((1 << sh.lg_ellz) - 1));
+    return ((int64_t)i * sh.n + j) * sh.nz + k;
 }
 
 // q[p] = scale * I[cell(p)] (FP32 or FP64 in, same type out)
 template <typename T>
-__global__ void permute_in_kernel(const T *__restrict__ I, int n, int lg_ell, int64_t N, T scale, T *__restrict__ q) {
+__global__ void permute_in_kernel(const T *__restrict__ I, Shape sh, int64_t N, T scale, T *__restrict__ q) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x)
-        q[p] = I[cell_of_slot(p, n, lg_ell)] * scale;
+        q[p] = I[cell_of_slot(p, sh)] * scale;
 }
 
-// S[cell(p)] = scale * Sp[p], or 0 where want (one byte per leaf, Morton order; null: every
+// S[cell(p)] = scale * Sp[p], or 0 where want (one byte per leaf, leaf order; null: every
 // leaf is wanted) marks the leaf of slot p as not wanted
 template <typename T>
-__global__ void permute_out_kernel(const T *__restrict__ Sp, int n, int lg_ell, int64_t N, T scale,
+__global__ void permute_out_kernel(const T *__restrict__ Sp, Shape sh, int64_t N, T scale,
                                    const uint8_t *__restrict__ want, T *__restrict__ S) {
+    const int lg_s = 2 * sh.lg_ell + sh.lg_ellz;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x) {
         T v = 0;
-        if (!want || want[p >> (3 * lg_ell)]) v = Sp[p] * scale;
-        S[cell_of_slot(p, n, lg_ell)] = v;
+        if (!want || want[p >> lg_s]) v = Sp[p] * scale;
+        S[cell_of_slot(p, sh)] = v;
     }
 }
 
 // S[cell(p)] = scale * (Sa[p] + Sb[p])  (far field + near field), 0 where not wanted
 template <typename T>
-__global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb, int n, int lg_ell,
+__global__ void permute_out2_kernel(const T *__restrict__ Sa, const T *__restrict__ Sb, Shape sh,
                                     int64_t N, T scale, const uint8_t *__restrict__ want, T *__restrict__ S) {
+    const int lg_s = 2 * sh.lg_ell + sh.lg_ellz;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x) {
         T v = 0;
-        if (!want || want[p >> (3 * lg_ell)]) v = (Sa[p] + Sb[p]) * scale;
-        S[cell_of_slot(p, n, lg_ell)] = v;
+        if (!want || want[p >> lg_s]) v = (Sa[p] + Sb[p]) * scale;
+        S[cell_of_slot(p, sh)] = v;
     }
 }
 
@@ -148,31 +170,29 @@ unsigned grid_for(int64_t N) {
 }  // namespace
 
 int launch_morton_scatter(const Tree &t, hipStream_t st) {
-    hipLaunchKernelGGL(morton_scatter_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, t.n, t.ell,
-                       lg_of(t.ell), t.N, t.perm);
+    hipLaunchKernelGGL(morton_scatter_kernel, dim3(grid_for(t.N)), dim3(256), 0, st, shape_of(t), t.N, t.perm);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
 template <typename T>
 int launch_permute_in(const Tree &t, const T *I, T scale, T *q, hipStream_t st) {
-    if (sizeof(T) == 4 && t.ell == 8 && t.n % 32 == 0 && (uintptr_t)I % 16 == 0) {   // whole 128-byte rows
+    if (sizeof(T) == 4 && t.ell == 8 && t.ellz == 8 && t.R == 1 && t.n % 32 == 0 && (uintptr_t)I % 16 == 0) {   // whole 128-byte rows
         const int64_t nrows = t.N / 32;
         hipLaunchKernelGGL(permute_in_rows_kernel, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
                            (const float *)I, t.n, nrows, (float)scale, (float *)q);
         KIFMM_HIP(hipGetLastError());
         return KIFMM_OK;
     }
-    hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, t.n, lg_of(t.ell),
-                       t.N, scale, q);
+    hipLaunchKernelGGL(permute_in_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, I, shape_of(t), t.N, scale, q);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
 
 template <typename T>
 int launch_permute_out(const Tree &t, const T *Sp, T scale, const uint8_t *want, T *S, hipStream_t st) {
-    hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, t.n, lg_of(t.ell),
-                       t.N, scale, want, S);
+    hipLaunchKernelGGL(permute_out_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sp, shape_of(t), t.N, scale,
+                       want, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
@@ -180,15 +200,15 @@ int launch_permute_out(const Tree &t, const T *Sp, T scale, const uint8_t *want,
 template <typename T>
 int launch_permute_out2(const Tree &t, const T *Sa, const T *Sb, T scale, const uint8_t *want, T *S,
                         hipStream_t st) {
-    if (sizeof(T) == 4 && t.ell == 8 && (uintptr_t)S % 16 == 0) {   // whole 8-cell lines
+    if (sizeof(T) == 4 && t.ell == 8 && t.ellz == 8 && t.R == 1 && (uintptr_t)S % 16 == 0) {   // whole 8-cell lines
         const int64_t nlines = t.N / 8;
         hipLaunchKernelGGL(permute_out2_lines_kernel, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st,
                            (const float *)Sa, (const float *)Sb, t.n, nlines, (float)scale, want, (float *)S);
         KIFMM_HIP(hipGetLastError());
         return KIFMM_OK;
     }
-    hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, t.n,
-                       lg_of(t.ell), t.N, scale, want, S);
+    hipLaunchKernelGGL(permute_out2_kernel<T>, dim3(grid_for(t.N)), dim3(256), 0, st, Sa, Sb, shape_of(t), t.N,
+                       scale, want, S);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }

@@ -26,7 +26,7 @@ EXPORTS = ("kifmm_build_tree", "kifmm_precompute_operators", "kifmm_ops_rank", "
            "kifmm_eval", "direct_eval", "kifmm_tree_permutation", "kifmm_tree_destroy",
            "kifmm_ops_destroy", "kifmm_last_error", "kifmm_profile_enable", "kifmm_profile_read",
            "kifmm_ops_skip_zero_sources", "kifmm_ops_restrict_targets", "kifmm_ops_m2l_fft",
-           "kifmm_ops_p2p_fft", "kifmm_ops_serial",
+           "kifmm_ops_p2p_fft", "kifmm_ops_serial", "kifmm_tree_shape",
            "kifmm_nn_layer_forward", "kifmm_nn_layer_backward_data", "kifmm_nn_layer_backward_weight",
            "kifmm_nn_prepare_weights", "kifmm_nn_bias_act", "kifmm_nn_bias_act_backward",
            "kifmm_nn_rel_l2_loss", "kifmm_nn_adam", "kifmm_nn_pack_input", "kifmm_nn_unpack_output",
@@ -71,6 +71,8 @@ def load_library(path=LIB_PATH):
     lib.kifmm_ops_rank.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]
     lib.kifmm_tree_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.kifmm_tree_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
     lib.kifmm_eval.argtypes = [P, P, P, ctypes.c_double, P, ctypes.c_int32, P]
     lib.direct_eval.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Kernel), P, ctypes.c_double, P,
                                 ctypes.c_int64, P, ctypes.c_int32, P]
@@ -179,6 +181,12 @@ class Tree:
         d, e = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.kifmm_tree_info(handle, ctypes.byref(d), ctypes.byref(e)))
         self.depth, self.leaf_side = d.value, e.value
+        ez, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.kifmm_tree_shape(handle, None, ctypes.byref(ez), ctypes.byref(r)))
+        # leaf cells (x, y, z) and root cubes stacked along z (1 for a cubic grid)
+        self.leaf_shape, self.roots = (e.value, e.value, ez.value), r.value
+        nb = self.grid.n[0] // e.value
+        self.leaves = (nb, nb, self.roots * nb)   # leaves per axis (the restriction mask's shape)
 
     def permutation(self, stream=None):
         out = torch.empty(self.grid.N, dtype=torch.int64, device="cuda")
@@ -219,16 +227,16 @@ class Ops:
         _check(_lib.kifmm_ops_serial(self.handle, 1 if enable else 0))
 
     def restrict_targets(self, leaf_mask=None):
-        """Evaluate only at the leaves marked in leaf_mask (array of nb^3 values, C order
-        over leaf coordinates, nonzero = wanted); later eval() calls return 0 elsewhere.
-        None evaluates every target again."""
+        """Evaluate only at the leaves marked in leaf_mask (array of the tree's leaves per
+        axis, tree.leaves, C order over leaf coordinates, nonzero = wanted); later eval()
+        calls return 0 elsewhere.  None evaluates every target again."""
         if leaf_mask is None:
             _check(_lib.kifmm_ops_restrict_targets(self.handle, None))
             return
-        nb = self.tree.grid.n[0] // self.tree.leaf_side
+        nl = int(np.prod(self.tree.leaves))
         m = np.ascontiguousarray(np.asarray(leaf_mask).reshape(-1) != 0, dtype=np.uint8)
-        if m.size != nb ** 3:
-            raise ValueError("leaf_mask has %d values, the tree has %d leaves" % (m.size, nb ** 3))
+        if m.size != nl:
+            raise ValueError("leaf_mask has %d values, the tree has %d leaves" % (m.size, nl))
         _check(_lib.kifmm_ops_restrict_targets(self.handle, ctypes.c_void_p(m.ctypes.data)))
 
     def profile(self, on=True):

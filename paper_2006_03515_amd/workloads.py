@@ -203,3 +203,35 @@ def paper_multipeak(dtype=np.float32):
     S = (1.53e25 * f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]).astype(dtype)
     return BoxWorkload("paper_multipeak", shape, h, 760.0, 150.0, XI * OMEGA_OVER_ALPHA * quench(760.0), S,
                        (xd / 2, xd / 2, zd / 2), 0.05)
+
+
+@dataclass
+class ColumnWorkload:
+    """A source on a box of n x n x nz cells of hx = hy != hz (cell centres (i + 1/2) h)."""
+    name: str
+    shape: tuple
+    h: tuple              # (hx, hy, hz) [cm]
+    p: float
+    p_o2: float
+    prefactor: float
+    I: np.ndarray
+    x0: tuple             # centre of the local error ball [cm]
+    delta: float
+
+
+SPEED_OF_LIGHT = 2.99792458e10   # cm / s
+
+
+def paper_pressure(p_o2, dtype=np.float32):
+    """Section 4.2: I = 4 pi xi c exp(-|x - x_s|^2 / sigma^2) (I of eq. (Ifun) itself, so the
+    prefactor is 1), xi = 0.1, sigma = 0.01 cm, on V = [0, 0.25] x [0, 0.25] x [0, 1.4] cm cut
+    into 256 x 256 x 320 cells (hz = 4.48 hx); pO2 / p = 0.2; the source centre x_s and the
+    error ball's centre x0 at the centre of V, delta = 0.05 cm."""
+    shape = (256, 256, 320)
+    ext = (0.25, 0.25, 1.4)
+    h = tuple(e / m for e, m in zip(ext, shape))
+    xc = tuple(e / 2 for e in ext)
+    sigma = 0.01
+    f = [np.exp(-(((np.arange(m) + 0.5) * hh - c) / sigma) ** 2) for m, hh, c in zip(shape, h, xc)]
+    I = (4 * np.pi * XI * SPEED_OF_LIGHT * f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]).astype(dtype)
+    return ColumnWorkload("paper_pressure_%g" % p_o2, shape, h, p_o2 / 0.2, p_o2, 1.0, I, xc, 0.05)

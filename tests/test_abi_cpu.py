@@ -37,10 +37,15 @@ def test_argument_errors_before_device_work():
     h = ctypes.c_void_p()
     # NULL grid
     assert lib.kifmm_build_tree(None, 64, None, ctypes.byref(h)) == K.EINVAL
-    # non-cubic grid, non-power-of-two, bad spacing, bad leaf cap
+    # a box that is not a column of whole cubes of leaves, nx != ny, hx != hy,
+    # non-power-of-two, bad spacing, bad leaf cap
     g = K.Grid((8, 8, 4), (1e-3,) * 3).c()
     assert lib.kifmm_build_tree(ctypes.byref(g), 64, None, ctypes.byref(h)) == K.EUNSUPPORTED
-    assert b"cubic" in lib.kifmm_last_error()
+    assert b"multiple" in lib.kifmm_last_error()
+    g = K.Grid((8, 16, 16), (1e-3,) * 3).c()
+    assert lib.kifmm_build_tree(ctypes.byref(g), 64, None, ctypes.byref(h)) == K.EUNSUPPORTED
+    g = K.Grid((8, 8, 8), (1e-3, 2e-3, 1e-3)).c()
+    assert lib.kifmm_build_tree(ctypes.byref(g), 64, None, ctypes.byref(h)) == K.EUNSUPPORTED
     g = K.Grid((12, 12, 12), (1e-3,) * 3).c()
     assert lib.kifmm_build_tree(ctypes.byref(g), 64, None, ctypes.byref(h)) == K.EUNSUPPORTED
     g = K.Grid((8, 8, 8), (1e-3, 0.0, 1e-3)).c()

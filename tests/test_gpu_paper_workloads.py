@@ -95,6 +95,39 @@ def test_section4_workloads_full_size(K, name, paper_bars, nested_bars, record_p
         del ops
 
 
+# (pO2, paper layout bars, nested layout bars), bars (E_V, E_delta); the paper's own figures at
+# m0 = 6 (Tables 5, 6): E_V 0.15 / 0.19 %, E_delta 1.24 / 0.44 %
+PRESSURE_CASES = [(160.0, (2e-2, 3e-2), (1e-4, 2e-4)), (10.0, (2e-2, 3e-2), (1e-4, 2e-4))]
+
+
+@pytest.mark.parametrize("p_o2,paper_bars,nested_bars", PRESSURE_CASES)
+def test_section42_pressures_full_size(K, p_o2, paper_bars, nested_bars, record_property):
+    # Section 4.2: 256 x 256 x 320 cells with hz = 4.48 hx, as the tree's column of 5 cubes
+    # of leaves of 8 x 8 x 2 cells (no embedding: the box is the column)
+    w = workloads.paper_pressure(p_o2)
+    print("section 4.2, pO2 %g" % p_o2, flush=True)
+    ref = odirect.fft_full(w.I.astype(np.float64), w.h, w.p_o2, prefactor=w.prefactor, workers=16)
+    tree = K.build_tree(K.Grid(w.shape, w.h), 512)
+    assert (tree.leaf_shape, tree.roots) == ((8, 8, 2), 5)
+    I = torch.from_numpy(w.I.ravel()).cuda()
+    kern = K.Kernel(w.p_o2)
+    for lname, opts, (bar_v, bar_d) in (("paper_m0_6", K.Opts(K.LAYOUT_PAPER, 6, 10, 1e-7), paper_bars),
+                                        ("nested_m0_5", K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), nested_bars)):
+        ops = K.precompute_operators(tree, kern, opts)
+        S = K.eval(tree, ops, I, w.prefactor, precision=K.FP32).double().cpu().numpy().reshape(w.shape)
+        ev = metrics.rel_l2(S, ref)
+        c = [(np.arange(m) + 0.5) * hh for m, hh in zip(w.shape, w.h)]
+        sub = tuple(slice(int(np.nonzero(np.abs(cc - x) <= w.delta)[0][0]),
+                          int(np.nonzero(np.abs(cc - x) <= w.delta)[0][-1]) + 1) for cc, x in zip(c, w.x0))
+        cen = np.stack(np.meshgrid(*[cc[sl] for cc, sl in zip(c, sub)], indexing="ij"), -1)
+        ed = metrics.e_delta(S[sub], ref[sub], cen, w.x0, w.delta)
+        record_property(lname, {"E_V": ev, "E_delta": ed})
+        print("section 4.2 pO2 %g %s: E_V %.3e  E_delta %.3e" % (p_o2, lname, ev, ed), flush=True)
+        assert ev < bar_v, (lname, ev)
+        assert ed < bar_d, (lname, ed)
+        del ops
+
+
 def test_zero_source_skipping_is_the_same_sum(K):
     # a box of sources in the low corner of a 64^3 cube (the rest exactly zero), plus a
     # localized Gaussian that underflows to zero far away: skipping the all-zero source

@@ -39,3 +39,33 @@ def test_leaf_order_is_preorder_of_octree(n, ell):
     if nb >= 2:
         first8 = lb[:8]
         assert [tuple(v) for v in first8] == [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+
+
+def test_column_order_hand_worked():
+    # 2 x 2 x 4 cells, leaves of 1 x 1 x 1, so 2 cubes of 2^3 leaves along z: the first 8
+    # positions are the cube z in {0, 1} in octant order (x, y, z) = 000, 001, 010, ...,
+    # the next 8 the cube z in {2, 3}; grid index = (i * 2 + j) * 4 + k
+    perm = morton.column_leaf_order(2, 4, 1, 1)
+    first = [(i * 2 + j) * 4 + k for i in (0, 1) for j in (0, 1) for k in (0, 1)]
+    second = [(i * 2 + j) * 4 + k + 2 for i in (0, 1) for j in (0, 1) for k in (0, 1)]
+    assert perm.tolist() == first + second
+    # leaves of 1 x 1 x 2 cells (ellz = 2): each leaf's two cells are consecutive along z
+    perm = morton.column_leaf_order(2, 8, 1, 2)
+    assert perm[:4].tolist() == [0, 1, 2, 3]          # leaf (0,0,0): cells k = 0, 1; leaf (0,0,1): k = 2, 3
+
+
+@pytest.mark.parametrize("n,nz,ell,ellz", [(8, 24, 4, 4), (16, 40, 8, 2), (8, 8, 4, 4), (4, 20, 4, 4)])
+def test_column_order_invariants(n, nz, ell, ellz):
+    perm = morton.column_leaf_order(n, nz, ell, ellz)
+    assert np.array_equal(np.sort(perm), np.arange(n * n * nz))
+    i, j, k = np.unravel_index(perm, (n, n, nz))
+    s = ell * ell * ellz
+    leaf = np.stack([i // ell, j // ell, k // ellz], 1).reshape(-1, s, 3)
+    assert np.all(leaf == leaf[:, :1, :])            # runs of s cells are one leaf
+    lb = leaf[:, 0, :]
+    nb = n // ell
+    root = lb[:, 2] // nb
+    assert np.all(np.diff(root) >= 0)                # cube after cube upwards
+    # a cube is the Morton (octree pre-order) leaf order of a cube of side nb
+    if nz == n and ellz == ell:
+        assert np.array_equal(perm, morton.leaf_order(n, ell))
