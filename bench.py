@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--pressures", default="100,10",
                     help="further pressures timed with the headline configuration ('' for none)")
     ap.add_argument("--config-128", type=int, default=1, help="also time the 128^3 two-head workload")
+    ap.add_argument("--section42", type=int, default=1,
+                    help="also time the paper's Section 4.2 workload (256 x 256 x 320 cells, hz = 4.48 hx)")
     ap.add_argument("--max-leaf", type=int, default=512)
     ap.add_argument("--layout", default="lattice", choices=["paper", "single", "nested", "lattice"])
     ap.add_argument("--lattice-radius", type=float, default=0.0,
@@ -427,6 +429,44 @@ def main():
                     layout="%s m0=%d rcond=%g" % (lay, m0, rc), precompute_s=round(c.t_pre, 3))
                 del c
 
+    section42 = {}
+    if args.section42:
+        # the paper's pressure study at full size: a column of 5 cubes of leaves of 8 x 8 x 2
+        # cells, nested shells m0 = 5 (the lattice layout's FFT forms need a cube)
+        for p_o2 in (160.0, 10.0):
+            w42 = workloads.paper_pressure(p_o2)
+            log("Section 4.2, pO2 %g" % p_o2)
+            g42 = K.Grid(w42.shape, w42.h)
+            k42 = K.Kernel(w42.p_o2)
+            t0 = time.perf_counter()
+            t42 = K.build_tree(g42, args.max_leaf)
+            o42 = K.precompute_operators(t42, k42, K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5))
+            torch.cuda.synchronize()
+            pre42 = time.perf_counter() - t0
+            I42 = torch.from_numpy(np.ascontiguousarray(w42.I.reshape(-1))).to(case.dev)
+            S42 = torch.empty_like(I42)
+            for _ in range(args.warmup):
+                K.eval(t42, o42, I42, w42.prefactor, out=S42)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(case.stream)
+            for _ in range(args.steps):
+                K.eval(t42, o42, I42, w42.prefactor, out=S42)
+            e1.record(case.stream)
+            torch.cuda.synchronize()
+            ms42 = e0.elapsed_time(e1) / args.steps
+            N42 = int(np.prod(w42.shape))
+            tg42 = torch.from_numpy(workloads.sample_targets(N42, 4096, seed=1042)).to(case.dev)
+            ref42 = K.direct_eval(g42, k42, I42, w42.prefactor, tg42, fp64=True).cpu().numpy()
+            got42 = S42[tg42].double().cpu().numpy()
+            err42 = float(np.linalg.norm(got42 - ref42) / np.linalg.norm(ref42))
+            section42["pO2_%d" % int(p_o2)] = result(
+                N42, ms42, err42, grid="256 x 256 x 320, hz = %.2f hx" % (w42.h[2] / w42.h[0]),
+                tree="%d cubes of leaves %s" % (t42.roots, "x".join(map(str, t42.leaf_shape))),
+                layout="nested m0=5 rcond=1e-5", precompute_s=round(pre42, 3),
+                paper_80_cores_s=24.7371 if p_o2 == 160.0 else 24.8619)
+            del o42, t42, I42, S42
+
     variants = {}
     for v in [x for x in args.variants.split(",") if x]:
         log("timing variant %s" % v)
@@ -513,6 +553,7 @@ def main():
         "leaf_passes": leaf_passes,
         "pressures": pressures,
         "config_128": config_128,
+        "section42": section42,
         "variants": variants,
         "cpu_baseline": cpu,
     }
