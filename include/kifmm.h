@@ -224,14 +224,18 @@ int kifmm_ops_restrict_targets(kifmm_ops ops, const uint8_t *leaf_mask);
  * KIFMM_LAYOUT_LATTICE hold, per level, the spectra of the kernel on the
  * (2 m0 - 1)^3 cyclic grid for the 316 offsets and the maps between coefficients
  * and lattice values (W_u, U_d^T).  With enable != 0 (the default for that layout),
- * the M2L of FP32 and KIFMM_BF16X3 evaluations runs as: equivalent densities on the
- * lattice (FP32 MFMA GEMM), their half spectra (separable DFT), per frequency the
- * products with the kernel spectra over each box's interaction list (grouped by
- * parents into one 16 x 432 real matrix per frequency: FP32 MFMA, or split bfloat16
- * MFMA for KIFMM_BF16X3), check potentials on the lattice (separable inverse DFT)
- * and coefficients (FP32 MFMA GEMM).  FP32 computes the same sum as the dense M2L of
- * the same layout up to FP32 rounding; enable = 0 selects the dense M2L (other
- * precisions always use it).  Returns 0,
+ * the M2L of KIFMM_FP32, KIFMM_BF16X3, KIFMM_M2L_BF16X3, KIFMM_M2L_FP16 and
+ * KIFMM_M2L_BF16 evaluations runs as: equivalent densities on the lattice (FP32 MFMA
+ * GEMM), their half spectra (separable DFT), per frequency the products with the kernel
+ * spectra over each box's interaction list (grouped by parents into one 16 x 432 real
+ * matrix per frequency: FP32 MFMA; split bfloat16 MFMA for the two BF16X3 modes; single
+ * FP16 or bfloat16 operands for KIFMM_M2L_FP16 / KIFMM_M2L_BF16, each frequency's matrix
+ * and each workgroup's spectra scaled by powers of two into FP16's range), check
+ * potentials on the lattice (separable inverse DFT) and coefficients (FP32 MFMA GEMM).
+ * The levels with fewer than 4 parents per axis keep the products in FP32.  FP32
+ * computes the same sum as the dense M2L of the same layout up to FP32 rounding;
+ * enable = 0 selects the dense M2L (FP64, KIFMM_BF16 and KIFMM_FP16 always use it).
+ * Returns 0,
  * KIFMM_EINVAL (ops NULL) or KIFMM_EUNSUPPORTED (another layout). */
 int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
 
@@ -380,6 +384,8 @@ int kifmm_nn_sampled_rel_err(int64_t n_tgt, const float *S, const int64_t *tgt, 
                              double scale, double *out, void *stream);
 /* x[0:n] *= s (a prediction made for prefactor 1, rescaled) */
 int kifmm_nn_scale(int64_t n, float *x, float s, void *stream);
+/* y[0:n] += x[0:n] (the gradient of a skip connection's source, summed over its two uses) */
+int kifmm_nn_add(int64_t n, const float *x, float *y, void *stream);
 /* out[0] = ||S[tgt] - R[tgt]|| / ||R[tgt]|| for two FP32 fields in grid order (one workgroup,
  * FP64 sums in a fixed order): the serving check of a prediction S against a judge's field R */
 int kifmm_nn_sampled_rel_diff(int64_t n_tgt, const float *S, const float *R, const int64_t *tgt, double *out,

@@ -52,6 +52,8 @@ int run_m2l_hadamard(const float *, const float *, const int *, const int *, int
                      const uint8_t *, float *, hipStream_t);
 int run_m2l_pair_mfma(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
 int run_m2l_pair_bf16x3(const float *, const float *, int, int, const uint8_t *, const uint8_t *, float *, hipStream_t);
+int run_m2l_pair_lp1(int, const float *, const void *, const float *, int, int, const uint8_t *, const uint8_t *, float *,
+                     hipStream_t);
 int run_m2l_lattice(int, int, const float *, int64_t, int, int, const uint8_t *, float *, hipStream_t);
 int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, const uint8_t *, float *, float *,
                        float *, hipStream_t);
@@ -216,6 +218,9 @@ struct kifmm_ops_s {
     float *lat_buf = nullptr, *lat_buf_c = nullptr, *spec_e_c = nullptr, *spec_p_c = nullptr;
     std::vector<float *> fft_pair;   // levels with >= 8 boxes per axis: [nfp][27][64][4] MFMA fragments
     std::vector<float *> fft_pair_bf;   // the same as split BF16 fragments [nfp][14][64][16] (KIFMM_BF16X3)
+    std::vector<float *> fft_pair_h;    // single FP16 fragments [nfp][14][64][8], scaled per frequency (KIFMM_M2L_FP16)
+    std::vector<float *> fft_pair_b1;   // single BF16 fragments, the same layout and scaling (KIFMM_M2L_BF16)
+    std::vector<float *> fft_pair_us;   // [nfp] the inverse of each frequency's fragment scale
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
     // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
     // [nleaf][1920] complex, and the sums after the first inverse stage [nleaf][120][8]
@@ -340,7 +345,8 @@ static void free_ops(kifmm_ops o) {
         if (p) (void)hipFree(p);
     for (uint8_t *p : o->want)
         if (p) (void)hipFree(p);
-    for (auto *v : {&o->fft_g, &o->lat_w, &o->lat_u, &o->fft_pair, &o->fft_pair_bf})
+    for (auto *v : {&o->fft_g, &o->lat_w, &o->lat_u, &o->fft_pair, &o->fft_pair_bf, &o->fft_pair_h, &o->fft_pair_b1,
+                    &o->fft_pair_us})
         for (float *p : *v)
             if (p) (void)hipFree(p);
     for (double *p : o->cd)
@@ -817,6 +823,9 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
     o->lat_u.assign(D + 1, nullptr);
     o->fft_pair.assign(D + 1, nullptr);
     o->fft_pair_bf.assign(D + 1, nullptr);
+    o->fft_pair_h.assign(D + 1, nullptr);
+    o->fft_pair_b1.assign(D + 1, nullptr);
+    o->fft_pair_us.assign(D + 1, nullptr);
     // offset -> index into the 316 offsets, for the parent-pair matrices
     std::vector<int> oidx(343, -1);
     for (int t = 0; t < n316; ++t)
@@ -906,6 +915,53 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
                     }
             KIFMM_TRY(dmalloc(&o->fft_pair_bf[l], ab.size() / 2));   // counted in floats
             KIFMM_HIP(hipMemcpyAsync(o->fft_pair_bf[l], ab.data(), ab.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+            KIFMM_HIP(hipStreamSynchronize(st));
+            // Single-part FP16 and BF16 fragments, [f][k-step (14)][lane][8] in the k order of
+            // the split form, each frequency's matrix scaled by 2^(14 - e) (e the exponent of its
+            // largest magnitude, so the entries fit FP16's range); us[f] undoes the scale.
+            std::vector<float> smax(nfp, 0.f), us(nfp, 1.f);
+            for (int ks = 0; ks < 14; ++ks)
+                for (int ln = 0; ln < 64; ++ln)
+                    for (int j = 0; j < 8; ++j) {
+                        const int row = ln & 15, k = 32 * ks + 8 * (ln >> 4) + j, q = k / 16;
+                        if (q >= 27) continue;
+                        const int kd = 16 * (q == 13 ? 26 : (q == 26 ? 13 : q)) + k % 16;
+                        const int t = offset_of(row, kd);
+                        if (t < 0) continue;
+                        for (int f = 0; f < nf; ++f)
+                            smax[f] = std::max(smax[f], (float)std::fabs(entry(t, f, row, kd)));
+                    }
+            std::vector<float> sc(nfp, 1.f);
+            for (int f = 0; f < nf; ++f)
+                if (smax[f] > 0.f) {
+                    int ex = 0;
+                    std::frexp(smax[f], &ex);
+                    sc[f] = std::ldexp(1.f, 14 - ex);
+                    us[f] = std::ldexp(1.f, ex - 14);
+                }
+            std::vector<_Float16> ah((size_t)nfp * 14 * 64 * 8, (_Float16)0.f);
+            std::vector<uint16_t> a1((size_t)nfp * 14 * 64 * 8, 0);
+            for (int ks = 0; ks < 14; ++ks)
+                for (int ln = 0; ln < 64; ++ln)
+                    for (int j = 0; j < 8; ++j) {
+                        const int row = ln & 15, k = 32 * ks + 8 * (ln >> 4) + j, q = k / 16;
+                        if (q >= 27) continue;
+                        const int kd = 16 * (q == 13 ? 26 : (q == 26 ? 13 : q)) + k % 16;
+                        const int t = offset_of(row, kd);
+                        if (t < 0) continue;
+                        for (int f = 0; f < nf; ++f) {
+                            const float v = (float)entry(t, f, row, kd) * sc[f];
+                            const size_t at = (((size_t)f * 14 + ks) * 64 + ln) * 8 + j;
+                            ah[at] = (_Float16)v;
+                            a1[at] = bf16_bits(v);
+                        }
+                    }
+            KIFMM_TRY(dmalloc(&o->fft_pair_h[l], ah.size() / 2));
+            KIFMM_TRY(dmalloc(&o->fft_pair_b1[l], a1.size() / 2));
+            KIFMM_TRY(dmalloc(&o->fft_pair_us[l], us.size()));
+            KIFMM_HIP(hipMemcpyAsync(o->fft_pair_h[l], ah.data(), ah.size() * sizeof(_Float16), hipMemcpyHostToDevice, st));
+            KIFMM_HIP(hipMemcpyAsync(o->fft_pair_b1[l], a1.data(), a1.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+            KIFMM_HIP(hipMemcpyAsync(o->fft_pair_us[l], us.data(), us.size() * sizeof(float), hipMemcpyHostToDevice, st));
             KIFMM_HIP(hipStreamSynchronize(st));
         }
         const Factor &u = fu[l - 2], &dn = fd[l - 2];
@@ -1350,6 +1406,13 @@ struct OpSet {
     const T *p2m, *m2m, *m2l, *l2l, *l2p, *p2p;
 };
 
+// Precisions whose M2L runs in the FFT form when it is on: FP32, the split-BF16 modes, and
+// the single-part M2L modes (their parent-pair products in FP16 or BF16)
+static bool fft_precision(int precision) {
+    return precision == KIFMM_FP32 || precision == KIFMM_BF16X3 || precision == KIFMM_M2L_BF16X3 ||
+           precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16;
+}
+
 // M2L of one level (eq. (m2l)) into cd[l], in the requested arithmetic
 template <typename T>
 int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, hipStream_t st) {
@@ -1369,7 +1432,7 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
         return run(p, st);
     }
     if constexpr (sizeof(T) == 4) {
-        if (o->m2l_fft && (precision == KIFMM_FP32 || precision == KIFMM_BF16X3)) {
+        if (o->m2l_fft && fft_precision(precision)) {
             // FFT form: equivalent densities on the lattice, their spectra, pointwise
             // products, check potentials on the lattice, coefficients
             const int64_t nbx = (int64_t)1 << (3 * l);
@@ -1383,8 +1446,13 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             pf.in_nz = nz_of(o, l);
             KIFMM_TRY(run(pf, st));
             KIFMM_TRY(run_m2l_lattice(0, o->opts.m0, lat, nbx, o->nfp, lr, nz_of(o, l), se, st));
-            if (o->fft_pair[l] && precision == KIFMM_BF16X3)
+            if (o->fft_pair[l] && (precision == KIFMM_BF16X3 || precision == KIFMM_M2L_BF16X3))
                 KIFMM_TRY(run_m2l_pair_bf16x3(se, o->fft_pair_bf[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
+            else if (o->fft_pair[l] && (precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16)) {
+                const bool h = precision == KIFMM_M2L_FP16;
+                KIFMM_TRY(run_m2l_pair_lp1(h ? 1 : 0, se, h ? o->fft_pair_h[l] : o->fft_pair_b1[l], o->fft_pair_us[l],
+                                           1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
+            }
             else if (o->fft_pair[l])
                 KIFMM_TRY(run_m2l_pair_mfma(se, o->fft_pair[l], 1 << l, o->nfp, want_of(o, l), nz_of(o, l), sp, st));
             else
@@ -1641,8 +1709,7 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // on its own stream beside the upward pass and the coarse levels (their latency-bound
     // small launches leave most of the chip to it), into cd[D]; the L2L into level D then
     // adds to it.  The coarse levels use spectra buffers of their own.
-    const bool fine_apart = sizeof(T) == 4 && D >= 3 && o->m2l_fft &&
-                            (precision == KIFMM_FP32 || precision == KIFMM_BF16X3);
+    const bool fine_apart = sizeof(T) == 4 && D >= 3 && o->m2l_fft && fft_precision(precision);
     if (fine_apart) {
         KIFMM_HIP(hipEventRecord(o->fork_fine, st));
         KIFMM_HIP(hipStreamWaitEvent(fine, o->fork_fine, 0));

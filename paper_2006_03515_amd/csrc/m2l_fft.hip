@@ -111,6 +111,24 @@ __global__ __launch_bounds__(512) void m2l_hadamard_kernel(const float2 *__restr
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int PF = 4;   // frequencies per workgroup of the MFMA kernel (one per wave)
 
+// Workgroup -> (block of 4^3 parents, frequency group).  Workgroups are dealt to the 8 XCDs
+// in turn; when the blocks divide by 8, XCD x takes the blocks x B/8 .. (x+1) B/8 - 1 (a
+// Morton-contiguous region) for one frequency group after another, so the halos that
+// neighbouring blocks share are read from that XCD's L2 instead of once per block.
+__device__ __forceinline__ void pair_tile(int64_t &pt, int &fg) {
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) {
+        const int64_t i = blockIdx.x + (int64_t)nb * blockIdx.y;
+        const int per = nb >> 3;
+        const int64_t j = i >> 3;
+        pt = (int64_t)(i & 7) * per + j % per;
+        fg = (int)(j / per);
+    } else {
+        pt = blockIdx.x;
+        fg = blockIdx.y;
+    }
+}
+
 // Am[f][d][lane][s]: lane l of k-step ks = 4 d + s holds entry (row l % 16, k = 4 ks + l / 16)
 // of the 16 x 432 real matrix of frequency f; row = 2 c_t + (re/im), k = 16 d + 2 c_s + (re/im).
 __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__restrict__ E, const float *__restrict__ Am,
@@ -121,8 +139,10 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     __shared__ int any_wanted;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int np = nl / 2;
-    const int64_t pt = blockIdx.x;        // 64 parents 64 pt .. 64 pt + 63, boxes 512 pt ..
-    const int f0 = blockIdx.y * PF;
+    int64_t pt;                           // 64 parents 64 pt .. 64 pt + 63, boxes 512 pt ..
+    int fg;
+    pair_tile(pt, fg);
+    const int f0 = fg * PF;
     if (out_need) {
         if (tid == 0) any_wanted = 0;
         __syncthreads();
@@ -130,31 +150,48 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
         __syncthreads();
         if (!any_wanted) return;
     }
+    // this wave's operator fragments (26 source parents x 4 k-steps) and the workgroup's share
+    // of the source region's spectra are requested together, before anything waits: one
+    // memory latency per workgroup instead of one per staging round and per source parent
+    const float4 *Af = (const float4 *)(Am + (int64_t)(f0 + w) * 108 * 64) + lane;
+    float4 a[26];
+#pragma unroll
+    for (int d = 0; d < 27; ++d)
+        if (d != 13) a[d - (d > 13)] = Af[d * 64];
     int ox, oy, oz;
     morton_decode((uint32_t)pt, ox, oy, oz);
     ox = 4 * ox - 1;
     oy = 4 * oy - 1;
     oz = 4 * oz - 1;
-    for (int e = tid; e < 216 * 8; e += 256) {
-        const int q = e >> 3, c = e & 7;
+    constexpr int NST = (216 * 8 + 255) / 256;   // staging rounds: 216 parents x 8 children
+    float4 v[NST][2];
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
         const int x = ox + q / 36, y = oy + (q / 6) % 6, z = oz + q % 6;
-        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
-        if (x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
+        v[i][0] = v[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < 216 * 8 && x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
             const int64_t box = 8 * (int64_t)morton_encode(x, y, z) + c;
             if (!in_nz || in_nz[box]) {
                 const float4 *src = (const float4 *)(E + box * nfp + f0);
-                v0 = src[0];
-                v1 = src[1];
+                v[i][0] = src[0];
+                v[i][1] = src[1];
             }
         }
-        Es[((0 * 8 + c) * 2 + 0) * 216 + q] = v0.x;
-        Es[((0 * 8 + c) * 2 + 1) * 216 + q] = v0.y;
-        Es[((1 * 8 + c) * 2 + 0) * 216 + q] = v0.z;
-        Es[((1 * 8 + c) * 2 + 1) * 216 + q] = v0.w;
-        Es[((2 * 8 + c) * 2 + 0) * 216 + q] = v1.x;
-        Es[((2 * 8 + c) * 2 + 1) * 216 + q] = v1.y;
-        Es[((3 * 8 + c) * 2 + 0) * 216 + q] = v1.z;
-        Es[((3 * 8 + c) * 2 + 1) * 216 + q] = v1.w;
+    }
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
+        if (e < 216 * 8) {
+            Es[((0 * 8 + c) * 2 + 0) * 216 + q] = v[i][0].x;
+            Es[((0 * 8 + c) * 2 + 1) * 216 + q] = v[i][0].y;
+            Es[((1 * 8 + c) * 2 + 0) * 216 + q] = v[i][0].z;
+            Es[((1 * 8 + c) * 2 + 1) * 216 + q] = v[i][0].w;
+            Es[((2 * 8 + c) * 2 + 0) * 216 + q] = v[i][1].x;
+            Es[((2 * 8 + c) * 2 + 1) * 216 + q] = v[i][1].y;
+            Es[((3 * 8 + c) * 2 + 0) * 216 + q] = v[i][1].z;
+            Es[((3 * 8 + c) * 2 + 1) * 216 + q] = v[i][1].w;
+        }
     }
     __syncthreads();
     // lane: k slot g = lane / 16 of each MFMA, parent 16 nb + lane % 16 of column block nb
@@ -169,13 +206,13 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     floatx4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float4 *Af = (const float4 *)(Am + (int64_t)(f0 + w) * 108 * 64) + lane;
     const float *Ew = Es + w * 16 * 216 + g * 216;
+#pragma unroll
     for (int d = 0; d < 27; ++d) {   // source parent p + (dx, dy, dz), d = 9 (dx+1) + 3 (dy+1) + dz+1
         if (d == 13) continue;   // the target's own parent: all its children are adjacent (zeros)
         const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
-        const float4 a = Af[d * 64];   // k-steps 4 d .. 4 d + 3
-        const float a4[4] = {a.x, a.y, a.z, a.w};
+        const float4 ad = a[d - (d > 13)];   // k-steps 4 d .. 4 d + 3
+        const float a4[4] = {ad.x, ad.y, ad.z, ad.w};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {   // k-step 4 d + s: c_s = 2 s + g / 2, re/im = g % 2
             const float *eb = Ew + s * 4 * 216 + dq;
@@ -229,8 +266,10 @@ __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__re
     __shared__ int any_wanted;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int np = nl / 2;
-    const int64_t pt = blockIdx.x;
-    const int f0 = blockIdx.y * PF;
+    int64_t pt;
+    int fg;
+    pair_tile(pt, fg);
+    const int f0 = fg * PF;
     if (out_need) {
         if (tid == 0) any_wanted = 0;
         __syncthreads();
@@ -238,24 +277,42 @@ __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__re
         __syncthreads();
         if (!any_wanted) return;
     }
+    // operator fragments and the source region's spectra requested together (one memory
+    // latency per workgroup)
+    const uint4 *Af = (const uint4 *)(Ab + ((int64_t)(f0 + w) * 14 * 64 + lane) * 16);
+    uint4 ah[13], al[13];
+#pragma unroll
+    for (int ks = 0; ks < 13; ++ks) {
+        ah[ks] = Af[ks * 64 * 2];
+        al[ks] = Af[ks * 64 * 2 + 1];
+    }
     int ox, oy, oz;
     morton_decode((uint32_t)pt, ox, oy, oz);
     ox = 4 * ox - 1;
     oy = 4 * oy - 1;
     oz = 4 * oz - 1;
-    for (int e = tid; e < 216 * 8; e += 256) {
-        const int q = e >> 3, c = e & 7;
+    constexpr int NST = (216 * 8 + 255) / 256;
+    float4 v[NST][2];
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
         const int x = ox + q / 36, y = oy + (q / 6) % 6, z = oz + q % 6;
-        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
-        if (x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
+        v[i][0] = v[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < 216 * 8 && x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
             const int64_t box = 8 * (int64_t)morton_encode(x, y, z) + c;
             if (!in_nz || in_nz[box]) {
                 const float4 *src = (const float4 *)(E + box * nfp + f0);
-                v0 = src[0];
-                v1 = src[1];
+                v[i][0] = src[0];
+                v[i][1] = src[1];
             }
         }
-        const float vals[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};   // (f, re/im)
+    }
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
+        if (e >= 216 * 8) continue;
+        const float vals[8] = {v[i][0].x, v[i][0].y, v[i][0].z, v[i][0].w,
+                               v[i][1].x, v[i][1].y, v[i][1].z, v[i][1].w};   // (f, re/im)
 #pragma unroll
         for (int f = 0; f < PF; ++f) {
             uint16_t hr, lr, hi, li;
@@ -278,19 +335,17 @@ __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__re
     floatx4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const uint4 *Af = (const uint4 *)(Ab + ((int64_t)(f0 + w) * 14 * 64 + lane) * 16);
     const uint16_t *Ehw = Eh + w * 216 * 16 + 8 * (g & 1), *Elw = El + w * 216 * 16 + 8 * (g & 1);
-#pragma unroll 2
     // k order: position q = 2 ks + g / 2 holds source parent d = q with 13 and 26 swapped, so
     // the last k-step (d = 13, the target's own parent, whose children are all adjacent, and
     // the padding) is all zeros and is skipped
+#pragma unroll
     for (int ks = 0; ks < 13; ++ks) {
         const int q = 2 * ks + (g >> 1), d = q == 13 ? 26 : (q == 26 ? 13 : q);
         const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
-        const uint4 ah = Af[ks * 64 * 2], al = Af[ks * 64 * 2 + 1];
         bf16x8 a_hi, a_lo;
-        __builtin_memcpy(&a_hi, &ah, 16);
-        __builtin_memcpy(&a_lo, &al, 16);
+        __builtin_memcpy(&a_hi, &ah[ks], 16);
+        __builtin_memcpy(&a_lo, &al[ks], 16);
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
             const int q = qn[nb] + dq;
@@ -311,6 +366,145 @@ __global__ __launch_bounds__(256) void m2l_pair_bf16x3_kernel(const float2 *__re
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * g + v;
             Os[((n * 8 + (row >> 1)) * PF + w) * 2 + (row & 1)] = acc[nb][v];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 512 * 2; e += 256) {
+        const int bl = e >> 1, half = e & 1;
+        ((float4 *)(P + (512 * pt + bl) * nfp + f0))[half] = ((const float4 *)Os)[bl * 2 + half];
+    }
+}
+
+// The parent-pair products with single FP16 or BF16 operands (FP32 accumulation) on
+// v_mfma_f32_16x16x32_{f16,bf16}: the workgroup shape and k order of m2l_pair_bf16x3_kernel,
+// one part instead of three.  Operands are scaled by powers of two so that FP16's range holds
+// them (and the scaling is exact): each frequency's operator fragments were scaled at the
+// precompute (so that its largest entry lies in [2^13, 2^14); `unscale` holds the inverse
+// factors), and each workgroup scales the spectra it stages by 2^(14 - e), e the exponent of
+// their largest magnitude.  The products are multiplied back in FP32.
+template <typename LT>
+__device__ __forceinline__ floatx4 mfma_lp32(const LT *a, const LT *b, floatx4 c);
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <>
+__device__ __forceinline__ floatx4 mfma_lp32<_Float16>(const _Float16 *a, const _Float16 *b, floatx4 c) {
+    f16x8 x, y;
+    __builtin_memcpy(&x, a, 16);
+    __builtin_memcpy(&y, b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx4 mfma_lp32<__bf16>(const __bf16 *a, const __bf16 *b, floatx4 c) {
+    bf16x8 x, y;
+    __builtin_memcpy(&x, a, 16);
+    __builtin_memcpy(&y, b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
+template <typename LT>
+__global__ __launch_bounds__(256) void m2l_pair_lp1_kernel(const float2 *__restrict__ E, const LT *__restrict__ Al,
+                                                           const float *__restrict__ unscale, int nl, int nfp,
+                                                           const uint8_t *__restrict__ out_need,
+                                                           const uint8_t *__restrict__ in_nz,
+                                                           float2 *__restrict__ P) {
+    __shared__ __align__(16) LT Eh[PF * 216 * 16];   // [f][region parent][c_s][re/im], reused for the output
+    __shared__ float wmax[4];
+    __shared__ int any_wanted;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int np = nl / 2;
+    int64_t pt;
+    int fg;
+    pair_tile(pt, fg);
+    const int f0 = fg * PF;
+    if (out_need) {
+        if (tid == 0) any_wanted = 0;
+        __syncthreads();
+        if (out_need[512 * pt + tid] || out_need[512 * pt + 256 + tid]) any_wanted = 1;
+        __syncthreads();
+        if (!any_wanted) return;
+    }
+    const uint4 *Af = (const uint4 *)(Al + ((int64_t)(f0 + w) * 14 * 64 + lane) * 8);
+    uint4 a[13];
+#pragma unroll
+    for (int ks = 0; ks < 13; ++ks) a[ks] = Af[ks * 64];
+    int ox, oy, oz;
+    morton_decode((uint32_t)pt, ox, oy, oz);
+    ox = 4 * ox - 1;
+    oy = 4 * oy - 1;
+    oz = 4 * oz - 1;
+    constexpr int NST = (216 * 8 + 255) / 256;
+    float4 v[NST][2];
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
+        const int x = ox + q / 36, y = oy + (q / 6) % 6, z = oz + q % 6;
+        v[i][0] = v[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < 216 * 8 && x >= 0 && y >= 0 && z >= 0 && x < np && y < np && z < np) {
+            const int64_t box = 8 * (int64_t)morton_encode(x, y, z) + c;
+            if (!in_nz || in_nz[box]) {
+                const float4 *src = (const float4 *)(E + box * nfp + f0);
+                v[i][0] = src[0];
+                v[i][1] = src[1];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NST; ++i)
+        m = fmaxf(m, fmaxf(fmaxf(fmaxf(fabsf(v[i][0].x), fabsf(v[i][0].y)), fmaxf(fabsf(v[i][0].z), fabsf(v[i][0].w))),
+                           fmaxf(fmaxf(fabsf(v[i][1].x), fabsf(v[i][1].y)), fmaxf(fabsf(v[i][1].z), fabsf(v[i][1].w)))));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) wmax[w] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    int ex = 0;
+    if (m > 0.f) frexpf(m, &ex);   // m < 2^ex
+    const int sh = min(14 - ex, 126);
+    const float scale = ldexpf(1.f, sh), back = ldexpf(1.f, -sh);
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = tid + 256 * i, q = e >> 3, c = e & 7;
+        if (e >= 216 * 8) continue;
+        const float vals[8] = {v[i][0].x, v[i][0].y, v[i][0].z, v[i][0].w,
+                               v[i][1].x, v[i][1].y, v[i][1].z, v[i][1].w};   // (f, re/im)
+#pragma unroll
+        for (int f = 0; f < PF; ++f) {
+            LT pr[2] = {(LT)(vals[2 * f] * scale), (LT)(vals[2 * f + 1] * scale)};
+            __builtin_memcpy(&Eh[(f * 216 + q) * 16 + 2 * c], pr, 2 * sizeof(LT));
+        }
+    }
+    __syncthreads();
+    const int g = lane >> 4;
+    int qn[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        int x, y, z;
+        morton_decode((uint32_t)(16 * nb + (lane & 15)), x, y, z);
+        qn[nb] = ((x + 1) * 6 + (y + 1)) * 6 + (z + 1);
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const LT *Ehw = Eh + w * 216 * 16 + 8 * (g & 1);
+#pragma unroll
+    for (int ks = 0; ks < 13; ++ks) {   // source parents in the k order of the split-BF16 kernel
+        const int q = 2 * ks + (g >> 1), d = q == 13 ? 26 : (q == 26 ? 13 : q);
+        const int dq = ((d / 9 - 1) * 6 + ((d / 3) % 3 - 1)) * 6 + (d % 3 - 1);
+        LT av[8];
+        __builtin_memcpy(av, &a[ks], 16);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_lp32<LT>(av, Ehw + (qn[nb] + dq) * 16, acc[nb]);
+    }
+    const float u = unscale[f0 + w] * back;
+    __syncthreads();
+    float *Os = (float *)Eh;   // [parent][c_t][f][re/im]: 512 boxes x PF frequencies (16 KB)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int n = 16 * nb + (lane & 15);
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const int row = 4 * g + vv;
+            Os[((n * 8 + (row >> 1)) * PF + w) * 2 + (row & 1)] = acc[nb][vv] * u;
         }
     }
     __syncthreads();
@@ -563,6 +757,23 @@ int run_m2l_pair_bf16x3(const float *E, const float *Ab, int nl, int nfp, const 
     const int64_t ntile = (int64_t)nl * nl * nl / 512;
     hipLaunchKernelGGL(m2l_pair_bf16x3_kernel, dim3((unsigned)ntile, (unsigned)(nfp / PF)), dim3(256), 0, st,
                        (const float2 *)E, (const uint16_t *)Ab, nl, nfp, out_need, in_nz, (float2 *)P);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int run_m2l_pair_lp1(int fp16, const float *E, const void *Al, const float *unscale, int nl, int nfp,
+                     const uint8_t *out_need, const uint8_t *in_nz, float *P, hipStream_t st) {
+    if (nl < 8 || (nl & (nl - 1)) != 0) return fail(KIFMM_EINVAL, "M2L spectra: boxes per axis must be 8, 16, ...");
+    if (nfp % PF != 0) return fail(KIFMM_EINVAL, "M2L spectra: frequency count not a multiple of 4");
+    if (!Al || !unscale) return fail(KIFMM_EINVAL, "M2L spectra: no single-part operator fragments");
+    const int64_t ntile = (int64_t)nl * nl * nl / 512;
+    const dim3 grid((unsigned)ntile, (unsigned)(nfp / PF));
+    if (fp16)
+        hipLaunchKernelGGL(m2l_pair_lp1_kernel<_Float16>, grid, dim3(256), 0, st, (const float2 *)E,
+                           (const _Float16 *)Al, unscale, nl, nfp, out_need, in_nz, (float2 *)P);
+    else
+        hipLaunchKernelGGL(m2l_pair_lp1_kernel<__bf16>, grid, dim3(256), 0, st, (const float2 *)E, (const __bf16 *)Al,
+                           unscale, nl, nfp, out_need, in_nz, (float2 *)P);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }

@@ -297,6 +297,11 @@ __global__ void scale_kernel(int64_t n, float *__restrict__ x, float s) {
         x[e] *= s;
 }
 
+__global__ void add_kernel(int64_t n, const float *__restrict__ x, float *__restrict__ y) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] += x[e];
+}
+
 // out[0] = ||S[tgt] - R[tgt]|| / ||R[tgt]|| (two FP32 fields compared at the targets)
 __global__ void sampled_diff_kernel(int64_t nt, const float *__restrict__ S, const float *__restrict__ R,
                                     const int64_t *__restrict__ tgt, double *__restrict__ out) {
@@ -632,6 +637,14 @@ int kifmm_nn_scale(int64_t n, float *x, float s, void *stream) {
     if (n < 0 || (n > 0 && !x)) return fail(KIFMM_EINVAL, "bad argument");
     if (n == 0) return KIFMM_OK;
     hipLaunchKernelGGL(scale_kernel, dim3(blocks(n)), dim3(kT), 0, (hipStream_t)stream, n, x, s);
+    KIFMM_HIP(hipGetLastError());
+    return KIFMM_OK;
+}
+
+int kifmm_nn_add(int64_t n, const float *x, float *y, void *stream) {
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(KIFMM_EINVAL, "bad argument");
+    if (n == 0) return KIFMM_OK;
+    hipLaunchKernelGGL(add_kernel, dim3(blocks(n)), dim3(kT), 0, (hipStream_t)stream, n, x, y);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }

@@ -105,6 +105,7 @@ def load_library(path=LIB_PATH):
         "kifmm_nn_sampled_rel_err": [I64, P, P, P, F64, P, P],
         "kifmm_nn_sampled_rel_diff": [I64, P, P, P, P, P],
         "kifmm_nn_scale": [I64, P, F32, P],
+        "kifmm_nn_add": [I64, P, P, P],
         "kifmm_nn_max_abs_noalloc": [I32, I64, P, P, I32, P],
     }
     for f, a in nn.items():

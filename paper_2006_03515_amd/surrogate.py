@@ -191,7 +191,7 @@ class Surrogate:
             if skip is not None:
                 gs = B["g_" + skip]
                 if have.get(skip):
-                    gs.add_(gy)
+                    K.nn_call("kifmm_nn_add", gy.numel(), gy, gs)
                 else:
                     gs.copy_(gy)
                     have[skip] = True
