@@ -159,8 +159,10 @@ class Case:
         return ms, med, prof
 
     def timed_graph(self, precision, steps, warmup):
-        # one evaluation captured in a HIP graph (its side streams join the capture through
-        # the library's fork/join events), then replayed
+        """One evaluation captured in a HIP graph (its side streams join the capture through
+        the library's fork/join events), then replayed: (mean ms over `steps` back-to-back
+        replays, median of `steps` single-replay event timings).  Every replay runs every
+        kernel of the evaluation on the current contents of I (tests/test_gpu_graph.py)."""
         import torch
         side = torch.cuda.Stream()
         side.wait_stream(self.stream)
@@ -181,8 +183,23 @@ class Case:
             g.replay()
         e1.record(self.stream)
         torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(self.stream)
+        for i in range(steps):
+            g.replay()
+            ev[i + 1].record(self.stream)
+        torch.cuda.synchronize()
+        med = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
         del g
-        return e0.elapsed_time(e1) / steps
+        return ms, med
+
+    def timed_launch(self, precision, steps, warmup, launch):
+        """(mean ms, median ms) of the evaluation issued as `launch`: 'graph' or 'eager'."""
+        if launch == "graph":
+            return self.timed_graph(precision, steps, warmup)
+        ms, med, _ = self.timed(precision, steps, warmup)
+        return ms, med
 
 
 def result(N, ms, err, **extra):
@@ -279,11 +296,15 @@ def main():
     ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "serial"],
                     help="serial: every pass of the headline on the calling stream (per-kernel profiles "
                          "without overlap; the headline value is then the serial step)")
-    ap.add_argument("--variants", default="fp32/graph,bf16x3/graph,bf16x3,fp16,bf16,m2l_bf16x3,m2l_fp16,m2l_bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense",
+    ap.add_argument("--launch", default="graph", choices=["graph", "eager"],
+                    help="how the timed evaluations are issued: replays of one evaluation captured in a "
+                         "HIP graph (the launches of all three streams recorded once), or one kifmm_eval "
+                         "call per step")
+    ap.add_argument("--variants", default="fp32/eager,bf16x3,bf16x3/eager,m2l_fp16,m2l_bf16,fp16,bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "
                          "'<precision>/dense' or '/fft' also sets the M2L form (lattice layout), "
-                         "'/near_fft' or '/near_dense' the near-field form, '/graph' times replays "
-                         "of one evaluation captured in a HIP graph")
+                         "'/near_fft' or '/near_dense' the near-field form, '/graph' or '/eager' the "
+                         "launch (default: that of the headline)")
     ap.add_argument("--check-targets", type=int, default=4096)
     ap.add_argument("--cpu-targets", type=int, default=2048,
                     help="targets of the oracle CPU baseline's direct-sum sample (0 = skip the CPU baseline)")
@@ -322,9 +343,10 @@ def main():
 
     # headline precision: timed without instrumentation, then once with per-pass events on
     # the launch streams, then once with every pass on the calling stream (no overlap)
-    log("timing %s: %d warmup + %d steps" % (args.precision, args.warmup, args.steps))
-    ms, med, _ = case.timed(args.precision, args.steps, args.warmup)
-    err = case.accuracy()
+    log("timing %s (%s): %d warmup + %d steps" % (args.precision, args.launch, args.warmup, args.steps))
+    ms, med = case.timed_launch(args.precision, args.steps, args.warmup, args.launch)
+    err = case.accuracy()   # the field the timed launches wrote
+    ms_eager, med_eager, _ = case.timed(args.precision, args.steps, args.warmup)
     _, _, prof = case.timed(args.precision, args.steps, 1, profile=True)
     ops.serial(True)
     ms_serial, _, prof_serial = case.timed(args.precision, args.steps, 1, profile=True)
@@ -411,7 +433,7 @@ def main():
     pressures = {str(int(args.p)): result(N, ms, err, ms_median=round(med, 4), precompute_s=round(case.t_pre, 3))}
     for p in [float(x) for x in args.pressures.split(",") if x]:
         c = channel_case(p)
-        pms, pmed, _ = c.timed(args.precision, args.steps, args.warmup)
+        pms, pmed = c.timed_launch(args.precision, args.steps, args.warmup, args.launch)
         pressures[str(int(p))] = result(N, pms, c.accuracy(), ms_median=round(pmed, 4), precompute_s=round(c.t_pre, 3))
         log("%g Torr: %.3f ms/step, rel-L2 %.3e" % (p, pms, pressures[str(int(p))]["rel_l2"]))
         del c
@@ -423,7 +445,7 @@ def main():
             for name, lay, m0, rc in (("fast", "lattice", args.m0, args.rcond), ("surface_order_8", "nested", 8, 1e-7)):
                 log("128^3 two heads at %g Torr, %s" % (p, name))
                 c = Case(args, K, workloads, w2, lay, m0, rc, args.lattice_radius, "fft", "fft", 4096, 1008)
-                cms, cmed, _ = c.timed(args.precision, args.steps, args.warmup)
+                cms, cmed = c.timed_launch(args.precision, args.steps, args.warmup, args.launch)
                 config_128["%s/%d" % (name, p)] = result(
                     c.N, cms, c.accuracy(), ms_median=round(cmed, 4),
                     layout="%s m0=%d rcond=%g" % (lay, m0, rc), precompute_s=round(c.t_pre, 3))
@@ -476,11 +498,9 @@ def main():
                 ops.m2l_fft(form == "fft")
             if form in ("near_fft", "near_dense"):
                 ops.p2p_fft(form == "near_fft")
-        if "graph" in forms:
-            vms = case.timed_graph(prec, args.steps, args.warmup)
-        else:
-            vms, _, _ = case.timed(prec, args.steps, args.warmup)
-        variants[v] = result(N, vms, case.accuracy(), speedup_vs_headline=round(ms / vms, 3))
+        launch = "graph" if "graph" in forms else ("eager" if "eager" in forms else args.launch)
+        vms, _ = case.timed_launch(prec, args.steps, args.warmup, launch)
+        variants[v] = result(N, vms, case.accuracy(), launch=launch, speedup_vs_headline=round(ms / vms, 3))
         if args.layout == "lattice":
             ops.m2l_fft(case.m2l == "fft")
         ops.p2p_fft(case.p2p == "fft")
@@ -528,6 +548,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
         "ms_per_step_median": round(med, 4),
+        "ms_per_step_eager": round(ms_eager, 4),
+        "ms_per_step_eager_median": round(med_eager, 4),
         "ms_per_step_serial": round(ms_serial, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -539,7 +561,7 @@ def main():
                    "rcond": args.rcond, "max_leaf": args.max_leaf, "leaf_side": tree.leaf_side,
                    "depth": tree.depth, "precision": args.precision, "m2l": case.m2l, "p2p": case.p2p,
                    "lattice_radius": (args.lattice_radius or 1.2) if args.layout == "lattice" else None,
-                   "schedule": args.schedule, "parallelism": "none"},
+                   "schedule": args.schedule, "launch": args.launch, "parallelism": "none"},
         "rel_l2_sampled": err,
         "accuracy_ok": err <= BAR,
         "pair_interactions_per_s_dense_equivalent": near_pairs(nb, s) / (ms * 1e-3),

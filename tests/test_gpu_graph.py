@@ -56,6 +56,12 @@ def test_graph_replay_is_the_eager_evaluation(K, n, prec, m2l_fft, near_fft):
         torch.cuda.synchronize()
     exact = odirect.fft_full(I.astype(np.float64), (L / n,) * 3, p_o2).ravel()
     assert rel_l2(S.double().cpu().numpy(), exact) < 1e-4
+    # a replay reads the input buffer as it is at replay time: new contents, new field
+    ref_other = K.eval(tree, ops, other, 1.0, precision=prec)
+    It.copy_(other)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(S, ref_other)
     del g
 
 
