@@ -56,7 +56,7 @@ int run_m2l_pair_lp1(int, const float *, const void *, const float *, int, int, 
                      hipStream_t);
 int run_m2l_lattice(int, int, const float *, int64_t, int, int, const uint8_t *, float *, hipStream_t);
 int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, const uint8_t *, float *, float *,
-                       float *, hipStream_t);
+                       float *, hipStream_t, const float *, float);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
 int launch_pack_fragments(const float *, int, int, int, float4 *, hipStream_t);
@@ -1540,8 +1540,11 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
 }
 
 // near field (eq. (nearfar), direct part, with the self cell) of every leaf into out
+// I_grid (FP32, Fourier form only): the sources read from the grid-order input times vol
+// instead of q
 template <typename T>
-int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision, hipStream_t st) {
+int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision, hipStream_t st,
+             const float *I_grid = nullptr, float vol = 1.f) {
     const int s = o->s, nb = o->nb;
     const int64_t nleaf = (int64_t)o->R * nb * nb * nb;
     if constexpr (sizeof(T) == 4) {
@@ -1549,7 +1552,7 @@ int p2p_pass(kifmm_ops o, const OpSet<T> &ops, const T *q, T *out, int precision
             for (int stage = 0; stage < 3; ++stage) {
                 PassTimer pt(o, stage == 1 ? KIFMM_PASS_NEAR_PRODUCTS : -1, st);
                 KIFMM_TRY(run_near_fft_stage(stage, (const float *)q, o->near_gh, nb, want_of(o, o->D), nz_of(o, o->D),
-                                             o->near_q, o->near_p, (float *)out, st));
+                                             o->near_q, o->near_p, (float *)out, st, I_grid, vol));
             }
             return KIFMM_OK;
         }
@@ -1666,9 +1669,28 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     const bool fused_in = sizeof(T) == 4 && D >= 2 && o->p2m_frag && !lowp && !o->skip_zero &&
                           (uintptr_t)I % 16 == 0;
     const bool fused_out = sizeof(T) == 4 && D >= 2 && o->l2p_frag && !lowp && (uintptr_t)S % 16 == 0;
+    // the side streams, or the calling stream itself when every pass is to run in order
+    // (kifmm_ops_serial: per-kernel timings without overlap)
+    hipStream_t side = o->serial ? st : o->side, fine = o->serial ? st : o->fine;
+    ForkJoin fj{o, st, side, fine};
+    // With the fused way in and the near field in Fourier space, the near field reads the
+    // grid-order input itself (no leaf-ordered copy of the sources is written): its stream is
+    // forked before P2M, which then runs beside the near field's first transform.
+    const bool near_grid = fused_in && o->p2p_fft && nb >= 4 && D >= lmin;
+    if (near_grid) {
+        KIFMM_HIP(hipEventRecord(o->fork, st));
+        KIFMM_HIP(hipStreamWaitEvent(side, o->fork, 0));
+        fj.side_forked = true;
+        {
+            PassTimer pt(o, KIFMM_PASS_P2P, side);
+            KIFMM_TRY(p2p_pass<T>(o, ops, nullptr, SpN, precision, side, (const float *)I, (float)vol));
+        }
+        KIFMM_HIP(hipEventRecord(o->join, side));
+    }
     if (fused_in) {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        KIFMM_TRY(run_p2m_permute_in(*t, (const float *)I, (float)vol, o->p2m_frag, KU, (float *)q, (float *)o->cu[D], st));
+        KIFMM_TRY(run_p2m_permute_in(*t, (const float *)I, (float)vol, o->p2m_frag, KU, near_grid ? nullptr : (float *)q,
+                                     (float *)o->cu[D], st));
     } else {
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, vol, q, st));
@@ -1682,21 +1704,19 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         PassTimer pt(o, KIFMM_PASS_PERMUTE_OUT, st);
         return launch_permute_out<T>(*t, Sp, scale, want_of(o, D), S, st);
     }
-    // the side streams, or the calling stream itself when every pass is to run in order
-    // (kifmm_ops_serial: per-kernel timings without overlap)
-    hipStream_t side = o->serial ? st : o->side, fine = o->serial ? st : o->fine;
     // near field on the side stream, forked as early as possible: whatever runs beside it
     // waits for its long workgroups (forking it later, after the upward pass or before the
     // finest M2L level, measured slower)
-    KIFMM_HIP(hipEventRecord(o->fork, st));
-    KIFMM_HIP(hipStreamWaitEvent(side, o->fork, 0));
-    ForkJoin fj{o, st, side, fine};
-    fj.side_forked = true;
-    {
-        PassTimer pt(o, KIFMM_PASS_P2P, side);
-        KIFMM_TRY(p2p_pass<T>(o, ops, q, SpN, precision, side));
+    if (!near_grid) {
+        KIFMM_HIP(hipEventRecord(o->fork, st));
+        KIFMM_HIP(hipStreamWaitEvent(side, o->fork, 0));
+        fj.side_forked = true;
+        {
+            PassTimer pt(o, KIFMM_PASS_P2P, side);
+            KIFMM_TRY(p2p_pass<T>(o, ops, q, SpN, precision, side));
+        }
+        KIFMM_HIP(hipEventRecord(o->join, side));
     }
-    KIFMM_HIP(hipEventRecord(o->join, side));
     // far field: upward pass, downward pass, local expansion at the cells
     if (!fused_in) {
         PassTimer pt(o, KIFMM_PASS_P2M, st);

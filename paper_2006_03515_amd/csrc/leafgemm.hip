@@ -94,9 +94,11 @@ __global__ __launch_bounds__(256, 2) void p2m_permute_in_kernel(const float *__r
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int m = block_code(ii >> 3, jj >> 3, c);
-            float4 *dq = (float4 *)(q + ((int64_t)((g << 5) + m) << 9) + local);
-            dq[0] = v[2 * c];
-            dq[1] = v[2 * c + 1];
+            if (q) {   // the leaf-ordered sources, when a later pass reads them
+                float4 *dq = (float4 *)(q + ((int64_t)((g << 5) + m) << 9) + local);
+                dq[0] = v[2 * c];
+                dq[1] = v[2 * c + 1];
+            }
             Qs[m * kQRow + (local >> 2)] = v[2 * c];
             Qs[m * kQRow + (local >> 2) + 1] = v[2 * c + 1];
         }
@@ -160,27 +162,6 @@ __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
     const float4 *bc = Cs + col * crow + h;
-    floatx16 acc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
-    const float4 *lf = Lf + (int64_t)(4 * wave) * nchunk * 64 + lane;
-    // the next chunk's operator fragments are loaded while one chunk is multiplied
-    float4 a[4], an[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = lf[(int64_t)i * nchunk * 64];
-    for (int c = 0; c < nchunk; ++c) {
-        if (c + 1 < nchunk) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) an[i] = lf[((int64_t)i * nchunk + c + 1) * 64];
-        }
-        const float4 b = bc[2 * c];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = mfma4(a[i], b, acc[i]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = an[i];
-    }
     // column col of the tiles is leaf 32 g + col
     const int leaf = (int)(g << 5) + col;
     int bx, by, bz, dx, dy, dz;
@@ -189,20 +170,48 @@ __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__
     const bool keep = !want || want[leaf];
     const float *sn = Snear + ((int64_t)leaf << 9);
     float *base = S + ((int64_t)((bx + dx) << 3) * n + ((by + dy) << 3)) * n + ((bz + dz) << 3);
+#pragma unroll 1
+    for (int pr = 0; pr < 2; ++pr) {
+        float4 sv[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int gg = 0; gg < 4; ++gg) {
-            // cells c .. c + 3 of the leaf (C order x, y, z inside it): one half z-line
-            const int c = 128 * wave + 32 * i + 8 * gg + 4 * h;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (keep) {
-                const float4 s = *(const float4 *)(sn + c);
-                v = make_float4((acc[i][4 * gg] + s.x) * scale, (acc[i][4 * gg + 1] + s.y) * scale,
-                                (acc[i][4 * gg + 2] + s.z) * scale, (acc[i][4 * gg + 3] + s.w) * scale);
+            for (int gg = 0; gg < 4; ++gg) {
+                const int c = 128 * wave + 32 * (2 * pr + i) + 8 * gg + 4 * h;
+                sv[i][gg] = keep ? *(const float4 *)(sn + c) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            *(float4 *)(base + ((int64_t)(c >> 6) * n + ((c >> 3) & 7)) * n + (c & 7)) = v;
+        floatx16 ac[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) ac[i][v] = 0.f;
+        const float4 *lf = Lf + (int64_t)(4 * wave + 2 * pr) * nchunk * 64 + lane;
+        float4 a[2], an[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = lf[(int64_t)i * nchunk * 64];
+        for (int c = 0; c < nchunk; ++c) {
+            if (c + 1 < nchunk) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) an[i] = lf[((int64_t)i * nchunk + c + 1) * 64];
+            }
+            const float4 b = bc[2 * c];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) ac[i] = mfma4(a[i], b, ac[i]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = an[i];
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg) {
+                const int c = 128 * wave + 32 * (2 * pr + i) + 8 * gg + 4 * h;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (keep)
+                    v = make_float4((ac[i][4 * gg] + sv[i][gg].x) * scale, (ac[i][4 * gg + 1] + sv[i][gg].y) * scale,
+                                    (ac[i][4 * gg + 2] + sv[i][gg].z) * scale, (ac[i][4 * gg + 3] + sv[i][gg].w) * scale);
+                *(float4 *)(base + ((int64_t)(c >> 6) * n + ((c >> 3) & 7)) * n + (c & 7)) = v;
+            }
+    }
 }
 
 }  // namespace
@@ -228,6 +237,7 @@ bool leafgemm_fits(const Tree &t, int KU, int KD) {
 int run_p2m_permute_in(const Tree &t, const float *I, float vol, const float4 *Af, int KU, float *q, float *cu,
                        hipStream_t st) {
     if ((uintptr_t)I % 16 || (uintptr_t)q % 16 || (uintptr_t)cu % 16) return fail(KIFMM_EINVAL, "fused P2M: misaligned buffer");
+    // q may be NULL: the leaf-ordered sources are then not written
     const int64_t nblk = (int64_t)t.nb * t.nb * t.nb / kLeafBlock;
     hipLaunchKernelGGL(p2m_permute_in_kernel, dim3((unsigned)nblk), dim3(256), 0, st, I, t.n, vol, Af, KU / 32, KU, q,
                        cu);

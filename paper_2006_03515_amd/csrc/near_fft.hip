@@ -62,16 +62,31 @@ constexpr int LPW = 4;   // leaves per workgroup of the transforms: one per wave
 // y: lane = (x, kz) forms ky = 0..14 (twiddles as immediates); x: 15 groups of 8 columns
 // (ky, kz), lane = (column, slot pair).  Each lane keeps its inputs in registers, so LDS
 // carries only the hand-offs.
+// GRID: the sources are read from the grid-order field I (n^3 cells, times vol) instead of
+// the leaf-ordered q = vol I, the same FP32 values: the near field then needs no way in.
+template <bool GRID>
 __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restrict__ q, const uint8_t *__restrict__ in_nz,
-                                                           int64_t nleaf, float2 *__restrict__ Q) {
+                                                           int64_t nleaf, float2 *__restrict__ Q, int n, float vol) {
     __shared__ float2 W[LPW][8 * NCOL];   // per wave: Z [kz][x][y], then Y [x][ky][kz]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t leaf = (int64_t)blockIdx.x * LPW + w;
     if (leaf >= nleaf || (in_nz && !in_nz[leaf])) return;   // never read: the products skip zero leaves
     float2 *Wb = W[w];
     {
-        const float4 *src = (const float4 *)(q + leaf * 512 + lane * 8);
-        const float4 a = src[0], b = src[1];
+        const float4 *src;
+        if constexpr (GRID) {   // the leaf's line (x, y) = (lane / 8, lane % 8): 8 cells along z
+            int lx, ly, lz;
+            morton_decode((uint32_t)leaf, lx, ly, lz);
+            src = (const float4 *)(q + ((int64_t)(8 * lx + (lane >> 3)) * n + 8 * ly + (lane & 7)) * n + 8 * lz);
+        } else {
+            src = (const float4 *)(q + leaf * 512 + lane * 8);
+        }
+        float4 a = src[0], b = src[1];
+        if constexpr (GRID) {   // rounded products, as stored in q (never contracted into the sums)
+#pragma clang fp contract(off)
+            a = make_float4(a.x * vol, a.y * vol, a.z * vol, a.w * vol);
+            b = make_float4(b.x * vol, b.y * vol, b.z * vol, b.w * vol);
+        }
         const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int kz = 0; kz < 8; ++kz) {
@@ -321,12 +336,16 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
 
 // stage 0: spectra of the sources, 1: products, 2: inverse transforms into S
 int run_near_fft_stage(int stage, const float *q, const float *Gh, int nb, const uint8_t *out_need,
-                       const uint8_t *in_nz, float *Qbuf, float *Pbuf, float *S, hipStream_t st) {
+                       const uint8_t *in_nz, float *Qbuf, float *Pbuf, float *S, hipStream_t st, const float *I_grid,
+                       float vol) {
     if (nb < 4 || (nb & (nb - 1)) != 0) return fail(KIFMM_EINVAL, "near-field spectra: leaves per axis must be 4, 8, 16, ...");
     const int64_t nleaf = (int64_t)nb * nb * nb;
-    if (stage == 0)
-        hipLaunchKernelGGL(near_forward_kernel, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st, q, in_nz,
-                           nleaf, (float2 *)Qbuf);
+    if (stage == 0 && I_grid)
+        hipLaunchKernelGGL(near_forward_kernel<true>, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st,
+                           I_grid, in_nz, nleaf, (float2 *)Qbuf, 8 * nb, vol);
+    else if (stage == 0)
+        hipLaunchKernelGGL(near_forward_kernel<false>, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st, q,
+                           in_nz, nleaf, (float2 *)Qbuf, 0, 1.f);
     else if (stage == 1)
         hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16 / NCH))), dim3(256), 0, st,
                            (const float2 *)Qbuf, (const float2 *)Gh, nb, out_need, in_nz, (float2 *)Pbuf);
