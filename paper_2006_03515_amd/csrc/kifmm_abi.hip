@@ -1779,7 +1779,10 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         if (coarse_side && l >= 3) KIFMM_HIP(hipEventRecord(o->ev_up[l], st));
     }
     if (coarse_side) {   // the events waited for below are all recorded (enqueued) above
-        for (int l = 3; l <= D - 1; ++l) {   // coarsest first: the L2L chain can start on it
+        // finest first: level D - 1 is the longest and its coefficients are ready first (the
+        // coarsest-first order, which lets the L2L chain start earlier, measured 20 us slower
+        // per step as a graph)
+        for (int l = D - 1; l >= 3; --l) {
             KIFMM_HIP(hipStreamWaitEvent(side, o->ev_up[l], 0));
             {
                 PassTimer pt(o, KIFMM_PASS_M2L, side);
