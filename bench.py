@@ -409,11 +409,14 @@ def main():
                     "flops_per_step": m2l_flops, "ms_per_step": round(pass_step_serial["m2l"], 4)}
 
     # leaf passes fused with the permutes (HBM-side algorithmic bytes: values read and written
-    # once; the operators come from L2): way in + P2M reads I and writes q and c_u; L2P + way
-    # out reads c_d and the near field and writes S
+    # once; the operators come from L2): way in + P2M reads I and writes c_u (and q, when the
+    # near field reads it); L2P + way out reads c_d and the near field and writes S
     esz = 8 if args.precision == "fp64" else 4
     KU, KD = ranks[tree.depth]
-    leaf_bytes = {"p2m": (2 * N + (N // s) * KU) * esz, "l2p": (2 * N + (N // s) * KD) * esz,
+    # (with the near field in Fourier space it reads the grid-order input itself and P2M writes
+    # no leaf-ordered copy of the sources)
+    p2m_q = 0 if case.p2p == "fft" else N
+    leaf_bytes = {"p2m": (N + p2m_q + (N // s) * KU) * esz, "l2p": (2 * N + (N // s) * KD) * esz,
                   "permute_in": 2 * N * esz, "permute_out": 3 * N * esz}
     leaf_flops = {"p2m": 2.0 * N * KU, "l2p": 2.0 * N * KD}
     leaf_passes = {}
