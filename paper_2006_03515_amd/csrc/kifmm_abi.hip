@@ -247,7 +247,6 @@ struct kifmm_ops_s {
     // 8^3 cells): [KU / 32 tiles][64 chunks][64 lanes] and [16 tiles][KD / 8 chunks][64 lanes]
     float4 *p2m_frag = nullptr, *l2p_frag = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
-    hipEvent_t l2l_fine = nullptr;   // the L2L into the finest level is done (its M2L then adds)
     // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
     std::vector<hipEvent_t> ev_up, ev_m2l;
     // per-pass timing (kifmm_profile_enable)
@@ -356,7 +355,6 @@ static void free_ops(kifmm_ops o) {
     if (o->join) (void)hipEventDestroy(o->join);
     if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
     if (o->join_fine) (void)hipEventDestroy(o->join_fine);
-    if (o->l2l_fine) (void)hipEventDestroy(o->l2l_fine);
     for (auto *v : {&o->ev_up, &o->ev_m2l})
         for (hipEvent_t e : *v)
             if (e) (void)hipEventDestroy(e);
@@ -1104,7 +1102,6 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
-    KIFMM_HIP(hipEventCreateWithFlags(&o->l2l_fine, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
     KIFMM_TRY(dmalloc(&o->amax_q, (size_t)o->n_amax));
     o->cu.assign(D + 1, nullptr);
@@ -1416,11 +1413,9 @@ static bool fft_precision(int precision) {
            precision == KIFMM_M2L_FP16 || precision == KIFMM_M2L_BF16;
 }
 
-// M2L of one level (eq. (m2l)) into cd[l], in the requested arithmetic.  In the FFT form the
-// launches can be issued in two parts: part 1 up to the lattice potentials, part 2 the map
-// to coefficients that writes (or, with acc, adds to) cd[l]; part 0 issues both.
+// M2L of one level (eq. (m2l)) into cd[l], in the requested arithmetic
 template <typename T>
-int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, hipStream_t st, int part = 0) {
+int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, hipStream_t st) {
     const int KU = o->KU, KD = o->KD;
     const int64_t nper = (int64_t)o->R << (3 * (l - 1));   // boxes per parity class
     const size_t per = (size_t)316 * KD * KU;
@@ -1446,7 +1441,6 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
             const size_t off = fine ? 0 : (((size_t)1 << (3 * l)) - 64) / 7;   // boxes of levels 2 .. l - 1
             float *lat = fine ? o->lat_buf : o->lat_buf_c + off * lr, *se = fine ? o->spec_e : o->spec_e_c + off * o->mf,
                   *sp = fine ? o->spec_p : o->spec_p_c + off * o->mf;
-            if (part != 2) {
             auto pf = tap<float, float>(o->lat_w[l], 0, lr, KU, (const float *)o->cu[l], KU, lat, lr, SRC_SAME, 0,
                                         o->t_single, 1, nbx, 0);
             pf.in_nz = nz_of(o, l);
@@ -1465,8 +1459,6 @@ int m2l_level(kifmm_ops o, const OpSet<T> &ops, int l, int precision, int acc, h
                 KIFMM_TRY(run_m2l_hadamard(se, o->fft_g[l], o->t_m2l.op_dev, o->t_m2l.off_dev, o->t_m2l.ntaps, 1 << l,
                                            o->nfp, want_of(o, l), nz_of(o, l), sp, st));
             KIFMM_TRY(run_m2l_lattice(1, o->opts.m0, sp, nbx, o->nfp, lr, want_of(o, l), lat, st));
-            }
-            if (part == 1) return KIFMM_OK;
             auto pi = tap<float, float>(o->lat_u[l], 0, KD, lr, (const float *)lat, lr, (float *)o->cd[l],
                                         KD, SRC_SAME, 0, o->t_single, 1, nbx, acc);
             pi.out_need = want_of(o, l);
@@ -1742,8 +1734,11 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         KIFMM_HIP(hipEventRecord(o->fork_fine, st));
         KIFMM_HIP(hipStreamWaitEvent(fine, o->fork_fine, 0));
         fj.fine_forked = true;
-        PassTimer pt(o, KIFMM_PASS_M2L, fine);
-        KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 0, fine, 1));   // up to the lattice potentials
+        {
+            PassTimer pt(o, KIFMM_PASS_M2L, fine);
+            KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 0, fine));
+        }
+        KIFMM_HIP(hipEventRecord(o->join_fine, fine));
     }
     // With the near field in Fourier space its stream is free early: the M2L of levels
     // D - 1 .. 3 then runs there, each as soon as M2M has made that level's coefficients,
@@ -1798,9 +1793,11 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         const bool m2l_done = (fine_apart && l == D) || (coarse_side && l >= 3);
         const int64_t npar = (int64_t)R << (3 * (l - 1));   // boxes of level l - 1 (l > lmin)
         if (l > lmin) {
-            // the finest level: the L2L writes cd[D] first, and the finest M2L's last map then
-            // adds to it on its own stream, so the L2L chain is off the step's tail
-            if (m2l_done && !(fine_apart && l == D)) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
+            // the finest level's M2L (own stream) and the coarse ones (near-field stream) have
+            // written cd[l]; the L2L adds to it.  (Issuing the finest L2L first and letting the
+            // finest M2L's last map add to it measured no faster as a graph, slower eagerly.)
+            if (fine_apart && l == D) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
+            else if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             if (lowp) {
                 const size_t so = (size_t)(l - lmin - 1) * 8 * KD * KD;
@@ -1816,21 +1813,10 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
             } else {
                 const T *A = ops.l2l + (size_t)(l - lmin - 1) * 8 * KD * KD;
                 auto p = tap<T, T>(A, (int64_t)KD * KD, KD, KD, (T *)o->cd[l - 1], KD, (T *)o->cd[l], KD, SRC_PARENT,
-                                   0, o->t_l2l, 8, npar, m2l_done && !(fine_apart && l == D) ? 1 : 0);
+                                   0, o->t_l2l, 8, npar, m2l_done ? 1 : 0);
                 p.out_need = want_of(o, l);
                 KIFMM_TRY(run(p, st));
             }
-        }
-        if (fine_apart && l == D) {
-            KIFMM_HIP(hipEventRecord(o->l2l_fine, st));
-            KIFMM_HIP(hipStreamWaitEvent(fine, o->l2l_fine, 0));
-            {
-                PassTimer pt(o, KIFMM_PASS_M2L, fine);
-                KIFMM_TRY(m2l_level<T>(o, ops, D, precision, 1, fine, 2));   // adds to the L2L's cd[D]
-            }
-            KIFMM_HIP(hipEventRecord(o->join_fine, fine));
-            KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
-            continue;
         }
         if (m2l_done) continue;
         PassTimer pt(o, KIFMM_PASS_M2L, st);
