@@ -69,7 +69,13 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
                                                            int64_t nleaf, float2 *__restrict__ Q, int n, float vol) {
     __shared__ float2 W[LPW][8 * NCOL];   // per wave: Z [kz][x][y], then Y [x][ky][kz]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t leaf = (int64_t)blockIdx.x * LPW + w;
+    int64_t leaf = (int64_t)blockIdx.x * LPW + w;
+    if constexpr (GRID) {   // the 4 waves take 4 leaves in a row along z: whole 128-byte lines of I
+        const int nb = n >> 3, q4 = nb >> 2;
+        const int64_t gq = blockIdx.x;
+        const int lx = (int)(gq / ((int64_t)nb * q4)), ly = (int)((gq / q4) % nb), lz = 4 * (int)(gq % q4) + w;
+        leaf = morton_encode(lx, ly, lz);
+    }
     if (leaf >= nleaf || (in_nz && !in_nz[leaf])) return;   // never read: the products skip zero leaves
     float2 *Wb = W[w];
     {
