@@ -70,3 +70,42 @@ def test_source_confined_to_one_leaf(setup):
     ref = odirect.fft_full(I1 + I2, (L / N,) * 3, P_O2)
     assert rel_l2(c, ref) < 1e-4
     assert rel_l2(a + b, c) < 1e-6
+
+
+def test_largest_grid_1024(record_property):
+    # the largest grid the tree takes (1024^3 cells, 2^30 points; leaves of 8^3, depth 7): the
+    # benchmark's channel at four times the resolution (3.9 um cells), against direct_eval
+    # (FP32 kernel values, FP64 sums; itself checked against the oracle) at 4,096 seeded
+    # cells.  The benchmark configuration (lattice layout R = 1.2, both Fourier forms) runs at
+    # the same throughput as at 256^3 and lands at 1.2e-4 here (its 125-point lattices cap the
+    # accuracy, and the channel's sampled cells weigh the dim background); the nested layout
+    # (m0 = 5, dense M2L, near field in Fourier space) holds 1e-4.
+    import time
+    from paper_2006_03515_amd import kifmm as K, workloads
+    n = 1024
+    w = workloads.streamer_channel(n=n, L=0.4, p=760.0)
+    tree = K.build_tree(K.Grid.cube(n, w.L), 512)
+    assert tree.depth == 7
+    I = torch.from_numpy(w.I.reshape(-1)).cuda()
+    del w.I
+    tg = torch.from_numpy(workloads.sample_targets(n ** 3, 4096, seed=1024)).cuda()
+    ref = K.direct_eval(K.Grid.cube(n, 0.4), K.Kernel(w.p_o2), I, w.prefactor, tg, fp64=False).cpu().numpy()
+    for name, opts, fft, bar in (("lattice_R1.2", K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.2), True, 2e-4),
+                                 ("nested_m0_5", K.Opts(K.LAYOUT_NESTED, 5, 10, 1e-5), False, 1e-4)):
+        ops = K.precompute_operators(tree, K.Kernel(w.p_o2), opts)
+        if fft:
+            ops.m2l_fft(True)
+        ops.p2p_fft(True)
+        S = K.eval(tree, ops, I, w.prefactor)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            K.eval(tree, ops, I, w.prefactor, out=S)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+        e = rel_l2(S[tg].double().cpu().numpy(), ref)
+        record_property(name, {"ms": ms, "rel_l2_sampled": e})
+        print("1024^3 %s: %.2f ms per evaluation, sampled rel-L2 %.3e" % (name, ms, e))
+        assert bool(torch.isfinite(S).all())
+        assert e < bar, (name, e)
+        del ops, S
