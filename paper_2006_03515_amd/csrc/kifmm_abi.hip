@@ -781,8 +781,9 @@ int build_near_spectra(DevBuf &db, kifmm_ops o, double h, hipStream_t st) {
 // around the box centre, G(x^d_i, y^u_j + 2 r o) = g_o(i - j) with g_o(d) = G(d t - 2 r o).
 // On the cyclic grid of N = 2 m0 - 1 points per axis the differences i - j never wrap onto
 // one another, so the M2L product is the inverse DFT of DFT(g_o) times DFT(density).  Per
-// level: the half spectra (frequencies (kx, ky, kz), kz < m0, index (kx N + ky) m0 + kz,
-// real and imaginary parts interleaved) of g_o for the 316 offsets, with the MFMA operator
+// level: the spectra of g_o for the 316 offsets at the stored frequencies of the lattice
+// transforms (kz = 1 .. m0 - 1 at (kx N + ky)(m0 - 1) + kz - 1, then one of each conjugate
+// pair of the plane kz = 0; real and imaginary parts interleaved), with the MFMA operator
 // fragments of the parent-pair form; the map from upward coefficients to the equivalent
 // density on the lattice, W_u; and the map from check potentials on the lattice to
 // downward coefficients, U_d^T.  The transforms between lattice values and spectra run
@@ -791,14 +792,30 @@ int build_fft_m2l(DevBuf &db, kifmm_ops o, double Lside, double h, const std::ve
                   const std::vector<Factor> &fu, const std::vector<Factor> &fd, hipStream_t st) {
     const int m = o->opts.m0, N = 2 * m - 1, D = o->D, KU = o->KU, KD = o->KD;
     const int n316 = (int)m2lo.size() / 3;
-    const int nf = N * N * m, nfp = pad_to(nf, 16), mf = 2 * nfp;
+    // stored frequencies: kz = 1 .. m - 1 in full, and one of each conjugate pair of the plane
+    // kz = 0 (the device transforms read the other as the conjugate of its mirror)
+    const int H = m - 1, B0 = N * N * H;
+    const int nf = B0 + m + H * N, nfp = pad_to(nf, 16), mf = 2 * nfp;
     const int nd = N * N * N, nlat = m * m * m;
     o->nfp = nfp;
     o->mf = mf;
     o->lrow = pad_to(nlat, 32);
     const double twopi_n = 2.0 * M_PI / N;
     auto phase = [&](int f, int x, int y, int z) {   // exact integer phase, reduced mod N
-        const int kx = f / (N * m), ky = (f / m) % N, kz = f % m;
+        int kx, ky, kz;
+        if (f < B0) {
+            kz = f % H + 1;
+            kx = f / H / N;
+            ky = f / H % N;
+        } else if (f < B0 + m) {
+            kx = 0;
+            ky = f - B0;
+            kz = 0;
+        } else {
+            kx = (f - B0 - m) / N + 1;
+            ky = (f - B0 - m) % N;
+            kz = 0;
+        }
         const int64_t ph = (int64_t)kx * x + (int64_t)ky * y + (int64_t)kz * z;
         return twopi_n * (double)(((ph % N) + N) % N);
     };

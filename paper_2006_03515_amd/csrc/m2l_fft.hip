@@ -5,10 +5,11 @@
 // G(x^d_i, y^u_j + 2 r o) = g_o(i - j), a block of a 3-D convolution.  On the cyclic grid
 // of N = 2 m0 - 1 points per axis the product becomes a pointwise product of spectra:
 //     P_t(f) = sum over the interaction list of t:  Gh_o(f) * E_s(f)
-// with E_s the half spectrum (N x N x (N+1)/2 complex values) of source box s's
-// equivalent density and Gh_o the spectrum of g_o.  Coefficients become lattice values
-// through the bases (tap GEMMs, W_u and U_d^T); this file holds the separable transforms
-// between lattice values and half spectra, and the sums of pointwise products.
+// with E_s the spectrum of source box s's equivalent density at (N^3 + 1)/2 frequencies (one
+// of each conjugate pair: the density is real) and Gh_o the spectrum of g_o.  Coefficients
+// become lattice values through the bases (tap GEMMs, W_u and U_d^T); this file holds the
+// separable transforms
+// between lattice values and spectra, and the sums of pointwise products.
 //
 // For one frequency the sum is a 189-tap stencil over the boxes, with no contraction of its
 // own.  Grouped by parents it becomes one: the 8 children c_t of a target parent p take
@@ -515,19 +516,46 @@ __global__ __launch_bounds__(256) void m2l_pair_lp1_kernel(const float2 *__restr
 }
 
 // Transforms between the lattice values of a box (m0^3 equivalent densities or check
-// potentials, C order (x, y, z), rows of m0^3 padded to 32 floats) and its half spectrum on
-// the cyclic N^3 grid, N = 2 m0 - 1: frequency (kx, ky, kz), kz < m0, at
-// f = (kx N + ky) m0 + kz.  Separable, one wave per box (four per workgroup): each lane
-// holds one line of a stage in registers and forms all its outputs, with the twiddles as
-// immediates (every loop over cells and frequencies is unrolled); LDS carries the two
-// hand-offs between stages.  The spectra rows hold nfp = f padded to 16 complex values, the
-// padding written as zeros.
+// potentials, C order (x, y, z), rows of m0^3 padded to 32 floats) and its spectrum on the
+// cyclic N^3 grid, N = 2 m0 - 1.  The lattice values are real, so X(-k) = conj X(k): only
+// the frequencies of one half are stored, and within the plane kz = 0 only one of each
+// conjugate pair (H = m0 - 1):
+//   kz = 1 .. H                      at f = (kx N + ky) H + kz - 1
+//   kz = 0, kx = 0, ky = 0 .. H      at f = N^2 H + ky
+//   kz = 0, kx = 1 .. H, any ky      at f = N^2 H + m0 + (kx - 1) N + ky
+// (the other half of the plane kz = 0 is read back as the conjugate of its mirror
+// (-kx, -ky)).  The pointwise products of real kernels and real densities have the same
+// symmetry, so they too are computed at these frequencies only.  Separable, one wave per
+// box (four per workgroup): each lane holds one line of a stage in registers and forms all
+// its outputs, with the twiddles as immediates (every loop over cells and frequencies is
+// unrolled); LDS carries the two hand-offs between stages.  The spectra rows hold the NF
+// stored frequencies padded to nfp (a multiple of 16) complex values, the padding written
+// as zeros.
 template <int M>
 struct LatticeDims {
-    static constexpr int N = 2 * M - 1, NF = N * N * M, NFP = (NF + 15) / 16 * 16, M3 = M * M * M;
-    static constexpr int NM = N * M;                  // columns (ky, kz) of the x stage
-    static constexpr int ROW = (M3 + 31) / 32 * 32;   // lattice row length
+    static constexpr int N = 2 * M - 1, H = M - 1, M3 = M * M * M;
+    static constexpr int B0 = N * N * H;                       // first frequency of the plane kz = 0
+    static constexpr int NF = B0 + M + H * N, NFP = (NF + 15) / 16 * 16;
+    static constexpr int NM = N * M;                           // columns (ky, kz) of the x stage
+    static constexpr int ROW = (M3 + 31) / 32 * 32;            // lattice row length
 };
+
+// Stored position of frequency (kx, ky, kz), and whether it is read as the conjugate of its
+// mirror (kz = 0 only)
+template <int M>
+__device__ __forceinline__ int lattice_freq(int kx, int ky, int kz, bool &conj) {
+    using L = LatticeDims<M>;
+    constexpr int N = L::N, H = L::H;
+    conj = false;
+    if (kz > 0) return (kx * N + ky) * H + kz - 1;
+    if (kx == 0) {
+        conj = ky > H;
+        return L::B0 + (conj ? N - ky : ky);
+    }
+    if (kx <= H) return L::B0 + M + (kx - 1) * N + ky;
+    conj = true;
+    return L::B0 + M + (N - kx - 1) * N + (N - ky) % N;
+}
 
 // cos and sin of 2 pi m / N, m < N, for the odd N = 2 m0 - 1 of m0 = 3 .. 8
 template <int N>
@@ -621,6 +649,7 @@ __global__ __launch_bounds__(256) void m2l_lattice_forward_kernel(const float *_
     lattice_wave_sync();
     float2 *dst = E + box * L::NFP;
     for (int c = lane; c < NM; c += 64) {   // x: lane = column (ky, kz), kx = 0..N-1
+        const int ky = c / M, kz = c % M;
         float2 v[M];
 #pragma unroll
         for (int x = 0; x < M; ++x) v[x] = Y[w][x * NM + c];
@@ -633,7 +662,9 @@ __global__ __launch_bounds__(256) void m2l_lattice_forward_kernel(const float *_
                 re = fmaf(v[x].x, cv, fmaf(v[x].y, sv, re));
                 im = fmaf(v[x].y, cv, fmaf(-v[x].x, sv, im));
             }
-            dst[kx * NM + c] = make_float2(re, im);
+            bool mirrored;
+            const int f = lattice_freq<M>(kx, ky, kz, mirrored);
+            if (!mirrored) dst[f] = make_float2(re, im);
         }
     }
     for (int f = L::NF + lane; f < L::NFP; f += 64) dst[f] = make_float2(0.f, 0.f);
@@ -661,9 +692,14 @@ __global__ __launch_bounds__(256) void m2l_lattice_inverse_kernel(const float2 *
     }
     const float2 *src = P + box * L::NFP;
     for (int c = lane; c < NM; c += 64) {   // x: lane = column (ky, kz), e^{+i theta}
+        const int ky = c / M, kz = c % M;
         float2 u[N];
 #pragma unroll
-        for (int kx = 0; kx < N; ++kx) u[kx] = src[kx * NM + c];
+        for (int kx = 0; kx < N; ++kx) {
+            bool mirrored;
+            u[kx] = src[lattice_freq<M>(kx, ky, kz, mirrored)];
+            if (mirrored) u[kx].y = -u[kx].y;
+        }
 #pragma unroll
         for (int x = 0; x < M; ++x) {
             float re = 0.f, im = 0.f;
@@ -732,8 +768,8 @@ int launch_lattice(int dir, const float *in, int64_t nbx, int nfp, int row, cons
 
 }  // namespace
 
-// dir 0: lattice values [nbx][row] -> half spectra [nbx][nfp] complex (boxes with
-// in_nz = 0 skipped); dir 1: half spectra -> lattice values (boxes with out_need = 0
+// dir 0: lattice values [nbx][row] -> spectra [nbx][nfp] complex at the stored frequencies
+// (boxes with in_nz = 0 skipped); dir 1: spectra -> lattice values (boxes with out_need = 0
 // written as zeros).  m0 in [3, 8], row = m0^3 padded to 32.
 int run_m2l_lattice(int dir, int m0, const float *in, int64_t nbx, int nfp, int row, const uint8_t *flags,
                     float *out, hipStream_t st) {
