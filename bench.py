@@ -380,10 +380,10 @@ def main():
     def near_roofline(pm, tag):
         if case.p2p == "fft" and pm.get("near_products", 0) > 0:
             # near field in Fourier space: the dominant kernel is the products kernel, one
-            # complex multiply-add (8 flops) per frequency of the half spectrum (15 x 15 x 8;
-            # the kernel's 16th slot per column, kept zero for alignment, is not counted) and
-            # existing leaf pair
-            prod_flops = 8.0 * 1800 * float(3 * nb - 2) ** 3
+            # complex multiply-add (8 flops) per multiplied frequency (113 columns (ky, kz) of
+            # 15 kx: the half spectrum less the mirrored half of the plane kz = 0; the 16th
+            # slot per column, kept zero for alignment, is not counted) and existing leaf pair
+            prod_flops = 8.0 * 113 * 15 * float(3 * nb - 2) ** 3
             t = pm["near_products"]
             a = prod_flops / (t * 1e-3) / 1e12
             return {"bound": "alu", "kernel": "near_products (near field in Fourier space)%s" % tag,

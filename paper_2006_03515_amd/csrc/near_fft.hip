@@ -13,18 +13,23 @@
 // products).
 //
 // Frequencies (kx, ky, kz), kz <= 7, are stored per leaf at f = (ky * 8 + kz) * 16 + kx:
-// 120 columns (ky, kz) of 16 slots, the last slot of each zero.
+// 120 columns (ky, kz) of 16 slots, the last slot of each zero.  The sources and the kernel
+// are real, so X(-k) = conj X(k): the columns (ky, 0) with ky = 8 .. 14 are the conjugates of
+// the columns (15 - ky, 0), slots reversed.  They are neither written by the forward
+// transform nor multiplied (113 columns are), and the inverse transform reads them back as
+// conjugates.
 //
 //   near_forward_kernel   one wave per source leaf: z, y and x transforms of the 8^3 values
 //                         zero-padded to 15^3, each lane holding a line in registers and
 //                         forming all its frequencies (twiddles as immediates); writes
-//                         1920 slots.
+//                         the 113 stored columns.
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
 //                         the block and the 27 kernel spectra are staged in LDS; lane = 16
 //                         frequencies x 16 columns of 4 targets along z (the 12 taps of a
 //                         column at one (ox, oy) read 6 source spectra).
-//                         A workgroup takes 8 chunks of 16 frequencies in turn, the next
+//                         A workgroup takes 8 or 7 chunks of 16 frequencies (15 per
+//                         block: 8 x 8 + 7 x 7 = 113 columns) in turn, the next
 //                         chunk's spectra in flight (registers) while one is multiplied;
 //                         XCD-contiguous order of the workgroups.
 //                         Each chunk ends with the first inverse stage (over kx, at the 8
@@ -43,6 +48,15 @@ __constant__ float kSin15[15] = {0.000000000f, 0.406736643f, 0.743144825f, 0.951
 
 constexpr int NCOL = 120;       // columns (ky, kz): 15 x 8
 constexpr int NF = NCOL * 16;   // frequency slots per leaf
+constexpr int NKEEP = 113;      // stored columns: all but (ky, 0) for ky = 8 .. 14
+
+// column of the j-th stored column: columns 0 .. 63 (ky < 8), then for ky = 8 .. 14 the
+// columns kz = 1 .. 7
+__device__ __forceinline__ int kept_column(int j) {
+    if (j < 64) return j;
+    const int t = j - 64;
+    return 64 + 8 * (t / 7) + 1 + t % 7;
+}
 
 // The same values as compile-time constants: with every loop over frequencies and cells
 // unrolled, each twiddle is an immediate operand.
@@ -158,12 +172,15 @@ __global__ __launch_bounds__(256) void near_forward_kernel(const float *__restri
             c = fmaf(v.y, cw[x], c);
             d = fmaf(v.x, sw[x], d);
         }
-        dst[r * 16] = make_float2(a + b, c - d);
-        dst[r * 16 + 15 - 2 * kp] = kp == 0 ? make_float2(0.f, 0.f) : make_float2(a - b, c + d);
+        if (g < 8 || (lane >> 3) != 0) {   // (ky, 0) with ky >= 8: the mirror of (15 - ky, 0)
+            dst[r * 16] = make_float2(a + b, c - d);
+            dst[r * 16 + 15 - 2 * kp] = kp == 0 ? make_float2(0.f, 0.f) : make_float2(a - b, c + d);
+        }
     }
 }
 
-constexpr int NCH = 8;   // frequency chunks per products workgroup
+constexpr int NCH = 8;    // frequency chunks per products workgroup (7 in the last 7 groups)
+constexpr int NGRP = 15;  // workgroups per block of target leaves: 8 x 8 + 7 x 7 = 113 chunks
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -178,11 +195,15 @@ __global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__r
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
     // source spectra run out of the same L2.
-    const int64_t nblk = (int64_t)nb * nb * nb / 64, total = nblk * (NF / 16 / NCH);
+    const int64_t nblk = (int64_t)nb * nb * nb / 64, total = nblk * NGRP;
     const int64_t wg = blockIdx.x;
     const int64_t lin = total % 8 == 0 ? (wg % 8) * (total / 8) + wg / 8 : wg;
     const int64_t blk = lin % nblk;
-    const int c0 = (int)(lin / nblk) * NCH;   // first of this workgroup's chunks of 16 frequencies
+    // this workgroup's chunks of 16 frequencies: stored columns j0 .. j1 - 1 (groups 0 .. 7
+    // take 8 columns, groups 8 .. 14 the 7 stored columns of ky = 8 .. 14).  The two kinds
+    // alternate in the order of the workgroups, so every XCD gets the same share of each.
+    const int k = (int)(lin / nblk), cg = (k & 1) ? 8 + (k >> 1) : k >> 1;
+    const int j0 = cg < 8 ? NCH * cg : 64 + 7 * (cg - 8), j1 = cg < 8 ? j0 + NCH : j0 + 7;
     if (out_need) {   // the same ballot in every wave: all return or none
         if (__ballot(out_need[64 * blk + lane] != 0) == 0) return;
     }
@@ -234,14 +255,15 @@ __global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__r
 #pragma unroll
     for (int s = 0; s < 4; ++s) tl[s] = (int)morton_encode(ta, tb, s);
     const int col = (((ta + 1) * 6 + (tb + 1)) * 6) * 16 + f;   // region (ta+1, tb+1, 0)
-    fetch(c0);
-    for (int c = c0; c < c0 + NCH; ++c) {
+    fetch(kept_column(j0));
+    for (int j = j0; j < j1; ++j) {
+        const int c = kept_column(j);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (tid + 256 * i < 216 * 8) ((float4 *)Es)[tid + 256 * i] = pre[i];
         if (gsrc) ((float4 *)Gs)[tid] = gpre;
         __syncthreads();
-        if (c + 1 < c0 + NCH) fetch(c + 1);   // in flight while this chunk is multiplied
+        if (j + 1 < j1) fetch(kept_column(j + 1));   // in flight while this chunk is multiplied
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int oxy = 0; oxy < 9; ++oxy) {   // (ox, oy); oz and the 4 targets share 6 sources
@@ -297,7 +319,11 @@ __global__ __launch_bounds__(256) void near_inverse_kernel(const float2 *__restr
         const int kz = lane >> 3, x = lane & 7;
         float2 u[15];
 #pragma unroll
-        for (int ky = 0; ky < 15; ++ky) u[ky] = U[leaf * NCOL * 8 + ky * 64 + lane];   // [ky * 8 + kz][x]
+        for (int ky = 0; ky < 15; ++ky) {   // [ky * 8 + kz][x]; (ky >= 8, 0): conj of (15 - ky, 0)
+            const bool mirrored = ky >= 8 && kz == 0;
+            u[ky] = U[leaf * NCOL * 8 + (mirrored ? 15 - ky : ky) * 64 + lane];
+            if (mirrored) u[ky].y = -u[ky].y;
+        }
         // ky and 15 - ky together: u(ky) e^{+i theta} + u(15 - ky) e^{-i theta}
         //   = (u(ky) + u(15 - ky)) cos theta + i (u(ky) - u(15 - ky)) sin theta
         float2 pk[8], mk[8];
@@ -353,7 +379,7 @@ int run_near_fft_stage(int stage, const float *q, const float *Gh, int nb, const
         hipLaunchKernelGGL(near_forward_kernel<false>, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st, q,
                            in_nz, nleaf, (float2 *)Qbuf, 0, 1.f);
     else if (stage == 1)
-        hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * (NF / 16 / NCH))), dim3(256), 0, st,
+        hipLaunchKernelGGL(near_products_kernel, dim3((unsigned)(nleaf / 64 * NGRP)), dim3(256), 0, st,
                            (const float2 *)Qbuf, (const float2 *)Gh, nb, out_need, in_nz, (float2 *)Pbuf);
     else
         hipLaunchKernelGGL(near_inverse_kernel, dim3((unsigned)((nleaf + LPW - 1) / LPW)), dim3(256), 0, st,
