@@ -693,12 +693,20 @@ __global__ __launch_bounds__(256) void m2l_lattice_inverse_kernel(const float2 *
     const float2 *src = P + box * L::NFP;
     for (int c = lane; c < NM; c += 64) {   // x: lane = column (ky, kz), e^{+i theta}
         const int ky = c / M, kz = c % M;
+        // stored positions of the column's frequencies (as lattice_freq, with kx a constant
+        // of the unrolled loop: one select per frequency, every load unconditional)
+        constexpr int H = L::H;
+        const int lin = ky * H + kz - 1;                              // kz > 0: + kx N H
+        const int p0 = L::B0 + (ky <= H ? ky : N - ky);               // kz = 0, kx = 0
+        const int qb = L::B0 + M - N + ky;                            // kz = 0, kx <= H: + kx N
+        const int rb = L::B0 + M + (N - 1) * N + (N - ky) % N;        // kz = 0, kx > H: - kx N
         float2 u[N];
 #pragma unroll
         for (int kx = 0; kx < N; ++kx) {
-            bool mirrored;
-            u[kx] = src[lattice_freq<M>(kx, ky, kz, mirrored)];
-            if (mirrored) u[kx].y = -u[kx].y;
+            const int f0 = kx == 0 ? p0 : (kx <= H ? qb + kx * N : rb - kx * N);
+            const bool cj = kz == 0 && (kx == 0 ? ky > H : kx > H);   // the conjugate of its mirror
+            const float2 v = src[kz > 0 ? lin + kx * N * H : f0];
+            u[kx] = make_float2(v.x, cj ? -v.y : v.y);
         }
 #pragma unroll
         for (int x = 0; x < M; ++x) {
