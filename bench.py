@@ -359,10 +359,11 @@ def main():
     nb, s = tree.grid.n[0] // tree.leaf_side, tree.leaf_side ** 3
     if case.m2l == "fft":
         # FFT form: coefficients -> lattice values and back (two GEMMs per box, m0^3 x rank),
-        # plus one complex multiply-add (8 flops) per interaction pair and frequency (the
+        # plus one complex multiply-add (8 flops) per interaction pair and stored frequency
+        # (one of each conjugate pair of the N^3 grid, N = 2 m0 - 1: (N^3 + 1) / 2; the
         # parent-pair products also multiply the zero entries of adjacent children, and the
         # separable transforms run on the VALU: neither counted)
-        nf = (2 * args.m0 - 1) ** 2 * args.m0
+        nf = ((2 * args.m0 - 1) ** 3 + 1) // 2
         m2l_flops = sum(2.0 * 8 ** l * args.m0 ** 3 * (ranks[l][0] + ranks[l][1]) + 8.0 * m2l_pairs(l) * nf
                         for l in ranks)
     else:
