@@ -177,13 +177,13 @@ int kifmm_tree_shape(kifmm_tree tree, int32_t *leaf_xy, int32_t *leaf_z, int32_t
  * float otherwise, in grid order; they must not overlap.  `ops` must come from
  * `tree` (else KIFMM_EMISMATCH).  Uses the work buffers owned by `ops`, so
  * calls sharing one ops object must be ordered on one stream.  The near field
- * (and, after it, the M2L of the coarse levels when both Fourier forms are on) runs
- * on a second stream, and the finest level's FFT-form M2L on a third; the library
- * creates these two once per device and shares them between all operator objects
- * (kept until the process ends), and both are forked from and joined back into
- * `stream` with events, so when the call returns, all its work is ordered on `stream`
- * (also when it returns an error).  Evaluations of different ops objects may be
- * issued on different streams; their side work then shares the two streams.  With
+ * (and, after it, the M2L of the coarse levels D-1 .. 4 when both Fourier forms are on)
+ * runs on a second stream, the finest level's FFT-form M2L on a third and level 3's on
+ * a fourth; the library creates these three once per device and shares them between all
+ * operator objects (kept until the process ends), and all are forked from and joined
+ * back into `stream` with events, so when the call returns, all its work is ordered on
+ * `stream` (also when it returns an error).  Evaluations of different ops objects may be
+ * issued on different streams; their side work then shares the three streams.  With
  * leaves of 8^3 cells and FP32 arithmetic, P2M runs fused with the permute of I into
  * leaf order and L2P fused with the sum of far and near field and the permute back
  * (16-byte aligned I_dev and S_dev; otherwise separate permutes and tap GEMMs). */

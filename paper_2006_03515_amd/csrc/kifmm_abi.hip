@@ -2,6 +2,7 @@
 // precompute orchestration and the evaluation schedule (Section 3, algorithm
 // outline: tree, upward pass, downward pass, target potential).
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -239,14 +240,15 @@ struct kifmm_ops_s {
     float *part = nullptr;             // tap-group partial sums of the M2L launches
     int64_t part_capacity = 0;         // floats
     // the near field runs on a second stream (then, with both Fourier forms, the coarse
-    // levels' M2L), joined by events; with the FFT form of M2L the finest level's M2L runs
-    // on a third, beside the upward pass and the coarse levels
-    hipStream_t side = nullptr, fine = nullptr;
+    // levels' M2L down to level 4), joined by events; with the FFT form of M2L the finest
+    // level's M2L runs on a third, beside the upward pass and the coarse levels, and level 3's
+    // M2L on a fourth
+    hipStream_t side = nullptr, fine = nullptr, coarse = nullptr;
     bool serial = false;             // kifmm_ops_serial: every pass on the calling stream, in order
     // P2M and L2P as MFMA fragments for the kernels fused with the permutes (FP32, leaves of
     // 8^3 cells): [KU / 32 tiles][64 chunks][64 lanes] and [16 tiles][KD / 8 chunks][64 lanes]
     float4 *p2m_frag = nullptr, *l2p_frag = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr, join_coarse = nullptr;
     // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
     std::vector<hipEvent_t> ev_up, ev_m2l;
     // per-pass timing (kifmm_profile_enable)
@@ -306,23 +308,25 @@ struct PassTimer {
     }
 };
 
-// The near-field and finest-level streams of the evaluations, one pair per device, shared
-// by every operator object and kept until the process ends.  HIP spreads streams over a few
-// hardware queues (4 by default); a pair per live object would put the passes of several
-// objects, and the calling stream, on shared queues and serialise what should overlap.
+// The near-field, finest-level and level-3 streams of the evaluations, one set per device,
+// shared by every operator object and kept until the process ends.  HIP spreads streams over
+// a few hardware queues (4 by default); a set per live object would put the passes of
+// several objects, and the calling stream, on shared queues and serialise what should
+// overlap.
 static std::mutex g_stream_mu;
-static std::vector<std::pair<hipStream_t, hipStream_t>> g_streams;
+static std::vector<std::array<hipStream_t, 3>> g_streams;
 
-static int shared_streams(hipStream_t *side, hipStream_t *fine) {
+static int shared_streams(hipStream_t *side, hipStream_t *fine, hipStream_t *coarse) {
     int dev = 0;
     KIFMM_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_stream_mu);
-    if (dev >= (int)g_streams.size()) g_streams.resize(dev + 1, {nullptr, nullptr});
+    if (dev >= (int)g_streams.size()) g_streams.resize(dev + 1, {nullptr, nullptr, nullptr});
     auto &p = g_streams[dev];
-    if (!p.first) KIFMM_HIP(hipStreamCreateWithFlags(&p.first, hipStreamNonBlocking));
-    if (!p.second) KIFMM_HIP(hipStreamCreateWithFlags(&p.second, hipStreamNonBlocking));
-    *side = p.first;
-    *fine = p.second;
+    for (hipStream_t &s : p)
+        if (!s) KIFMM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    *side = p[0];
+    *fine = p[1];
+    *coarse = p[2];
     return KIFMM_OK;
 }
 
@@ -331,6 +335,7 @@ static void free_ops(kifmm_ops o) {
     clear_profile(o);
     if (o->side) (void)hipStreamSynchronize(o->side);
     if (o->fine) (void)hipStreamSynchronize(o->fine);
+    if (o->coarse) (void)hipStreamSynchronize(o->coarse);
     void *ptrs[] = {o->p2m32, o->m2m32, o->m2l32, o->l2l32, o->l2p32, o->p2p32, o->p2m64,
                     o->m2m64, o->m2l64, o->l2l64, o->l2p64, o->p2p64, o->m2lbf, o->m2lbf_lo,
                     o->p2mbf, o->m2mbf, o->l2lbf, o->l2pbf, o->p2mh, o->m2mh, o->l2lh, o->l2ph,
@@ -355,6 +360,7 @@ static void free_ops(kifmm_ops o) {
     if (o->join) (void)hipEventDestroy(o->join);
     if (o->fork_fine) (void)hipEventDestroy(o->fork_fine);
     if (o->join_fine) (void)hipEventDestroy(o->join_fine);
+    if (o->join_coarse) (void)hipEventDestroy(o->join_coarse);
     for (auto *v : {&o->ev_up, &o->ev_m2l})
         for (hipEvent_t e : *v)
             if (e) (void)hipEventDestroy(e);
@@ -1114,11 +1120,12 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     KIFMM_TRY(dmalloc(&o->q, (size_t)tree->N));
     KIFMM_TRY(dmalloc(&o->Sp, (size_t)tree->N));
     KIFMM_TRY(dmalloc(&o->SpN, (size_t)tree->N));
-    KIFMM_TRY(shared_streams(&o->side, &o->fine));
+    KIFMM_TRY(shared_streams(&o->side, &o->fine, &o->coarse));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->fork_fine, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&o->join_fine, hipEventDisableTiming));
+    KIFMM_HIP(hipEventCreateWithFlags(&o->join_coarse, hipEventDisableTiming));
     KIFMM_TRY(dmalloc(&o->amax, (size_t)o->n_amax));
     KIFMM_TRY(dmalloc(&o->amax_q, (size_t)o->n_amax));
     o->cu.assign(D + 1, nullptr);
@@ -1645,8 +1652,8 @@ int mark_nonzero_sources(kifmm_ops o, const T *q, hipStream_t st) {
 // running on them, and a stream capture stays joined.
 struct ForkJoin {
     kifmm_ops o;
-    hipStream_t st, side, fine;
-    bool side_forked = false, fine_forked = false;
+    hipStream_t st, side, fine, coarse;
+    bool side_forked = false, fine_forked = false, coarse_forked = false;
     ~ForkJoin() {
         if (side_forked && side != st) {
             (void)hipEventRecord(o->join, side);
@@ -1655,6 +1662,10 @@ struct ForkJoin {
         if (fine_forked && fine != st) {
             (void)hipEventRecord(o->join_fine, fine);
             (void)hipStreamWaitEvent(st, o->join_fine, 0);
+        }
+        if (coarse_forked && coarse != st) {
+            (void)hipEventRecord(o->join_coarse, coarse);
+            (void)hipStreamWaitEvent(st, o->join_coarse, 0);
         }
     }
 };
@@ -1681,7 +1692,8 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     // the side streams, or the calling stream itself when every pass is to run in order
     // (kifmm_ops_serial: per-kernel timings without overlap)
     hipStream_t side = o->serial ? st : o->side, fine = o->serial ? st : o->fine;
-    ForkJoin fj{o, st, side, fine};
+    hipStream_t coarse = o->serial ? st : o->coarse;
+    ForkJoin fj{o, st, side, fine, coarse};
     // With the fused way in and the near field in Fourier space, the near field reads the
     // grid-order input itself (no leaf-ordered copy of the sources is written): its stream is
     // forked before P2M, which then runs beside the near field's first transform.
@@ -1758,9 +1770,10 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         KIFMM_HIP(hipEventRecord(o->join_fine, fine));
     }
     // With the near field in Fourier space its stream is free early: the M2L of levels
-    // D - 1 .. 3 then runs there, each as soon as M2M has made that level's coefficients,
-    // into cd[l]; the main stream does level 2 and the L2L chain, each L2L adding to the M2L
-    // sum (the coarse chain of small launches is otherwise the step's longest path).
+    // D - 1 .. 4 then runs there, each as soon as M2M has made that level's coefficients,
+    // into cd[l], and level 3's on a stream of its own; the main stream does level 2 and the
+    // L2L chain, each L2L adding to the M2L sum (the coarse chain of small launches is
+    // otherwise the step's longest path).
     const bool coarse_side = fine_apart && D >= 4 && o->p2p_fft && nb >= 4;
     for (int l = D - 1; l >= lmin; --l) {
         const int64_t nbl = (int64_t)R << (3 * l);   // boxes of level l
@@ -1793,14 +1806,19 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     if (coarse_side) {   // the events waited for below are all recorded (enqueued) above
         // finest first: level D - 1 is the longest and its coefficients are ready first (the
         // coarsest-first order, which lets the L2L chain start earlier, measured 20 us slower
-        // per step as a graph)
+        // per step as a graph).  Level 3 runs beside them on its own stream, as soon as its
+        // coefficients exist (behind level 4 on the near-field stream it ended the step's
+        // longest chain; level 4 on its own stream instead measured the same, every coarse
+        // level on one stream of its own or each on its own slower)
         for (int l = D - 1; l >= 3; --l) {
-            KIFMM_HIP(hipStreamWaitEvent(side, o->ev_up[l], 0));
+            hipStream_t ls = l == 3 ? coarse : side;
+            if (l == 3) fj.coarse_forked = true;
+            KIFMM_HIP(hipStreamWaitEvent(ls, o->ev_up[l], 0));
             {
-                PassTimer pt(o, KIFMM_PASS_M2L, side);
-                KIFMM_TRY(m2l_level<T>(o, ops, l, precision, 0, side));
+                PassTimer pt(o, KIFMM_PASS_M2L, ls);
+                KIFMM_TRY(m2l_level<T>(o, ops, l, precision, 0, ls));
             }
-            KIFMM_HIP(hipEventRecord(o->ev_m2l[l], side));
+            KIFMM_HIP(hipEventRecord(o->ev_m2l[l], ls));
         }
         KIFMM_HIP(hipEventRecord(o->join, side));
     }
@@ -1814,7 +1832,10 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
             // written cd[l]; the L2L adds to it.  (Issuing the finest L2L first and letting the
             // finest M2L's last map add to it measured no faster as a graph, slower eagerly.)
             if (fine_apart && l == D) KIFMM_HIP(hipStreamWaitEvent(st, o->join_fine, 0));
-            else if (m2l_done) KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
+            else if (m2l_done) {
+                KIFMM_HIP(hipStreamWaitEvent(st, o->ev_m2l[l], 0));
+                if (l == 3) fj.coarse_forked = false;   // level 3's stream joined
+            }
             PassTimer pt(o, KIFMM_PASS_L2L, st);
             if (lowp) {
                 const size_t so = (size_t)(l - lmin - 1) * 8 * KD * KD;
