@@ -60,7 +60,8 @@ int run_near_fft_stage(int, const float *, const float *, int, const uint8_t *, 
                        float *, hipStream_t, const float *, float);
 template <typename T>
 int launch_permute_out2(const Tree &, const T *, const T *, T, const uint8_t *, T *, hipStream_t);
-int launch_pack_fragments(const float *, int, int, int, float4 *, hipStream_t);
+int launch_pack_fragments(const float *, int, int, int, int, float4 *, hipStream_t);
+int l2p_fragment_chunks(int KD);
 bool leafgemm_fits(const Tree &, int, int);
 int run_p2m_permute_in(const Tree &, const float *, float, const float4 *, int, float *, float *, hipStream_t);
 int run_l2p_permute_out(const Tree &, const float *, int, const float4 *, const float *, float, const uint8_t *, float *,
@@ -1216,9 +1217,10 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
     // their MFMA fragments for the kernels fused with the permutes
     if (leafgemm_fits(*tree, KU, KD)) {
         KIFMM_TRY(dmalloc(&o->p2m_frag, (size_t)KU * s / 4));
-        KIFMM_TRY(dmalloc(&o->l2p_frag, (size_t)s * KD / 4));
-        KIFMM_TRY(launch_pack_fragments(o->p2m32, KU, s, s, o->p2m_frag, st));
-        KIFMM_TRY(launch_pack_fragments(o->l2p32, s, KD, KD, o->l2p_frag, st));
+        const int l2p_chunks = l2p_fragment_chunks(KD);   // KD / 8 rounded up to even
+        KIFMM_TRY(dmalloc(&o->l2p_frag, (size_t)(s / 32) * l2p_chunks * 64));
+        KIFMM_TRY(launch_pack_fragments(o->p2m32, KU, s, s, s / 8, o->p2m_frag, st));
+        KIFMM_TRY(launch_pack_fragments(o->l2p32, s, KD, KD, l2p_chunks, o->l2p_frag, st));
     }
     // child centre offsets at a level of half-widths (r, r, rz): (2c - 1) r per axis
     auto child_shifts = [&](double r, double rz) {

@@ -46,6 +46,9 @@ __device__ inline void block_leaf(int m, int &dx, int &dy, int &dz) {
     dx = (m >> 2) & 1;
 }
 
+// 8-wide reduction chunks of the L2P operator: KD / 8 rounded up to even
+__host__ __device__ inline int l2p_chunks(int KD) { return (KD / 8 + 1) & ~1; }
+
 __device__ inline floatx16 mfma4(const float4 &a, const float4 &b, floatx16 acc) {
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
@@ -144,20 +147,22 @@ __global__ __launch_bounds__(256, 2) void p2m_permute_in_kernel(const float *__r
 }
 
 // L2P + sum with the near field + way out.  Grid: one workgroup per block of 32 leaves.
-// KD % 8 == 0, KD <= 256; the operator has 512 rows (16 tiles), wave w takes the cells
-// 128 w .. 128 w + 127 of every leaf of the block (tiles 4w .. 4w + 3).
+// KD % 8 == 0, KD <= 256; the operator has 512 rows (16 tiles) and an even number of
+// 8-wide chunks (KD rounded up to 16, the padding zero in the fragments and in the staged
+// coefficients); wave w takes the cells 128 w .. 128 w + 127 of every leaf of the block
+// (tiles 4w .. 4w + 3).
 __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__restrict__ cd, int KD,
                                                                  const float4 *__restrict__ Lf,
                                                                  const float *__restrict__ Snear, int n, float scale,
                                                                  const uint8_t *__restrict__ want, float *__restrict__ S) {
     __shared__ float4 Cs[kLeafBlock * 65];
-    const int crow = KD / 4 + 1;
+    const int nchunk = l2p_chunks(KD), crow = 2 * nchunk + 1;
     const uint32_t g = blockIdx.x;
     const int tid = threadIdx.x;
-    const int nchunk = KD / 8;
-    for (int e = tid; e < kLeafBlock * (KD / 4); e += 256) {
-        const int m = e / (KD / 4), k4 = e % (KD / 4);
-        Cs[m * crow + k4] = ((const float4 *)(cd + (int64_t)((g << 5) + m) * KD))[k4];
+    for (int e = tid; e < kLeafBlock * 2 * nchunk; e += 256) {
+        const int m = e / (2 * nchunk), k4 = e % (2 * nchunk);
+        Cs[m * crow + k4] = 4 * k4 < KD ? ((const float4 *)(cd + (int64_t)((g << 5) + m) * KD))[k4]
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
@@ -170,6 +175,25 @@ __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__
     const bool keep = !want || want[leaf];
     const float *sn = Snear + ((int64_t)leaf << 9);
     float *base = S + ((int64_t)((bx + dx) << 3) * n + ((by + dy) << 3)) * n + ((bz + dz) << 3);
+    // The wave's operator fragments as one sequence of steps s = pr * nchunk + c (tiles
+    // 4 wave + 2 pr + i, chunk c), requested two steps ahead into two register sets: the last
+    // steps of the first pair request the second pair's first chunks, before the first pair's
+    // sums are stored.  Loads complete in the order they were issued, so a step waits only
+    // for its own fragments and what was issued before them, never for the stores or the
+    // near-field loads that follow; the step index is clamped, so every load is issued
+    // unconditionally (the clamped ones are repeats, never used).
+    const float4 *lf = Lf + (int64_t)(4 * wave) * nchunk * 64 + lane;
+    const int last = 2 * nchunk - 1;
+    auto frag = [&](int st, int i) {
+        st = min(st, last);
+        const int pr = st >= nchunk ? 1 : 0;
+        return lf[((int64_t)(2 * pr + i) * nchunk + st - pr * nchunk) * 64];
+    };
+    float4 a0[2], a1[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a0[i] = frag(0, i);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a1[i] = frag(1, i);
 #pragma unroll 1
     for (int pr = 0; pr < 2; ++pr) {
         float4 sv[2][4];
@@ -178,37 +202,37 @@ __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__
 #pragma unroll
             for (int gg = 0; gg < 4; ++gg) {
                 const int c = 128 * wave + 32 * (2 * pr + i) + 8 * gg + 4 * h;
-                sv[i][gg] = keep ? *(const float4 *)(sn + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+                sv[i][gg] = *(const float4 *)(sn + c);   // every leaf's row exists; unwanted ones are not used
             }
         floatx16 ac[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int v = 0; v < 16; ++v) ac[i][v] = 0.f;
-        const float4 *lf = Lf + (int64_t)(4 * wave + 2 * pr) * nchunk * 64 + lane;
-        float4 a[2], an[2];
+        for (int c = 0; c < nchunk; c += 2) {   // nchunk is even: chunk c in a0, c + 1 in a1
+            const int st = pr * nchunk + c;
+            const float4 b0 = bc[2 * c];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = lf[(int64_t)i * nchunk * 64];
-        for (int c = 0; c < nchunk; ++c) {
-            if (c + 1 < nchunk) {
+            for (int i = 0; i < 2; ++i) ac[i] = mfma4(a0[i], b0, ac[i]);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) an[i] = lf[((int64_t)i * nchunk + c + 1) * 64];
-            }
-            const float4 b = bc[2 * c];
+            for (int i = 0; i < 2; ++i) a0[i] = frag(st + 2, i);
+            const float4 b1 = bc[2 * c + 2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) ac[i] = mfma4(a[i], b, ac[i]);
+            for (int i = 0; i < 2; ++i) ac[i] = mfma4(a1[i], b1, ac[i]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = an[i];
+            for (int i = 0; i < 2; ++i) a1[i] = frag(st + 3, i);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int gg = 0; gg < 4; ++gg) {
                 const int c = 128 * wave + 32 * (2 * pr + i) + 8 * gg + 4 * h;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (keep)
-                    v = make_float4((ac[i][4 * gg] + sv[i][gg].x) * scale, (ac[i][4 * gg + 1] + sv[i][gg].y) * scale,
-                                    (ac[i][4 * gg + 2] + sv[i][gg].z) * scale, (ac[i][4 * gg + 3] + sv[i][gg].w) * scale);
+                // a select, not a branch: unwanted leaves are written as zeros whatever their
+                // (unwritten) near-field rows hold
+                const float4 v = make_float4(keep ? (ac[i][4 * gg] + sv[i][gg].x) * scale : 0.f,
+                                             keep ? (ac[i][4 * gg + 1] + sv[i][gg].y) * scale : 0.f,
+                                             keep ? (ac[i][4 * gg + 2] + sv[i][gg].z) * scale : 0.f,
+                                             keep ? (ac[i][4 * gg + 3] + sv[i][gg].w) * scale : 0.f);
                 *(float4 *)(base + ((int64_t)(c >> 6) * n + ((c >> 3) & 7)) * n + (c & 7)) = v;
             }
     }
@@ -217,15 +241,20 @@ __global__ __launch_bounds__(256, 2) void l2p_permute_out_kernel(const float *__
 }  // namespace
 
 // Operator fragments for the fused kernels: rows x cols (row-major, leading dimension
-// lda) into ceil(rows / 32) tiles of ceil(cols / 8) chunks.
-int launch_pack_fragments(const float *A, int rows, int cols, int lda, float4 *frag, hipStream_t st) {
-    const int ntile = (rows + 31) / 32, nchunk = (cols + 7) / 8;
+// lda) into ceil(rows / 32) tiles of nchunk >= ceil(cols / 8) chunks (the chunks past the
+// operator's columns zero).
+int launch_pack_fragments(const float *A, int rows, int cols, int lda, int nchunk, float4 *frag, hipStream_t st) {
+    if (nchunk * 8 < cols) return fail(KIFMM_EINVAL, "operator fragments: too few chunks");
+    const int ntile = (rows + 31) / 32;
     const int64_t total = (int64_t)ntile * nchunk * 64;
     hipLaunchKernelGGL(pack_fragments_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, rows, cols,
                        lda, ntile, nchunk, frag);
     KIFMM_HIP(hipGetLastError());
     return KIFMM_OK;
 }
+
+// chunks of the L2P fragments (the fused L2P reads an even number)
+int l2p_fragment_chunks(int KD) { return l2p_chunks(KD); }
 
 // The fused kernels apply to FP32 evaluations on leaves of 8^3 cells with at least 4 leaves
 // per axis (n % 32 == 0), 16-byte aligned fields, KU % 32 == 0 and KD % 8 == 0, KD <= 256.
