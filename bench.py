@@ -300,7 +300,7 @@ def main():
                          "without overlap; the headline value is then the serial step)")
     ap.add_argument("--launch", default="graph", choices=["graph", "eager"],
                     help="how the timed evaluations are issued: replays of one evaluation captured in a "
-                         "HIP graph (the launches of all three streams recorded once), or one kifmm_eval "
+                         "HIP graph (the launches of all four streams recorded once), or one kifmm_eval "
                          "call per step")
     ap.add_argument("--variants", default="fp32/eager,bf16x3,bf16x3/eager,m2l_fp16,m2l_bf16,fp16,bf16,bf16x3/near_dense,fp32/near_dense,fp32/dense/near_dense",
                     help="extra precisions timed after the headline one ('' for none); "

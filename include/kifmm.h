@@ -244,7 +244,8 @@ int kifmm_ops_m2l_fft(kifmm_ops ops, int32_t enable);
  * convolution, so with enable != 0 the near field of every single-precision evaluation
  * runs as: half spectra (15 x 15 x 8) of every leaf's sources zero-padded to 15^3,
  * 27 complex products per frequency against the kernel spectra of the 27 neighbour
- * offsets (built in FP64 with the operators), and the inverse transform at the 8^3 cells.
+ * offsets (built in FP64 with the operators; the frequencies that are conjugates of others
+ * are neither stored nor multiplied), and the inverse transform at the 8^3 cells.
  * Same sum as the dense near field up to FP32 rounding (about 1e-7 of the result).  The
  * first enable allocates spectra buffers of 22.5 KiB per leaf (owned by ops).  Returns
  * 0, KIFMM_EINVAL (ops NULL), KIFMM_EUNSUPPORTED (leaves other than 8^3, or fewer than 4

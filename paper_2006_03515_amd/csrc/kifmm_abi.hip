@@ -226,7 +226,8 @@ struct kifmm_ops_s {
     // near field in Fourier space (kifmm_ops_p2p_fft; leaves of 8^3): half spectra of the
     // kernel of the 27 neighbour offsets [27][1920] complex, per-leaf spectra of the sources
     // [nleaf][1920] complex, and the sums after the first inverse stage [nleaf][120][8]
-    // complex (allocated when first enabled)
+    // complex (allocated when first enabled; the kernels write and read the 113 stored
+    // columns of the 120, the others being conjugates)
     bool p2p_fft = false;
     float *near_gh = nullptr, *near_q = nullptr, *near_p = nullptr;
     float *spec_e = nullptr, *spec_p = nullptr;
