@@ -45,11 +45,12 @@ def _field(seed):
 
 
 def make_fields(seeds, workers=8):
-    # a process that has initialised the GPU runtime must not fork: draw in-process then
-    import torch
-    if workers <= 1 or torch.cuda.is_initialized():
+    # the workers are spawned, never forked: the calling process may already have initialised
+    # the GPU runtime (through torch or through the library's own HIP calls), and a forked
+    # copy of it is unusable
+    if workers <= 1:
         return np.stack([_field(s) for s in seeds])
-    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("fork")) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
         return np.stack(list(ex.map(_field, seeds, chunksize=16)))
 
 
