@@ -23,8 +23,9 @@
 //                        spectrum (z, y, x stages; inverse x, y, z).
 //   m2l_pair_mfma_kernel one workgroup per aligned 4^3 block of parents (512 target boxes) and
 //                        4 frequencies; the spectra of the block's source region (6^3
-//                        parents x 8 children) are staged in LDS, [frequency][child][re/im]
-//                        [parent] so that 16 lanes reading 16 parents hit distinct banks.
+//                        parents x 8 children) are staged in LDS, [frequency][parent][k slot]
+//                        [k-step], so that one 16-byte read gives a lane the four k-steps of
+//                        one source parent that its four MFMAs take in turn.
 //                        Wave w takes frequency w: 4 column blocks of 16 parents on
 //                        v_mfma_f32_16x16x4f32, operator fragments read from a table laid out
 //                        per frequency as [27 parents][64 lanes][4 k-steps].  Levels with at least 4
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
                                                             int nl, int nfp, const uint8_t *__restrict__ out_need,
                                                             const uint8_t *__restrict__ in_nz,
                                                             float2 *__restrict__ P) {
-    __shared__ float Es[PF * 16 * 216];   // [f][c_s][re/im][region parent], reused for the output
+    __shared__ __align__(16) float Es[PF * 16 * 216];   // [f][region parent][k slot][k-step], reused for the output
     __shared__ int any_wanted;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int np = nl / 2;
@@ -180,18 +181,21 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
             }
         }
     }
+    // LDS layout [f][region parent][k slot g][k-step s]: row 2 c_s + re/im = 4 s + g of the
+    // operator, so a lane's four k-steps of one source parent are one 16-byte read
 #pragma unroll
     for (int i = 0; i < NST; ++i) {
         const int e = tid + 256 * i, q = e >> 3, c = e & 7;
         if (e < 216 * 8) {
-            Es[((0 * 8 + c) * 2 + 0) * 216 + q] = v[i][0].x;
-            Es[((0 * 8 + c) * 2 + 1) * 216 + q] = v[i][0].y;
-            Es[((1 * 8 + c) * 2 + 0) * 216 + q] = v[i][0].z;
-            Es[((1 * 8 + c) * 2 + 1) * 216 + q] = v[i][0].w;
-            Es[((2 * 8 + c) * 2 + 0) * 216 + q] = v[i][1].x;
-            Es[((2 * 8 + c) * 2 + 1) * 216 + q] = v[i][1].y;
-            Es[((3 * 8 + c) * 2 + 0) * 216 + q] = v[i][1].z;
-            Es[((3 * 8 + c) * 2 + 1) * 216 + q] = v[i][1].w;
+            const int gs = 4 * (2 * (c & 1)) + (c >> 1);   // (g, s) of re; im is g + 1
+            Es[((0 * 216 + q) * 4) * 4 + gs] = v[i][0].x;
+            Es[((0 * 216 + q) * 4) * 4 + gs + 4] = v[i][0].y;
+            Es[((1 * 216 + q) * 4) * 4 + gs] = v[i][0].z;
+            Es[((1 * 216 + q) * 4) * 4 + gs + 4] = v[i][0].w;
+            Es[((2 * 216 + q) * 4) * 4 + gs] = v[i][1].x;
+            Es[((2 * 216 + q) * 4) * 4 + gs + 4] = v[i][1].y;
+            Es[((3 * 216 + q) * 4) * 4 + gs] = v[i][1].z;
+            Es[((3 * 216 + q) * 4) * 4 + gs + 4] = v[i][1].w;
         }
     }
     __syncthreads();
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     floatx4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float *Ew = Es + w * 16 * 216 + g * 216;
+    const floatx4 *Ew = (const floatx4 *)Es + w * 216 * 4 + g;   // [q][g]: the 4 k-steps
 #pragma unroll
     for (int d = 0; d < 27; ++d) {   // source parent p + (dx, dy, dz), d = 9 (dx+1) + 3 (dy+1) + dz+1
         if (d == 13) continue;   // the target's own parent: all its children are adjacent (zeros)
@@ -215,11 +219,13 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
         const float4 ad = a[d - (d > 13)];   // k-steps 4 d .. 4 d + 3
         const float a4[4] = {ad.x, ad.y, ad.z, ad.w};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {   // k-step 4 d + s: c_s = 2 s + g / 2, re/im = g % 2
-            const float *eb = Ew + s * 4 * 216 + dq;
+        for (int nb = 0; nb < 4; ++nb) {
+            // k-step 4 d + s: c_s = 2 s + g / 2, re/im = g % 2 (the same order of products
+            // into each column block's sums as one k-step after the other)
+            const floatx4 b = Ew[(qn[nb] + dq) * 4];
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[s], eb[qn[nb]], acc[nb], 0, 0, 0);
+            for (int s = 0; s < 4; ++s)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[s], b[s], acc[nb], 0, 0, 0);
         }
     }
     __syncthreads();
