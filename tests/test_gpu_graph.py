@@ -24,7 +24,10 @@ def K():
                                                      (64, "fp32", False, False),
                                                      # depth 4: the coarse levels' M2L on the near
                                                      # field's stream, gated by per-level events
-                                                     (128, "fp32", True, True), (128, "bf16x3", True, True)])
+                                                     (128, "fp32", True, True), (128, "bf16x3", True, True),
+                                                     # depth 5: the benchmark's schedule, levels 3
+                                                     # and 4 each on a stream of its own
+                                                     (256, "fp32", True, True), (256, "bf16x3", True, True)])
 def test_graph_replay_is_the_eager_evaluation(K, n, prec, m2l_fft, near_fft):
     L, p_o2 = 0.1 * n / 64, 150.0
     I = np.random.default_rng(71).random((n, n, n)).astype(np.float32)
@@ -65,14 +68,19 @@ def test_graph_replay_is_the_eager_evaluation(K, n, prec, m2l_fft, near_fft):
     del g
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
-def test_serial_schedule_is_the_concurrent_evaluation(K, prec):
+@pytest.mark.parametrize("n,prec,m2l_fft", [(128, "fp32", False), (128, "bf16x3", False), (128, "fp64", False),
+                                            # depth 5 with both Fourier forms: the schedule of the
+                                            # benchmark (the finest level, level 3 and level 4 on
+                                            # streams of their own)
+                                            (256, "fp32", True), (256, "bf16x3", True)])
+def test_serial_schedule_is_the_concurrent_evaluation(K, n, prec, m2l_fft):
     # every pass on the calling stream in order (the measurement schedule) runs the same
     # kernels on the same data: the same field bit for bit
-    n, L, p_o2 = 128, 0.2, 150.0
+    L, p_o2 = 0.2 * n / 128, 150.0
     I = np.random.default_rng(72).random((n, n, n))
     tree = K.build_tree(K.Grid.cube(n, L), 512)
     ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5, 1.0))
+    ops.m2l_fft(m2l_fft)
     ops.p2p_fft(prec != "fp64")
     It = torch.from_numpy(I.ravel()).cuda()
     It = It if prec == "fp64" else It.float()
