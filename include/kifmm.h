@@ -115,9 +115,11 @@ typedef struct {
  *                     of two bfloat16 numbers (high part + rounding residual)
  *                     and three bfloat16 products are accumulated in FP32
  *                     (about 16 significant bits per operand).
- *   KIFMM_BF16X3    : the near field (P2P) and M2L both in split bfloat16; the
- *                     near-range matrices, self cell included, are computed in
- *                     FP64 and then split.  Other passes FP32.
+ *   KIFMM_BF16X3    : the near field (P2P), M2L and, on leaves of 8^3 cells,
+ *                     P2M and L2P (fused with the permutes) in split bfloat16;
+ *                     the near-range matrices, self cell included, and the
+ *                     leaf operators are computed in FP64 and then split.
+ *                     Other passes FP32.
  *   KIFMM_BF16      : every translation GEMM (P2M, M2M, M2L, L2L, L2P) with
  *                     bfloat16 operands, FP32 accumulation: operators stored
  *                     divided by their maxima, inputs divided by theirs; the

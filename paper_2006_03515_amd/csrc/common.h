@@ -29,6 +29,20 @@ int hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+// ------------------------------------------------------------ split BF16 ----
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 value -> BF16 high part (round to nearest even) and the BF16 of what remains: hi + lo
+// holds about 16 of the value's 24 mantissa bits (finite values)
+__device__ __forceinline__ void split_bf16(float v, uint16_t &hi, uint16_t &lo) {
+    uint32_t u = __float_as_uint(v);
+    const uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    hi = (uint16_t)(h >> 16);
+    const float r = v - __uint_as_float(h);
+    const uint32_t ur = __float_as_uint(r);
+    lo = (uint16_t)((ur + 0x7fffu + ((ur >> 16) & 1u)) >> 16);
+}
+
 // ------------------------------------------------------------ Morton keys ---
 // 3D Morton key of box coordinates, bits interleaved ... x1 y1 z1 x0 y0 z0
 // (x most significant of each triple).  10 bits per axis.

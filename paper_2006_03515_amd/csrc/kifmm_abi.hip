@@ -66,6 +66,11 @@ bool leafgemm_fits(const Tree &, int, int);
 int run_p2m_permute_in(const Tree &, const float *, float, const float4 *, int, float *, float *, hipStream_t);
 int run_l2p_permute_out(const Tree &, const float *, int, const float4 *, const float *, float, const uint8_t *, float *,
                         hipStream_t);
+int launch_pack_fragments_x3(const double *, int, int, int, int, uint4 *, hipStream_t);
+int l2p_fragment_chunks_x3(int KD);
+int run_p2m_permute_in_x3(const Tree &, const float *, float, const uint4 *, int, float *, float *, hipStream_t);
+int run_l2p_permute_out_x3(const Tree &, const float *, int, const uint4 *, const float *, float, const uint8_t *,
+                           float *, hipStream_t);
 
 static std::atomic<uint64_t> g_magic{0x6b69666d6d000001ull};
 
@@ -250,6 +255,9 @@ struct kifmm_ops_s {
     // P2M and L2P as MFMA fragments for the kernels fused with the permutes (FP32, leaves of
     // 8^3 cells): [KU / 32 tiles][64 chunks][64 lanes] and [16 tiles][KD / 8 chunks][64 lanes]
     float4 *p2m_frag = nullptr, *l2p_frag = nullptr;
+    // the same in split BF16 (KIFMM_BF16X3): [KU / 32 tiles][32 chunks][hi, lo][64 lanes] and
+    // [16 tiles][KD / 16 chunks, even][hi, lo][64 lanes] of 8 BF16 values
+    uint4 *p2m_xf = nullptr, *l2p_xf = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, fork_fine = nullptr, join_fine = nullptr, join_coarse = nullptr;
     // per coarse level l (3 .. D - 1): c_u^l is ready (ev_up), its M2L is done (ev_m2l)
     std::vector<hipEvent_t> ev_up, ev_m2l;
@@ -343,7 +351,7 @@ static void free_ops(kifmm_ops o) {
                     o->p2mbf, o->m2mbf, o->l2lbf, o->l2pbf, o->p2mh, o->m2mh, o->l2lh, o->l2ph,
                     o->m2lh,  o->taps,  o->q,     o->Sp,    o->SpN,   o->amax,  o->part,
                     o->p2pbf, o->p2pbf_lo, o->amax_q, o->split_q, o->split_c, o->spec_e, o->spec_p,
-                    o->p2m_frag, o->l2p_frag, o->m2l0_32, o->m2l0_64, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
+                    o->p2m_frag, o->l2p_frag, o->p2m_xf, o->l2p_xf, o->m2l0_32, o->m2l0_64, o->lat_buf, o->lat_buf_c, o->spec_e_c, o->spec_p_c, o->near_gh, o->near_q, o->near_p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *p : o->cu)
@@ -1222,6 +1230,11 @@ int build_ops(kifmm_tree tree, kifmm_ops o, hipStream_t st) {
         KIFMM_TRY(dmalloc(&o->l2p_frag, (size_t)(s / 32) * l2p_chunks * 64));
         KIFMM_TRY(launch_pack_fragments(o->p2m32, KU, s, s, s / 8, o->p2m_frag, st));
         KIFMM_TRY(launch_pack_fragments(o->l2p32, s, KD, KD, l2p_chunks, o->l2p_frag, st));
+        const int l2p_chunks_x3 = l2p_fragment_chunks_x3(KD);   // KD / 16 rounded up to even
+        KIFMM_TRY(dmalloc(&o->p2m_xf, (size_t)(KU / 32) * (s / 16) * 128));
+        KIFMM_TRY(dmalloc(&o->l2p_xf, (size_t)(s / 32) * l2p_chunks_x3 * 128));
+        KIFMM_TRY(launch_pack_fragments_x3(o->p2m64, KU, s, s, s / 16, o->p2m_xf, st));
+        KIFMM_TRY(launch_pack_fragments_x3(o->l2p64, s, KD, KD, l2p_chunks_x3, o->l2p_xf, st));
     }
     // child centre offsets at a level of half-widths (r, r, rz): (2c - 1) r per axis
     auto child_shifts = [&](double r, double rz) {
@@ -1713,8 +1726,12 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
     }
     if (fused_in) {
         PassTimer pt(o, KIFMM_PASS_P2M, st);
-        KIFMM_TRY(run_p2m_permute_in(*t, (const float *)I, (float)vol, o->p2m_frag, KU, near_grid ? nullptr : (float *)q,
-                                     (float *)o->cu[D], st));
+        if (precision == KIFMM_BF16X3)
+            KIFMM_TRY(run_p2m_permute_in_x3(*t, (const float *)I, (float)vol, o->p2m_xf, KU,
+                                            near_grid ? nullptr : (float *)q, (float *)o->cu[D], st));
+        else
+            KIFMM_TRY(run_p2m_permute_in(*t, (const float *)I, (float)vol, o->p2m_frag, KU,
+                                         near_grid ? nullptr : (float *)q, (float *)o->cu[D], st));
     } else {
         PassTimer pt(o, KIFMM_PASS_PERMUTE_IN, st);
         KIFMM_TRY(launch_permute_in<T>(*t, I, vol, q, st));
@@ -1867,6 +1884,9 @@ int eval_typed(kifmm_tree t, kifmm_ops o, const T *I, T *S, double prefactor, in
         KIFMM_HIP(hipStreamWaitEvent(st, o->join, 0));
         fj.side_forked = fj.fine_forked = false;
         PassTimer pt(o, KIFMM_PASS_L2P, st);
+        if (precision == KIFMM_BF16X3)
+            return run_l2p_permute_out_x3(*t, (const float *)o->cd[D], KD, o->l2p_xf, (const float *)SpN,
+                                          (float)scale, want_of(o, D), (float *)S, st);
         return run_l2p_permute_out(*t, (const float *)o->cd[D], KD, o->l2p_frag, (const float *)SpN, (float)scale,
                                    want_of(o, D), (float *)S, st);
     }

@@ -247,18 +247,6 @@ __global__ __launch_bounds__(256) void m2l_pair_mfma_kernel(const float2 *__rest
     }
 }
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// FP32 value -> BF16 high part (round to nearest even) and the BF16 of what remains
-__device__ __forceinline__ void split_bf16(float v, uint16_t &hi, uint16_t &lo) {
-    uint32_t u = __float_as_uint(v);
-    const uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-    hi = (uint16_t)(h >> 16);
-    const float r = v - __uint_as_float(h);
-    const uint32_t ur = __float_as_uint(r);
-    lo = (uint16_t)((ur + 0x7fffu + ((ur >> 16) & 1u)) >> 16);
-}
-
 // The parent-pair products in split BF16 (A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32
 // accumulation, about 16 mantissa bits) on v_mfma_f32_16x16x32_bf16: the same workgroup
 // shape as m2l_pair_mfma_kernel, spectra staged as BF16 pairs [f][region parent][c_s][re/im]

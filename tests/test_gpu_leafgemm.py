@@ -1,6 +1,7 @@
 """P2M fused with the way into leaf order and L2P fused with the sum and the way out (FP32,
-leaves of 8^3 cells) against the same evaluation through the separate permutes and tap
-GEMMs, which the library takes when the fields are not 16-byte aligned."""
+and split BF16 under KIFMM_BF16X3; leaves of 8^3 cells) against the same evaluation through
+the separate permutes and tap GEMMs, which the library takes when the fields are not 16-byte
+aligned."""
 import numpy as np
 import pytest
 import torch
@@ -73,3 +74,36 @@ def test_fused_way_out_honours_target_restriction(K):
     cells = torch.from_numpy(np.kron(m, np.ones((8, 8, 8), dtype=np.uint8)) != 0).cuda()
     assert torch.equal(b[cells], a[cells])
     assert int(torch.count_nonzero(b[~cells])) == 0
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_split_bf16_leaf_passes(K, n, record_property):
+    # KIFMM_BF16X3 runs the fused P2M and L2P in split BF16: each operand is its BF16 high part
+    # plus the BF16 of the remainder (about 16 mantissa bits), and the dropped product of the
+    # two remainders is below 2^-16 of each term.  Through the separate passes (fields not
+    # 16-byte aligned) the same precision takes FP32 tap GEMMs for them, and KIFMM_M2L_BF16X3
+    # takes the FP32 fused kernels: with the near field in Fourier space (FP32) in all three,
+    # the fused split-BF16 field differs from the other two by the leaf passes' rounding only.
+    L, p_o2 = 0.1 * n / 64, 150.0
+    rng = np.random.default_rng(90 + n)
+    I = (rng.random((n, n, n)) * np.exp(-8 * rng.random((n, n, n)))).astype(np.float32)
+    tree = K.build_tree(K.Grid.cube(n, L), 512)
+    ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5))
+    ops.m2l_fft(True)
+    ops.p2p_fft(True)
+    It = torch.from_numpy(I.ravel()).cuda()
+    fused = K.eval(tree, ops, It, 0.7, precision="bf16x3")
+    sep = K.eval(tree, ops, _offset_view(It), 0.7, out=_offset_view(torch.zeros_like(It)), precision="bf16x3")
+    m2l_only = K.eval(tree, ops, It, 0.7, precision="m2l_bf16x3")
+    fp32 = K.eval(tree, ops, It, 0.7)
+    torch.cuda.synchronize()
+    a = fused.double().cpu().numpy()
+    e_sep, e_m2l = rel_l2(a, sep.double().cpu().numpy()), rel_l2(a, m2l_only.double().cpu().numpy())
+    e_fp32 = rel_l2(a, fp32.double().cpu().numpy())
+    record_property("rel_l2", {"vs_separate": e_sep, "vs_m2l_bf16x3": e_m2l, "vs_fp32": e_fp32})
+    print("%d^3 split-BF16 leaf passes: vs FP32 leaf passes %.2e (separate) %.2e (fused), vs FP32 %.2e"
+          % (n, e_sep, e_m2l, e_fp32))
+    assert 0 < e_sep < 2e-6 and 0 < e_m2l < 2e-6
+    assert e_fp32 < 2e-6
+    exact = odirect.fft_full(I.astype(np.float64), (L / n,) * 3, p_o2, prefactor=0.7).ravel()
+    assert rel_l2(a, exact) < 1e-4
