@@ -25,9 +25,12 @@
 //                         the 113 stored columns.
 //   near_products_kernel  one workgroup per aligned 4^3 block of target leaves and the 16
 //                         frequencies of one (ky, kz): the spectra of the 6^3 leaves around
-//                         the block and the 27 kernel spectra are staged in LDS; lane = 16
-//                         frequencies x 16 columns of 4 targets along z (the 12 taps of a
-//                         column at one (ox, oy) read 6 source spectra).
+//                         the block and 14 of the 27 kernel spectra are staged in LDS (the
+//                         kernel is even and real, so the spectrum of offset -o is the
+//                         conjugate of that of o: a column (ox, oy) and its mirror share
+//                         their three kernel values); lane = 16 frequencies x 16 columns of
+//                         4 targets along z (the 12 taps of a column at one (ox, oy) read 6
+//                         source spectra).
 //                         A workgroup takes 8 or 7 chunks of 16 frequencies (15 per
 //                         block: 8 x 8 + 7 x 7 = 113 columns) in turn, the next
 //                         chunk's spectra in flight (registers) while one is multiplied;
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__r
     // Es: [region leaf][kx]; after the products of a chunk it holds their sums,
     // [target][kx] (padded rows of 17, 64 x 17)
     __shared__ float2 Es[216 * 16];
-    __shared__ float2 Gs[27 * 16];    // [offset][kx]
+    __shared__ float2 Gs[14 * 16];    // [offset][kx], offsets 0 .. 13 (26 - t is the conjugate of t)
     const int tid = threadIdx.x, lane = tid & 63;
     // Workgroups go to the 8 XCDs in turn; each XCD takes one contiguous eighth of the
     // (frequency chunks, block) pairs, blocks fastest, so the neighbouring blocks that share
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__r
             }
         }
     }
-    const float4 *gsrc = tid < 27 * 8 ? (const float4 *)(Gh + (int64_t)(tid >> 3) * NF) + (tid & 7) : nullptr;
+    const float4 *gsrc = tid < 14 * 8 ? (const float4 *)(Gh + (int64_t)(tid >> 3) * NF) + (tid & 7) : nullptr;
     float4 pre[7], gpre;
     auto fetch = [&](int c) {   // chunk c: frequencies 16 c .. 16 c + 15 (8 float4 per leaf)
 #pragma unroll
@@ -265,22 +268,40 @@ __global__ __launch_bounds__(256, 5) void near_products_kernel(const float2 *__r
         __syncthreads();
         if (j + 1 < j1) fetch(kept_column(j + 1));   // in flight while this chunk is multiplied
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int oxy = 0; oxy < 9; ++oxy) {   // (ox, oy); oz and the 4 targets share 6 sources
+        // (ox, oy) = column c of 9 and its mirror 8 - c: the kernel is even and real, so the
+        // spectrum of offset -o is the conjugate of that of o (offset index 26 - t for t);
+        // oz and the 4 targets share 6 sources per column
+        auto column = [&](int oxy, const float2 (&g)[3], float sgn) {   // sgn -1: conjugates
             const int base = col + ((oxy / 3 - 1) * 36 + (oxy % 3 - 1) * 6) * 16;
-            float2 e[6], g[3];
+            float2 e[6];
 #pragma unroll
             for (int z = 0; z < 6; ++z) e[z] = Es[base + z * 16];
-#pragma unroll
-            for (int oz = 0; oz < 3; ++oz) g[oz] = Gs[(oxy * 3 + oz) * 16 + f];
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int oz = 0; oz < 3; ++oz) {   // source z = s + oz - 1, region z = s + oz
                     const float2 v = e[s + oz];
-                    ar[s] = fmaf(g[oz].x, v.x, fmaf(-g[oz].y, v.y, ar[s]));
-                    ai[s] = fmaf(g[oz].x, v.y, fmaf(g[oz].y, v.x, ai[s]));
+                    const float gy = sgn * g[oz].y;
+                    ar[s] = fmaf(g[oz].x, v.x, fmaf(-gy, v.y, ar[s]));
+                    ai[s] = fmaf(g[oz].x, v.y, fmaf(gy, v.x, ai[s]));
                 }
+        };
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float2 g[3], gm[3];
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) g[oz] = Gs[(c * 3 + oz) * 16 + f];
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) gm[oz] = g[2 - oz];
+            column(c, g, 1.f);
+            column(8 - c, gm, -1.f);
+        }
+        {   // the centre column: oz = +1 is the conjugate of oz = -1, oz = 0 the self offset
+            float2 g[3];
+            g[0] = Gs[12 * 16 + f];
+            g[1] = Gs[13 * 16 + f];
+            g[2] = make_float2(g[0].x, -g[0].y);
+            column(4, g, 1.f);
         }
         __syncthreads();   // every wave is done with Es before Ps overwrites it
 #pragma unroll
