@@ -56,20 +56,21 @@ def test_fused_leaf_passes_equal_the_separate_passes(K, n, layout, near_fft):
     assert rel_l2(a, exact) < 1e-4
 
 
-def test_fused_way_out_honours_target_restriction(K):
-    # unwanted leaves are written as zeros by the fused way out too; wanted ones keep the
-    # unrestricted values bit for bit
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_fused_way_out_honours_target_restriction(K, precision):
+    # unwanted leaves are written as zeros by the fused way out too (FP32 and split-BF16
+    # kernels); wanted ones keep the unrestricted values bit for bit
     n, L, p_o2 = 64, 0.1, 150.0
     I = np.random.default_rng(85).random((n, n, n)).astype(np.float32)
     tree = K.build_tree(K.Grid.cube(n, L), 512)
     ops = K.precompute_operators(tree, K.Kernel(p_o2), K.Opts(K.LAYOUT_LATTICE, 5, 10, 1e-5))
     ops.p2p_fft(True)
     It = torch.from_numpy(I.ravel()).cuda()
-    a = K.eval(tree, ops, It, 1.0).reshape(n, n, n)
+    a = K.eval(tree, ops, It, 1.0, precision=precision).reshape(n, n, n)
     nb = n // 8
     m = (np.random.default_rng(86).random((nb, nb, nb)) < 0.3).astype(np.uint8)
     ops.restrict_targets(m)
-    b = K.eval(tree, ops, It, 1.0).reshape(n, n, n)
+    b = K.eval(tree, ops, It, 1.0, precision=precision).reshape(n, n, n)
     ops.restrict_targets(None)
     cells = torch.from_numpy(np.kron(m, np.ones((8, 8, 8), dtype=np.uint8)) != 0).cuda()
     assert torch.equal(b[cells], a[cells])
